@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the state-vector hot path on one MI355X.
+
+Step (timed K times after W warm-ups): one pass of every single-GPU step of
+the path over a seeded random 30-qubit complex64 state (8 GiB, resident in
+HBM):
+  * a Haar U(2) on every target qubit 0..29 (eq. (1), k = 1);
+  * controlled gates CNOT(0->29), CZ(3,17), CRZ(29->0);
+  * dense Haar U(4) / U(8) on low, mixed and high target sets;
+  * permutation and diagonal gates X(29), SWAP(0,29), Z(5), a phase on 12;
+  * fused dense 4- and 5-qubit blocks (matrix cores) on low, high and mixed
+    targets;
+  * the open-chain transverse-field Ising energy (31 read passes) and the norm.
+value = algorithmic bytes of the step (each touched amplitude read and
+written once; read-only passes counted once) / measured time.
+
+Side measurements (reported, not part of `value`): per-target GB/s of the
+single-qubit sweep for complex64 and complex128, the adjoint gradient of the
+hardware-efficient ansatz (n = 20, 8 layers) in gradients/s against plain
+parameter shift on the same GPU, the roofline of the dominant kernel timed
+with HIP events, and the CPU oracle on a bounded sample (cpu_baseline).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "amplitude GB/s vs HBM peak at 30q; adjoint grads/s vs parameter-shift"
+HBM_PEAK_GBS = 8000.0
+
+
+def step_ops(n, rng, W):
+    ops = [W.Op("matrix", (t,), matrix=W.haar_unitary(rng, 2)) for t in range(n)]
+    ops += [W.Op("x", (n - 1,), controls=(0,)), W.Op("z", (17,), controls=(3,)),
+            W.Op("rz", (0,), controls=(n - 1,), param=0)]
+    for t in [(0, 1), (1, n - 1), (n - 2, n - 1), (0, 1, 2), (2, n // 2, n - 1),
+              (n - 3, n - 2, n - 1)]:
+        ops.append(W.Op("matrix", t, matrix=W.haar_unitary(rng, 2 ** len(t))))
+    ops += [W.Op("x", (n - 1,)), W.Op("swap", (0, n - 1)), W.Op("z", (5,)),
+            W.Op("matrix", (12,), matrix=__import__("numpy").diag([1, 1j]).astype(complex))]
+    for t in [(0, 1, 2, 3), (n - 4, n - 3, n - 2, n - 1), (0, 1, 2, 3, 4),
+              (n - 5, n - 4, n - 3, n - 2, n - 1), (0, 9, 15, 22, n - 1)]:
+        ops.append(W.Op("matrix", t, matrix=W.haar_unitary(rng, 2 ** len(t))))
+    return W.Circuit(n, ops, 1)
+
+
+def event_time(fn, reps, stream):
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / 1e3 / reps
+
+
+def cpu_baseline():
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    n = 26
+    rng = np.random.default_rng(1000)
+    psi = oracle.random_state(n, 7)
+    t0 = time.perf_counter()
+    nbytes = 0.0
+    for t in [0, 13, 25]:
+        psi = oracle.apply(psi, (t,), (), W.haar_unitary(rng, 2))
+        nbytes += 2.0 * 16 * (1 << n)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": "oracle eq.(1) complex128 out of place, Haar U(2) at targets 0, 13, 25 of a "
+                      "26-qubit random state (1 GiB); %.1f s" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--skip-side", action="store_true", help="only the timed step")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the path runs on a single MI355X and this build has no "
+              "multi-GPU mode (requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_07017_amd import qsv
+
+    n = args.n
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(1002)
+    circ = step_ops(n, rng, W)
+    plan = qsv.Plan(circ, qsv.C64, 1, params_host=np.array([1.234]))
+    nl, plan_bytes, plan_flops = plan.info()
+    H = qsv.PauliSum(W.tfim_chain(n))
+    S = 8
+    step_bytes = plan_bytes + (1 + n) * S * (1 << n) + S * (1 << n)
+    psi = torch.empty(1 << n, dtype=torch.complex64, device=dev)
+    qsv.qsv_init_random(psi, 1002)
+    e_out = torch.empty(2, dtype=torch.float64, device=dev)
+    n_out = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def step():
+        plan.run(psi)
+        qsv.qsv_expectation(psi, H, e_out)
+        qsv.qsv_norm2(psi, n_out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = elapsed / args.steps * 1e3
+    value = step_bytes * args.steps / elapsed / 1e9
+    norm = float(n_out.cpu()[0])
+
+    # Dominant kernel: the single-qubit sweep (30 of the step's launches),
+    # timed with HIP events on the stream it is launched on.
+    G = W.haar_unitary(rng, 2)
+    reps = 20
+    sweep_bytes = 2.0 * S * (1 << n)
+    avg = event_time(lambda: qsv.qsv_apply_gate(psi, (15,), (), G), reps, stream)
+    roof = {"bound": "hbm", "achieved": round(sweep_bytes / avg / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(sweep_bytes / avg / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": None, "kernel": "k_dense<float,1,W2> (single-qubit sweep, target 15)",
+            "avg_launch_ms": round(avg * 1e3, 4)}
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded random state, Haar-random gates)",
+           "config": {"workload": "n=30 complex64 gate sweeps + TFIM energy + norm", "n": n,
+                      "state": "complex64", "launches_per_step": nl + 3 + n,
+                      "step_bytes": step_bytes, "hbm_frac": round(value / HBM_PEAK_GBS, 4),
+                      "norm_after": norm},
+           "roofline": roof}
+
+    if not args.skip_side:
+        per = {}
+        for name, dt in [("c64", torch.complex64), ("c128", torch.complex128)]:
+            del psi
+            torch.cuda.empty_cache()
+            psi = torch.empty(1 << n, dtype=dt, device=dev)
+            qsv.qsv_init_random(psi, 5)
+            Sb = 8 if name == "c64" else 16
+            row = []
+            for t in range(n):
+                a = event_time(lambda: qsv.qsv_apply_gate(psi, (t,), (), G), 5, stream)
+                row.append(round(2.0 * Sb * (1 << n) / a / 1e9, 1))
+            per[name] = row
+        out["per_target_gbs"] = per
+        del psi
+        torch.cuda.empty_cache()
+        out["adjoint"] = adjoint_leg(qsv, W, torch, np, dev)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def adjoint_leg(qsv, W, torch, np, dev):
+    n, L = 20, 8
+    circ, H = W.hea(n, L), W.tfim_chain(n)
+    p = torch.from_numpy(W.random_params(circ.nparams, 1003)).to(dev)
+    res = {"workload": "HEA n=20 L=8, TFIM", "nparams": circ.nparams}
+    for name, code in [("c64", qsv.C64), ("c128", qsv.C128)]:
+        plan = qsv.AdjointPlan(circ, H, code, 5, device=dev)
+        e, g = plan.run(p)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.run(p, e, g)
+        torch.cuda.synchronize()
+        ta = (time.perf_counter() - t0) / reps
+        res[name + "_grads_per_s"] = round(1.0 / ta, 2)
+        if name == "c64":
+            # plain parameter shift on the same GPU: 2P energies, same forward plan
+            pe = p.clone()
+            en = torch.empty(1, dtype=torch.float64, device=dev)
+            plan.energy(pe, en)
+            vals = torch.empty(2 * circ.nparams, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for j in range(circ.nparams):
+                for s, sign in enumerate((1.0, -1.0)):
+                    pe.copy_(p)
+                    pe[j] += sign * np.pi / 2
+                    plan.energy(pe, en)
+                    vals[2 * j + s].copy_(en[0])
+            torch.cuda.synchronize()
+            tps = time.perf_counter() - t0
+            gps = 0.5 * (vals[0::2] - vals[1::2])
+            res["param_shift_grads_per_s"] = round(1.0 / tps, 3)
+            res["adjoint_over_param_shift"] = round(tps / ta, 1)
+            res["max_abs_adjoint_minus_shift"] = float((gps - g).abs().max().cpu())
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,304 @@
+/*
+ * qsv.h -- C ABI of the MI355X (gfx950) state-vector library libqsv.so.
+ *
+ * The library applies quantum gates to a 2^n-amplitude state vector held in
+ * GPU memory, in place, following eq. (1) of Carrazza, Efthymiou, Lazzarin &
+ * Pasquale, "An open-source modular framework for quantum computing" (Sec. 2):
+ *
+ *     psi'(tau, q) = sum_{tau'} G(tau, tau') psi(tau', q)
+ *
+ * where tau is the bitstring of the n_tar target qubits and q the bitstring of
+ * the other n - n_tar qubits.  Around that core it provides controlled and
+ * multi-qubit gates (Sec. 2, index generation for controlled and multi-target
+ * gates), fused dense blocks of up to 5 qubits, expectation values of
+ * Pauli-sum Hamiltonians (Sec. 3, Hamiltonian primitives), adjoint-method
+ * gradients of parametrised rotation circuits (the gradient role Sec. 2
+ * gives to automatic differentiation, Sec. 3 variational layers / VQE), and
+ * a batched mode that evaluates many small circuits in one persistent launch.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - State layout: 2^n complex amplitudes, interleaved (re, im), amplitude i
+ *    at element i.  QSV_C64 = 2 x float (8 bytes), QSV_C128 = 2 x double
+ *    (16 bytes).  The pointer must be device memory, 16-byte aligned.
+ *  - Qubit j is bit j of the amplitude index (weight 2^j).
+ *  - Gate matrices are host arrays of complex128, row-major, interleaved:
+ *    G[(row * 2^k + col) * 2 + {0: re, 1: im}].  For targets t[0..k-1] the
+ *    FIRST listed target is the MOST significant bit of the row/column index
+ *    (numpy kron order).  For QSV_C64 states every component is rounded to
+ *    the nearest float before use.
+ *  - Controlled gates apply G only to amplitudes whose control bits are all 1.
+ *  - Every call validates all arguments on the host before it enqueues
+ *    anything.  On error nothing is enqueued, device memory is unchanged and
+ *    qsv_last_error() describes the problem.  Validation covers: 1 <= n <=
+ *    QSV_MAX_QUBITS, dtype, 1 <= k <= QSV_MAX_TARGETS, c >= 0, k + c <= n,
+ *    every qubit in [0, n), all targets and controls distinct, non-NULL
+ *    pointers, 16-byte alignment of state pointers.
+ *  - Device work is enqueued on `stream` (a hipStream_t passed as void*;
+ *    NULL = the null stream) and calls never synchronise the device unless
+ *    stated.  Results written to device memory are valid once the stream has
+ *    reached them.
+ *  - Ownership: every state, workspace and output buffer belongs to the
+ *    caller; the library never frees it.  Host arrays are read only during
+ *    the call.  Plans belong to the caller and are released with *_destroy.
+ *  - Calls on different streams may run concurrently as long as they do not
+ *    share buffers.  Library-internal caches are guarded by a mutex.
+ */
+#ifndef QSV_H
+#define QSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QSV_MAX_QUBITS 40
+#define QSV_MAX_TARGETS 5
+#define QSV_MAX_CONTROLS 4 /* per op inside a circuit; qsv_apply_gate takes any count */
+
+typedef enum { QSV_C64 = 1, QSV_C128 = 2 } qsv_dtype;
+
+typedef enum {
+    QSV_OK = 0,
+    QSV_ERR_ARG = 1,         /* bad pointer, size, dtype or count */
+    QSV_ERR_QUBIT = 2,       /* qubit index out of range or repeated */
+    QSV_ERR_UNSUPPORTED = 3, /* valid request the library does not implement */
+    QSV_ERR_HIP = 4,         /* HIP runtime or launch failure (message has the HIP string) */
+    QSV_ERR_NOMEM = 5        /* host or device allocation failed */
+} qsv_status;
+
+/* Description of the last error on the calling thread; valid until the next
+ * qsv_* call on that thread.  Never NULL. */
+const char* qsv_last_error(void);
+
+/* Library version string, e.g. "qsv 0.1 gfx950". */
+const char* qsv_version(void);
+
+/* ------------------------------------------------------------------ states */
+
+/* Bytes of a state of n qubits: 2^n * (8 | 16).  The state is 2^n complex
+ * numbers (Sec. 1, memory of Schroedinger-style simulation). */
+qsv_status qsv_state_bytes(int n, qsv_dtype dt, size_t* bytes);
+
+/* Convenience allocation for C callers (hipMalloc); Python callers pass torch
+ * memory instead.  Free with qsv_state_free. */
+qsv_status qsv_state_alloc(int n, qsv_dtype dt, void** psi);
+qsv_status qsv_state_free(void* psi);
+
+/* psi = |index>: amplitude `index` = 1, every other amplitude = +0.
+ * index < 2^n. */
+qsv_status qsv_init_basis(void* psi, int n, qsv_dtype dt, uint64_t index, void* stream);
+
+/* Seeded synthetic state used by tests and benchmarks (not from the paper):
+ * amplitude i = s * ((u(i,0) - 1/2) + i (u(i,1) - 1/2)), where
+ * u(i,j) = (SplitMix64(seed XOR (2i+j)) >> 11) * 2^-53 (SplitMix64 output
+ * function of Steele, Lea & Flood 2014 evaluated at that state) and
+ * s = 1 / sqrt(sum_i |raw_i|^2) (FP64 sum).  Values are computed in FP64 and
+ * rounded to the state's precision.  `work` is a device buffer of
+ * qsv_reduce_workspace_bytes() bytes. */
+qsv_status qsv_init_random(void* psi, int n, qsv_dtype dt, uint64_t seed, void* work, void* stream);
+
+/* ------------------------------------------------------ gate application */
+
+/* Apply the k-target gate G (host, complex128, 2^k x 2^k, see conventions),
+ * controlled on `controls` (c entries, may be NULL when c == 0), to psi in
+ * place: eq. (1) for every bitstring q of the non-target qubits whose control
+ * bits are 1 (Sec. 2).  G need not be unitary.  The library recognises exact
+ * 0/1 permutation matrices (moved bit-exactly, no arithmetic) and diagonal
+ * matrices (only entries != 1 are touched), and uses MFMA matrix cores for
+ * uncontrolled k = 4, 5.  k <= 5; c any (k + c <= n). */
+qsv_status qsv_apply_gate(void* psi, int n, qsv_dtype dt, const int* targets, int k,
+                          const int* controls, int c, const double* G, void* stream);
+
+/* One dense block of a fused circuit: eq. (1) with a k-qubit matrix M (host,
+ * complex128, conventions above), k <= 5, no controls (fold them into M). */
+typedef struct {
+    int k;
+    int targets[QSV_MAX_TARGETS];
+    const double* M;
+} qsv_block;
+
+/* Apply nblocks blocks in order.  Block matrices are staged to device memory
+ * with an asynchronous copy on `stream` before the kernels that use them.
+ * Not capturable into a HIP graph (use a plan instead). */
+qsv_status qsv_apply_fused(void* psi, int n, qsv_dtype dt, const qsv_block* blocks, int nblocks,
+                           void* stream);
+
+/* ---------------------------------------------------------- observables */
+
+/* H = sum_j coeff[j] P_j (Sec. 3, Hamiltonian objects), each Pauli string
+ * given by masks: qubit q carries X if only bit q of x_mask is set, Z if only
+ * bit q of z_mask is set, Y if both, I if neither.  Host arrays, nterms >= 1.
+ * Bits at or above n must be 0. */
+typedef struct {
+    int nterms;
+    const uint64_t* x_mask;
+    const uint64_t* z_mask;
+    const double* coeff;
+} qsv_pauli_sum;
+
+/* Size in bytes of the scratch buffer used by reductions
+ * (qsv_norm2, qsv_expectation, qsv_inner, qsv_init_random). */
+qsv_status qsv_reduce_workspace_bytes(size_t* bytes);
+
+/* out_dev[0] = sum_i |psi_i|^2, accumulated in FP64 in a fixed order
+ * (deterministic for a given n).  out_dev: 1 double, device. */
+qsv_status qsv_norm2(const void* psi, int n, qsv_dtype dt, double* out_dev, void* work,
+                     void* stream);
+
+/* out_dev[0] = Re <psi|H|psi>, out_dev[1] = Im (a rounding diagnostic; 0 in
+ * exact arithmetic for real coefficients), accumulated in FP64 in a fixed
+ * order.  Diagonal terms share one pass; other terms share a pass per
+ * distinct x_mask.  out_dev: 2 doubles, device. */
+qsv_status qsv_expectation(const void* psi, int n, qsv_dtype dt, const qsv_pauli_sum* H,
+                           double* out_dev, void* work, void* stream);
+
+/* out_dev[0..1] = <a|b> (re, im) in FP64. */
+qsv_status qsv_inner(const void* a, const void* b, int n, qsv_dtype dt, double* out_dev,
+                     void* work, void* stream);
+
+/* out = H psi (out and psi distinct device states of the same n and dtype). */
+qsv_status qsv_apply_pauli_sum(const void* psi, void* out, int n, qsv_dtype dt,
+                               const qsv_pauli_sum* H, void* stream);
+
+/* ------------------------------------------------------------- circuits */
+
+/* Gate kinds (Sec. 3: circuits of 1-, 2- and 3-qubit gates).  Rotations are
+ * R_P(theta) = exp(-i theta P / 2) with theta = params[param]:
+ *   RX = [[c, -i s], [-i s, c]], RY = [[c, -s], [s, c]],
+ *   RZ = diag(e^{-i theta/2}, e^{i theta/2}), c = cos(theta/2), s = sin(theta/2).
+ * H = [[1,1],[1,-1]]/sqrt 2; X, Y, Z the Pauli matrices; SWAP on 2 targets;
+ * MATRIX uses M (k targets).  Any kind may carry controls (CNOT = X with one
+ * control, CZ = Z with one control, CRZ = RZ with one control). */
+typedef enum {
+    QSV_OP_MATRIX = 0,
+    QSV_OP_H = 1,
+    QSV_OP_X = 2,
+    QSV_OP_Y = 3,
+    QSV_OP_Z = 4,
+    QSV_OP_RX = 5,
+    QSV_OP_RY = 6,
+    QSV_OP_RZ = 7,
+    QSV_OP_SWAP = 8
+} qsv_op_kind;
+
+typedef struct {
+    int kind;                          /* qsv_op_kind */
+    int k;                             /* number of targets */
+    int targets[QSV_MAX_TARGETS];
+    int c;                             /* number of controls */
+    int controls[QSV_MAX_CONTROLS];
+    int param;                         /* rotations: index into params; else -1 */
+    const double* M;                   /* QSV_OP_MATRIX: host complex128 2^k x 2^k */
+} qsv_op;
+
+typedef struct {
+    int n;
+    int nops;
+    const qsv_op* ops;
+    int nparams; /* length of the parameter vector */
+} qsv_circuit;
+
+typedef struct qsv_plan qsv_plan;
+
+/* Compile a circuit into launches.  Gates are fused into dense blocks of at
+ * most fuse_k qubits (1..5; 1 = no fusion) wherever every qubit of the gate,
+ * targets and controls, fits the block; gates on disjoint qubits may be
+ * reordered.  If params_host is non-NULL, rotation angles are bound now and
+ * rotations fuse like any other gate; otherwise rotations stay separate
+ * launches that read their angle from params_dev at run time.  Matrices are
+ * copied to plan-owned device memory (this call synchronises the device). */
+qsv_status qsv_plan_create(const qsv_circuit* circ, qsv_dtype dt, int fuse_k,
+                           const double* params_host, qsv_plan** plan);
+
+/* Apply the plan to psi in place.  params_dev (device, nparams doubles) is
+ * read only by unbound rotations (may be NULL if there are none).  The first
+ * run for a given (psi, params_dev, stream) records the launches into a HIP
+ * graph that later runs replay (disable with the environment variable
+ * QSV_NO_GRAPH=1). */
+qsv_status qsv_plan_run(qsv_plan* plan, void* psi, const double* params_dev, void* stream);
+
+/* Launch count, algorithmic HBM bytes (each touched amplitude read and
+ * written once) and algorithmic flops of one run. */
+qsv_status qsv_plan_info(const qsv_plan* plan, int* nlaunches, double* bytes, double* flops);
+
+qsv_status qsv_plan_destroy(qsv_plan* plan);
+
+/* ------------------------------------------------------------ gradients */
+
+typedef struct qsv_adjoint_plan qsv_adjoint_plan;
+
+/* Prepare E(theta) = <psi(theta)|H|psi(theta)>, psi(theta) = U_N..U_1|0..0>,
+ * and its gradient by the adjoint method (Jones & Gacon 2020): one forward
+ * sweep, lambda = H psi, then one reverse sweep that uncomputes both vectors
+ * with U_k^dagger and reads g_k = Im <lambda_k| P_k |psi_k> for every rotation
+ * exp(-i theta P_k / 2) (controlled rotations: restricted to the
+ * control-on subspace).  No per-gate checkpoints are kept.  Ops must be
+ * unitary; parameters may be shared between ops (their terms add).
+ * *work_bytes = size of the device workspace qsv_adjoint_run needs (two
+ * states plus FP64 partial sums).  fuse_k as in qsv_plan_create (applies to
+ * runs of non-rotation gates). */
+qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum* H, qsv_dtype dt,
+                                   int fuse_k, qsv_adjoint_plan** plan, size_t* work_bytes);
+
+/* energy_dev[0] = E (FP64), grad_dev[0..nparams-1] = dE/dtheta (FP64),
+ * both device.  params_dev: device, nparams doubles.  The states are swept in
+ * the plan's dtype; every reduction accumulates in FP64. */
+qsv_status qsv_adjoint_run(qsv_adjoint_plan* plan, const double* params_dev, void* work,
+                           double* energy_dev, double* grad_dev, void* stream);
+
+/* Forward sweep only: E into energy_dev, the final state into work's first
+ * state slot (read it with qsv_adjoint_state). */
+qsv_status qsv_adjoint_energy(qsv_adjoint_plan* plan, const double* params_dev, void* work,
+                              double* energy_dev, void* stream);
+
+/* Device pointer of the state slot inside work (slot 0 = psi, 1 = lambda). */
+qsv_status qsv_adjoint_state(const qsv_adjoint_plan* plan, void* work, int slot, void** psi);
+
+qsv_status qsv_adjoint_plan_destroy(qsv_adjoint_plan* plan);
+
+/* One-shot form: plan, run, and release (host-synchronises the stream before
+ * releasing).  work from qsv_adjoint_plan_create's size for the same input. */
+qsv_status qsv_adjoint_gradient(const qsv_circuit* circ, const double* params_dev,
+                                const qsv_pauli_sum* H, qsv_dtype dt, void* work,
+                                double* energy_dev, double* grad_dev, void* stream);
+
+/* --------------------------------------------------------------- batches */
+
+typedef struct qsv_batch_plan qsv_batch_plan;
+
+/* Many independent (circuit, Hamiltonian) instances of uneven size
+ * (n <= QSV_BATCH_MAX_QUBITS, rotation circuits as for the adjoint plan)
+ * evaluated together: energies and adjoint gradients of all instances in one
+ * persistent kernel launch.  Instances whose two state vectors fit one
+ * compute unit's LDS run entirely there; larger ones sweep their own region
+ * of the workspace.  Parameters and gradients of instance i live at
+ * offsets[i] .. offsets[i+1]-1 of the concatenated vectors
+ * (qsv_batch_offsets).  *work_bytes = workspace size. */
+#define QSV_BATCH_MAX_QUBITS 24
+qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* Hs, int ninst,
+                                 qsv_dtype dt, qsv_batch_plan** plan, size_t* work_bytes);
+
+/* offsets: ninst + 1 int64 entries (host). */
+qsv_status qsv_batch_offsets(const qsv_batch_plan* plan, int64_t* offsets);
+
+/* energies_dev: ninst doubles; grads_dev: offsets[ninst] doubles (device). */
+qsv_status qsv_batch_run(qsv_batch_plan* plan, const double* params_dev, void* work,
+                         double* energies_dev, double* grads_dev, void* stream);
+
+/* Autotuner: times candidate launch shapes (LDS-tier threshold, workgroup
+ * size) on this batch with these inputs, keeps the fastest, and records it in
+ * the JSON cache named by QSV_TUNE_CACHE (if set).  Synchronises the stream.
+ * chosen (optional, host, 2 ints) receives (lds_max_qubits, threads). */
+qsv_status qsv_batch_tune(qsv_batch_plan* plan, const double* params_dev, void* work,
+                          double* energies_dev, double* grads_dev, void* stream, int* chosen);
+
+qsv_status qsv_batch_plan_destroy(qsv_batch_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSV_H */

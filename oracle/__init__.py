@@ -50,6 +50,7 @@ def lib():
             L.orc_apply.argtypes = [ctypes.c_int, _D, _D, _I, ctypes.c_int, _I, ctypes.c_int, _D]
             L.orc_inner.argtypes = [ctypes.c_int, _D, _D, _D]
             L.orc_expect.argtypes = [ctypes.c_int, _D, ctypes.c_int, _U, _U, _D, _D, _D]
+            L.orc_apply_hamiltonian.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, _U, _U, _D]
             L.orc_norm2.argtypes = [ctypes.c_int, _D, _D]
             L.orc_random_norm2.argtypes = [ctypes.c_int, ctypes.c_uint64, _D]
             L.orc_random_state.argtypes = [ctypes.c_int, ctypes.c_uint64, _D]
@@ -129,6 +130,17 @@ def expect(psi, H, per_term: bool = False):
     if per_term:
         return e, terms[0::2][:len(cf)] + 1j * terms[1::2][:len(cf)]
     return e
+
+
+def apply_hamiltonian(psi, H) -> np.ndarray:
+    """H psi for a Pauli sum H."""
+    psi = _as_c128(psi)
+    n = int(psi.size).bit_length() - 1
+    x, z, cf = _ham(H)
+    out = np.empty_like(psi)
+    _check(lib().orc_apply_hamiltonian(n, _p(psi, _D), _p(out, _D), len(cf), _p(x, _U), _p(z, _U),
+                                       _p(cf, _D)), "apply_hamiltonian")
+    return out
 
 
 def random_norm2(n: int, seed: int) -> float:

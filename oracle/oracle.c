@@ -256,7 +256,7 @@ int orc_expect(int n, const double* psi, int nterms, const uint64_t* x, const ui
 }
 
 /* lam = H psi = sum_j coeff_j P_j psi. */
-static int apply_hamiltonian(int n, const double* psi, double* lam, int nterms, const uint64_t* x,
+int orc_apply_hamiltonian(int n, const double* psi, double* lam, int nterms, const uint64_t* x,
                              const uint64_t* z, const double* coeff)
 {
     const size_t bytes = (sizeof(double) * 2) << n;
@@ -627,7 +627,7 @@ int orc_adjoint(int n, int nops, const int* kind, const int* k, const int* tgt, 
     }
     int rc = run_circuit(n, &C, params, NULL, phi);
     if (!rc)
-        rc = apply_hamiltonian(n, phi, lam, nterms, x, z, coeff);
+        rc = orc_apply_hamiltonian(n, phi, lam, nterms, x, z, coeff);
     if (!rc) {
         ocx e = dot((const ocx*)phi, (const ocx*)lam, n);
         *E = e.re;

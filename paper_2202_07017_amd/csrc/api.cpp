@@ -1,0 +1,779 @@
+// Host side of libqsv.so: argument validation, canonical gate forms, kernel
+// selection, the fusion planner, plans with HIP-graph replay, and the adjoint
+// gradient driver.  Every public function validates before it enqueues.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "qsv.h"
+#include "qsv_internal.h"
+#include "qsv_host.h"
+
+using namespace qsv;
+
+// ------------------------------------------------------------------ errors
+
+namespace qsv {
+thread_local std::string t_err = "no error";
+
+qsv_status fail(qsv_status st, const char* fmt, ...)
+{
+    char buf[768];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return st;
+}
+
+qsv_status ok()
+{
+    t_err = "no error";
+    return QSV_OK;
+}
+
+size_t amp_bytes(int dt)
+{
+    return dt == QSV_C64 ? 8 : 16;
+}
+
+qsv_status check_n_dt(int n, int dt)
+{
+    if (n < 1 || n > QSV_MAX_QUBITS)
+        return fail(QSV_ERR_ARG, "n = %d outside [1, %d]", n, QSV_MAX_QUBITS);
+    if (dt != QSV_C64 && dt != QSV_C128)
+        return fail(QSV_ERR_ARG, "dtype %d is neither QSV_C64 (1) nor QSV_C128 (2)", dt);
+    return QSV_OK;
+}
+
+qsv_status check_state(const void* psi, int n, int dt, const char* what)
+{
+    qsv_status st = check_n_dt(n, dt);
+    if (st)
+        return st;
+    if (!psi)
+        return fail(QSV_ERR_ARG, "%s is NULL", what);
+    if (reinterpret_cast<uintptr_t>(psi) % 16)
+        return fail(QSV_ERR_ARG, "%s is not 16-byte aligned", what);
+    return QSV_OK;
+}
+
+qsv_status check_qubits(int n, const int* t, int k, int kmax, const int* c, int nc)
+{
+    if (k < 1 || k > kmax)
+        return fail(QSV_ERR_ARG, "k = %d outside [1, %d]", k, kmax);
+    if (nc < 0)
+        return fail(QSV_ERR_ARG, "negative control count %d", nc);
+    if (k + nc > n)
+        return fail(QSV_ERR_ARG, "k + c = %d exceeds n = %d", k + nc, n);
+    if (!t)
+        return fail(QSV_ERR_ARG, "targets is NULL");
+    if (nc > 0 && !c)
+        return fail(QSV_ERR_ARG, "controls is NULL with c = %d", nc);
+    uint64_t seen = 0;
+    for (int j = 0; j < k + nc; ++j) {
+        const int q = j < k ? t[j] : c[j - k];
+        if (q < 0 || q >= n)
+            return fail(QSV_ERR_QUBIT, "qubit %d outside [0, %d)", q, n);
+        if ((seen >> q) & 1ull)
+            return fail(QSV_ERR_QUBIT, "qubit %d appears twice among targets and controls", q);
+        seen |= 1ull << q;
+    }
+    return QSV_OK;
+}
+
+qsv_status check_hamiltonian(const qsv_pauli_sum* H, int n)
+{
+    if (!H || H->nterms < 1 || !H->x_mask || !H->z_mask || !H->coeff)
+        return fail(QSV_ERR_ARG, "Pauli sum is NULL, empty or has NULL arrays");
+    const uint64_t lim = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    for (int j = 0; j < H->nterms; ++j)
+        if ((H->x_mask[j] | H->z_mask[j]) & ~lim)
+            return fail(QSV_ERR_QUBIT, "Pauli term %d acts on a qubit >= n = %d", j, n);
+    return QSV_OK;
+}
+
+// ---------------------------------------------------- canonical gate forms
+
+InsertSpec make_ins(std::vector<int> pos, uint64_t setmask)
+{
+    std::sort(pos.begin(), pos.end());
+    InsertSpec s{};
+    s.nins = (int)pos.size();
+    s.setmask = setmask;
+    for (size_t j = 0; j < pos.size(); ++j)
+        s.low[j] = (1ull << pos[j]) - 1;
+    return s;
+}
+
+// Targets sorted ascending; canonical tau bit j <-> ct[j].  The user's first
+// target is the most significant bit of the user's tau.
+void canonicalize(const int* t, int k, const double* G, int* ct, std::vector<double>& Gc)
+{
+    const int D = 1 << k;
+    int order[QSV_MAX_TARGETS];
+    for (int j = 0; j < k; ++j)
+        order[j] = j;
+    std::sort(order, order + k, [&](int a, int b) { return t[a] < t[b]; });
+    for (int j = 0; j < k; ++j)
+        ct[j] = t[order[j]];
+    auto to_user = [&](int tc) {
+        int tu = 0;
+        for (int j = 0; j < k; ++j)
+            if ((tc >> j) & 1)
+                tu |= 1 << (k - 1 - order[j]);
+        return tu;
+    };
+    Gc.assign((size_t)2 * D * D, 0.0);
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) {
+            const size_t u = ((size_t)to_user(r) * D + to_user(c)) * 2;
+            Gc[((size_t)r * D + c) * 2] = G[u];
+            Gc[((size_t)r * D + c) * 2 + 1] = G[u + 1];
+        }
+}
+
+static uint64_t deposit(uint64_t v, const int* pos, int m, int shift)
+{
+    uint64_t o = 0;
+    for (int j = 0; j < m; ++j)
+        if ((v >> j) & 1ull)
+            o |= 1ull << (pos[j] - shift);
+    return o;
+}
+
+// Build the launch for eq. (1) with canonical (ct, Gc) and controls.
+// `upload` receives bytes the kernel needs in device memory (set gdev to them).
+Built build_launch(int n, int dt, const int* ct, int k, const int* ctl, int c, const double* Gc,
+                   bool allow_mfma)
+{
+    Built b;
+    GateLaunch& L = b.L;
+    L.dt = dt;
+    L.n = n;
+    const int D = 1 << k;
+    const size_t S = amp_bytes(dt);
+    uint64_t cmask = 0;
+    bool ctl0 = false;
+    for (int j = 0; j < c; ++j) {
+        cmask |= 1ull << ctl[j];
+        ctl0 |= ctl[j] == 0;
+    }
+    auto G = [&](int r, int col, int part) { return Gc[((size_t)r * D + col) * 2 + part]; };
+
+    bool diag = true, perm = true, ident = true;
+    int src[32];
+    for (int r = 0; r < D; ++r) {
+        int ones = 0;
+        for (int col = 0; col < D; ++col) {
+            const double re = G(r, col, 0), im = G(r, col, 1);
+            if (r != col && (re != 0.0 || im != 0.0))
+                diag = false;
+            if (im != 0.0 || (re != 0.0 && re != 1.0))
+                perm = false;
+            if (re == 1.0 && im == 0.0) {
+                ++ones;
+                src[r] = col;
+            }
+            if (r == col && (re != 1.0 || im != 0.0))
+                ident = false;
+        }
+        if (ones != 1)
+            perm = false;
+    }
+    if (perm) {
+        int seen[32] = {0};
+        for (int r = 0; r < D; ++r)
+            if (seen[src[r]]++)
+                perm = false;
+    }
+    if (diag && ident) {
+        b.noop = true;
+        return b;
+    }
+    std::vector<int> tgt(ct, ct + k), ctlv(ctl, ctl + c);
+    if (perm) {
+        L.type = L_PERM;
+        std::vector<int> pos = tgt;
+        pos.insert(pos.end(), ctlv.begin(), ctlv.end());
+        const bool bit0 = std::find(pos.begin(), pos.end(), 0) != pos.end();
+        const int shift = (dt == QSV_C64 && !bit0) ? 1 : 0;
+        L.mode = shift ? W2 : W1;
+        for (int& p : pos)
+            p -= shift;
+        L.ins = make_ins(pos, cmask >> shift);
+        L.ngroups = 1ull << (n - shift - (int)pos.size());
+        int m = 0;
+        for (int r = 0; r < D; ++r)
+            if (src[r] != r) {
+                L.off[m] = deposit((uint64_t)r, ct, k, shift);
+                L.off2[m] = deposit((uint64_t)src[r], ct, k, shift);
+                ++m;
+            }
+        L.nmoved = m;
+        const double groups = std::ldexp(1.0, n - k - c);
+        L.bytes = 2.0 * S * groups * m;
+        return b;
+    }
+    if (diag) {
+        L.type = L_DIAG;
+        int nontriv = 0, tstar = 0;
+        for (int r = 0; r < D; ++r)
+            if (G(r, r, 0) != 1.0 || G(r, r, 1) != 0.0) {
+                ++nontriv;
+                tstar = r;
+            }
+        std::vector<int> pos = ctlv;
+        uint64_t set = cmask;
+        if (nontriv == 1) {
+            pos.insert(pos.end(), tgt.begin(), tgt.end());
+            set |= deposit((uint64_t)tstar, ct, k, 0);
+            L.K = 0;
+            L.g = {G(tstar, tstar, 0), G(tstar, tstar, 1)};
+        } else {
+            L.K = k;
+            for (int j = 0; j < k; ++j)
+                L.tpos[j] = ct[j];
+            L.g.resize((size_t)2 * D);
+            for (int r = 0; r < D; ++r) {
+                L.g[2 * r] = G(r, r, 0);
+                L.g[2 * r + 1] = G(r, r, 1);
+            }
+        }
+        const bool bit0 = std::find(pos.begin(), pos.end(), 0) != pos.end();
+        const int shift = (dt == QSV_C64 && !bit0) ? 1 : 0;
+        L.mode = shift ? W2 : W1;
+        for (int& p : pos)
+            p -= shift;
+        L.ins = make_ins(pos, set >> shift);
+        L.ngroups = 1ull << (n - shift - (int)pos.size());
+        const double touched = std::ldexp(1.0, n - (int)pos.size() - shift) * (shift ? 2 : 1);
+        L.bytes = 2.0 * S * touched;
+        L.flops = 6.0 * touched;
+        return b;
+    }
+    // dense
+    L.K = k;
+    L.flops = 8.0 * D * std::ldexp(1.0, n - c);
+    L.bytes = 2.0 * S * std::ldexp(1.0, n - c);
+    const char* nomfma = getenv("QSV_NO_MFMA");
+    if (allow_mfma && c == 0 && k >= 4 && n >= k + 6 && !(nomfma && nomfma[0] == '1')) {
+        L.type = L_MFMA;
+        std::vector<int> B = tgt;
+        for (int q = 0, got = 0; got < 6; ++q)
+            if (std::find(tgt.begin(), tgt.end(), q) == tgt.end()) {
+                B.push_back(q);
+                ++got;
+            }
+        std::sort(B.begin(), B.end());
+        int Lr = 0;
+        while (Lr < (int)B.size() && B[Lr] == Lr)
+            ++Lr;
+        L.L = Lr;
+        auto rank = [&](int q) { return (int)(std::find(B.begin(), B.end(), q) - B.begin()); };
+        for (int j = 0; j < k; ++j)
+            L.tloc[j] = rank(ct[j]);
+        int fj = 0;
+        for (int q : B)
+            if (std::find(tgt.begin(), tgt.end(), q) == tgt.end())
+                L.floc[fj++] = rank(q);
+        const int nch = 1 << ((int)B.size() - Lr);
+        for (int cidx = 0; cidx < nch; ++cidx) {
+            uint64_t o = 0;
+            for (int m = 0; m < (int)B.size() - Lr; ++m)
+                if ((cidx >> m) & 1)
+                    o |= 1ull << B[Lr + m];
+            L.choff[cidx] = o;
+        }
+        L.ins = make_ins(B, 0);
+        L.ntiles = 1ull << (n - k - 6);
+        L.ngroups = L.ntiles;
+        mfma_fragments(Gc, k, dt, b.upload);
+        return b;
+    }
+    L.type = L_DENSE;
+    std::vector<int> pos;
+    int shift = 0;
+    if (dt == QSV_C64 && ct[0] == 0) {
+        L.mode = INTRA;
+        shift = 1;
+        for (int j = 1; j < k; ++j)
+            pos.push_back(ct[j] - 1);
+        for (int q : ctlv)
+            pos.push_back(q - 1);
+        for (int v = 0; v < D / 2; ++v)
+            L.off[v] = deposit((uint64_t)v, ct + 1, k - 1, 1);
+    } else if (dt == QSV_C64 && !ctl0) {
+        L.mode = W2;
+        shift = 1;
+        for (int q : tgt)
+            pos.push_back(q - 1);
+        for (int q : ctlv)
+            pos.push_back(q - 1);
+        for (int v = 0; v < D; ++v)
+            L.off[v] = deposit((uint64_t)v, ct, k, 1);
+    } else {
+        L.mode = W1;
+        pos = tgt;
+        pos.insert(pos.end(), ctlv.begin(), ctlv.end());
+        for (int v = 0; v < D; ++v)
+            L.off[v] = deposit((uint64_t)v, ct, k, 0);
+    }
+    L.ins = make_ins(pos, cmask >> shift);
+    L.ngroups = 1ull << (n - shift - (int)pos.size());
+    if (k <= 3) {
+        L.g.assign(Gc, Gc + (size_t)2 * D * D);
+    } else {
+        const size_t cnt = (size_t)2 * D * D;
+        b.upload.resize(cnt * (dt == QSV_C64 ? 4 : 8));
+        for (size_t j = 0; j < cnt; ++j) {
+            if (dt == QSV_C64)
+                reinterpret_cast<float*>(b.upload.data())[j] = (float)Gc[j];
+            else
+                reinterpret_cast<double*>(b.upload.data())[j] = Gc[j];
+        }
+    }
+    return b;
+}
+
+// Launch for an unbound rotation exp(-i theta P/2) on `target` with controls.
+GateLaunch rotation_launch(int n, int dt, int rot, int target, const int* ctl, int c, int pidx)
+{
+    GateLaunch L;
+    L.dt = dt;
+    L.n = n;
+    L.rot = rot;
+    L.pidx = pidx;
+    const size_t S = amp_bytes(dt);
+    uint64_t cmask = 0;
+    bool ctl0 = false;
+    std::vector<int> ctlv(ctl, ctl + c);
+    for (int q : ctlv) {
+        cmask |= 1ull << q;
+        ctl0 |= q == 0;
+    }
+    L.bytes = 2.0 * S * std::ldexp(1.0, n - c);
+    if (rot == ROT_Z) {
+        L.type = L_DIAG;
+        L.K = 1;
+        L.tpos[0] = target;
+        const int shift = (dt == QSV_C64 && !ctl0) ? 1 : 0;
+        L.mode = shift ? W2 : W1;
+        std::vector<int> pos = ctlv;
+        for (int& p : pos)
+            p -= shift;
+        L.ins = make_ins(pos, cmask >> shift);
+        L.ngroups = 1ull << (n - shift - c);
+        L.flops = 6.0 * std::ldexp(1.0, n - c);
+        return L;
+    }
+    L.type = L_DENSE;
+    L.K = 1;
+    L.flops = 16.0 * std::ldexp(1.0, n - c);
+    std::vector<int> pos;
+    int shift = 0;
+    if (dt == QSV_C64 && target == 0) {
+        L.mode = INTRA;
+        shift = 1;
+        for (int q : ctlv)
+            pos.push_back(q - 1);
+        L.off[0] = 0;
+    } else if (dt == QSV_C64 && !ctl0) {
+        L.mode = W2;
+        shift = 1;
+        pos.push_back(target - 1);
+        for (int q : ctlv)
+            pos.push_back(q - 1);
+        L.off[0] = 0;
+        L.off[1] = 1ull << (target - 1);
+    } else {
+        L.mode = W1;
+        pos.push_back(target);
+        pos.insert(pos.end(), ctlv.begin(), ctlv.end());
+        L.off[0] = 0;
+        L.off[1] = 1ull << target;
+    }
+    L.ins = make_ins(pos, cmask >> shift);
+    L.ngroups = 1ull << (n - shift - (int)pos.size());
+    return L;
+}
+
+// -------------------------------------------------------- device staging
+
+namespace {
+// Per (device, stream) double-buffered staging of small host arrays: a pinned
+// host slot is refilled only after the copy that last used it has finished,
+// and the device slot is reused in stream order.
+struct Slot {
+    void* host = nullptr;
+    void* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+struct StageEntry {
+    Slot slot[2];
+    int next = 0;
+};
+std::mutex g_stage_mu;
+std::map<std::pair<int, hipStream_t>, StageEntry> g_stage;
+}  // namespace
+
+qsv_status stage_upload(const void* host, size_t bytes, hipStream_t s, const void** dev_out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    StageEntry& ent = g_stage[{dev, s}];
+    Slot& sl = ent.slot[ent.next];
+    ent.next ^= 1;
+    if (sl.used) {
+        e = hipEventSynchronize(sl.ev);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "staging event: %s", hipGetErrorString(e));
+    }
+    if (sl.cap < bytes) {
+        if (sl.dev) {
+            hipStreamSynchronize(s);
+            hipFree(sl.dev);
+            hipHostFree(sl.host);
+        }
+        size_t cap = bytes < (1u << 16) ? (1u << 16) : bytes;
+        if (hipMalloc(&sl.dev, cap) != hipSuccess || hipHostMalloc(&sl.host, cap, 0) != hipSuccess) {
+            sl.dev = sl.host = nullptr;
+            sl.cap = 0;
+            return fail(QSV_ERR_NOMEM, "staging allocation of %zu bytes failed", cap);
+        }
+        sl.cap = cap;
+        if (!sl.ev && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess)
+            return fail(QSV_ERR_HIP, "hipEventCreate failed");
+    }
+    std::memcpy(sl.host, host, bytes);
+    e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "staging copy: %s", hipGetErrorString(e));
+    e = hipEventRecord(sl.ev, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "staging event record: %s", hipGetErrorString(e));
+    sl.used = true;
+    *dev_out = sl.dev;
+    return QSV_OK;
+}
+
+qsv_status launch_checked(const GateLaunch& L, void* psi, void* psi2, hipStream_t s)
+{
+    hipError_t e = launch_gate(L, psi, psi2, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return QSV_OK;
+}
+
+// Group a Pauli sum into diagonal chunks and per-x-mask chunks.
+void group_terms(const qsv_pauli_sum* H, std::vector<TermChunk>& diag,
+                 std::vector<std::pair<uint64_t, TermChunk>>& pairs)
+{
+    std::map<uint64_t, std::vector<int>> byx;
+    std::vector<int> order;
+    for (int j = 0; j < H->nterms; ++j) {
+        if (byx.find(H->x_mask[j]) == byx.end())
+            order.push_back(j);
+        byx[H->x_mask[j]].push_back(j);
+    }
+    for (int first : order) {
+        const uint64_t x = H->x_mask[first];
+        const std::vector<int>& js = byx[x];
+        for (size_t s0 = 0; s0 < js.size(); s0 += kMaxTermsPerLaunch) {
+            TermChunk t{};
+            for (size_t s1 = s0; s1 < js.size() && s1 < s0 + kMaxTermsPerLaunch; ++s1) {
+                const int j = js[s1];
+                t.z[t.nt] = H->z_mask[j];
+                t.c[t.nt] = H->coeff[j];
+                t.ylo[t.nt] = __builtin_popcountll(H->x_mask[j] & H->z_mask[j]) & 3;
+                ++t.nt;
+            }
+            if (x == 0)
+                diag.push_back(t);
+            else
+                pairs.push_back({x, t});
+        }
+    }
+}
+
+qsv_status enqueue_expectation(const void* psi, int n, int dt, const qsv_pauli_sum* H, double* out,
+                               double* work, int ncomp, hipStream_t s)
+{
+    std::vector<TermChunk> diag;
+    std::vector<std::pair<uint64_t, TermChunk>> pairs;
+    group_terms(H, diag, pairs);
+    int acc = 0;
+    for (const TermChunk& t : diag) {
+        hipError_t e = launch_expect_diag(psi, n, dt, t, work, acc, s);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
+        acc = 1;
+    }
+    for (const auto& pr : pairs) {
+        hipError_t e = launch_expect_pair(psi, n, dt, pr.first, pr.second, work, acc, s);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
+        acc = 1;
+    }
+    hipError_t e = launch_finalize(work, reduce_blocks(n, dt), ncomp, out, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "finalize launch: %s", hipGetErrorString(e));
+    return QSV_OK;
+}
+
+qsv_status enqueue_hpsi(const void* psi, void* lam, int n, int dt, const qsv_pauli_sum* H,
+                        hipStream_t s)
+{
+    std::vector<TermChunk> diag;
+    std::vector<std::pair<uint64_t, TermChunk>> pairs;
+    group_terms(H, diag, pairs);
+    if (diag.empty())
+        diag.push_back(TermChunk{});  // lam = 0 * psi
+    int acc = 0;
+    for (const TermChunk& t : diag) {
+        hipError_t e = launch_hpsi_diag(psi, lam, n, dt, t, acc, s);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "H psi launch: %s", hipGetErrorString(e));
+        acc = 1;
+    }
+    for (const auto& pr : pairs) {
+        hipError_t e = launch_hpsi_pair(psi, lam, n, dt, pr.first, pr.second, s);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "H psi launch: %s", hipGetErrorString(e));
+    }
+    return QSV_OK;
+}
+
+}  // namespace qsv
+
+// ============================================================== C ABI
+
+extern "C" {
+
+const char* qsv_last_error(void)
+{
+    return t_err.c_str();
+}
+
+const char* qsv_version(void)
+{
+    return "qsv 0.1 gfx950";
+}
+
+qsv_status qsv_state_bytes(int n, qsv_dtype dt, size_t* bytes)
+{
+    qsv_status st = check_n_dt(n, dt);
+    if (st)
+        return st;
+    if (!bytes)
+        return fail(QSV_ERR_ARG, "bytes is NULL");
+    *bytes = amp_bytes(dt) << n;
+    return ok();
+}
+
+qsv_status qsv_state_alloc(int n, qsv_dtype dt, void** psi)
+{
+    qsv_status st = check_n_dt(n, dt);
+    if (st)
+        return st;
+    if (!psi)
+        return fail(QSV_ERR_ARG, "psi is NULL");
+    hipError_t e = hipMalloc(psi, amp_bytes(dt) << n);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_NOMEM, "hipMalloc of %zu bytes: %s", amp_bytes(dt) << n,
+                    hipGetErrorString(e));
+    return ok();
+}
+
+qsv_status qsv_state_free(void* psi)
+{
+    if (!psi)
+        return ok();
+    hipError_t e = hipFree(psi);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "hipFree: %s", hipGetErrorString(e));
+    return ok();
+}
+
+qsv_status qsv_init_basis(void* psi, int n, qsv_dtype dt, uint64_t index, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if (index >> n)
+        return fail(QSV_ERR_ARG, "basis index %llu >= 2^%d", (unsigned long long)index, n);
+    hipError_t e = launch_init_basis(psi, n, dt, index, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "init launch: %s", hipGetErrorString(e));
+    return ok();
+}
+
+qsv_status qsv_reduce_workspace_bytes(size_t* bytes)
+{
+    if (!bytes)
+        return fail(QSV_ERR_ARG, "bytes is NULL");
+    *bytes = kReduceWorkBytes;
+    return ok();
+}
+
+qsv_status qsv_init_random(void* psi, int n, qsv_dtype dt, uint64_t seed, void* work, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if (!work)
+        return fail(QSV_ERR_ARG, "work is NULL");
+    hipError_t e = launch_init_random(psi, n, dt, seed, static_cast<double*>(work), (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "init launch: %s", hipGetErrorString(e));
+    return ok();
+}
+
+qsv_status qsv_apply_gate(void* psi, int n, qsv_dtype dt, const int* targets, int k,
+                          const int* controls, int c, const double* G, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if ((st = check_qubits(n, targets, k, QSV_MAX_TARGETS, controls, c)))
+        return st;
+    if (!G)
+        return fail(QSV_ERR_ARG, "G is NULL");
+    if (k + c > kMaxIns)
+        return fail(QSV_ERR_UNSUPPORTED, "k + c = %d exceeds %d", k + c, kMaxIns);
+    int ct[QSV_MAX_TARGETS];
+    std::vector<double> Gc;
+    canonicalize(targets, k, G, ct, Gc);
+    Built b = build_launch(n, dt, ct, k, controls, c, Gc.data(), true);
+    if (b.noop)
+        return ok();
+    hipStream_t s = (hipStream_t)stream;
+    if (!b.upload.empty()) {
+        const void* d = nullptr;
+        if ((st = stage_upload(b.upload.data(), b.upload.size(), s, &d)))
+            return st;
+        b.L.gdev = d;
+    }
+    if ((st = launch_checked(b.L, psi, nullptr, s)))
+        return st;
+    return ok();
+}
+
+qsv_status qsv_apply_fused(void* psi, int n, qsv_dtype dt, const qsv_block* blocks, int nblocks,
+                           void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if (nblocks < 0 || (nblocks > 0 && !blocks))
+        return fail(QSV_ERR_ARG, "bad block list");
+    for (int j = 0; j < nblocks; ++j) {
+        if ((st = check_qubits(n, blocks[j].targets, blocks[j].k, QSV_MAX_TARGETS, nullptr, 0)))
+            return st;
+        if (!blocks[j].M)
+            return fail(QSV_ERR_ARG, "block %d has a NULL matrix", j);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int j = 0; j < nblocks; ++j) {
+        int ct[QSV_MAX_TARGETS];
+        std::vector<double> Gc;
+        canonicalize(blocks[j].targets, blocks[j].k, blocks[j].M, ct, Gc);
+        Built b = build_launch(n, dt, ct, blocks[j].k, nullptr, 0, Gc.data(), true);
+        if (b.noop)
+            continue;
+        if (!b.upload.empty()) {
+            const void* d = nullptr;
+            if ((st = stage_upload(b.upload.data(), b.upload.size(), s, &d)))
+                return st;
+            b.L.gdev = d;
+        }
+        if ((st = launch_checked(b.L, psi, nullptr, s)))
+            return st;
+    }
+    return ok();
+}
+
+qsv_status qsv_norm2(const void* psi, int n, qsv_dtype dt, double* out_dev, void* work, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if (!out_dev || !work)
+        return fail(QSV_ERR_ARG, "out_dev or work is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_norm2(psi, n, dt, static_cast<double*>(work), 0, s);
+    if (e == hipSuccess)
+        e = launch_finalize(static_cast<double*>(work), reduce_blocks(n, dt), 1, out_dev, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "norm launch: %s", hipGetErrorString(e));
+    return ok();
+}
+
+qsv_status qsv_expectation(const void* psi, int n, qsv_dtype dt, const qsv_pauli_sum* H,
+                           double* out_dev, void* work, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if ((st = check_hamiltonian(H, n)))
+        return st;
+    if (!out_dev || !work)
+        return fail(QSV_ERR_ARG, "out_dev or work is NULL");
+    if ((st = enqueue_expectation(psi, n, dt, H, out_dev, static_cast<double*>(work), 2,
+                                  (hipStream_t)stream)))
+        return st;
+    return ok();
+}
+
+qsv_status qsv_inner(const void* a, const void* b, int n, qsv_dtype dt, double* out_dev, void* work,
+                     void* stream)
+{
+    qsv_status st = check_state(a, n, dt, "a");
+    if (st)
+        return st;
+    if ((st = check_state(b, n, dt, "b")))
+        return st;
+    if (!out_dev || !work)
+        return fail(QSV_ERR_ARG, "out_dev or work is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_inner(a, b, n, dt, static_cast<double*>(work), 0, s);
+    if (e == hipSuccess)
+        e = launch_finalize(static_cast<double*>(work), reduce_blocks(n, dt), 2, out_dev, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "inner launch: %s", hipGetErrorString(e));
+    return ok();
+}
+
+qsv_status qsv_apply_pauli_sum(const void* psi, void* out, int n, qsv_dtype dt,
+                               const qsv_pauli_sum* H, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if ((st = check_state(out, n, dt, "out")))
+        return st;
+    if (psi == out)
+        return fail(QSV_ERR_ARG, "psi and out must be distinct");
+    if ((st = check_hamiltonian(H, n)))
+        return st;
+    if ((st = enqueue_hpsi(psi, out, n, dt, H, (hipStream_t)stream)))
+        return st;
+    return ok();
+}
+
+}  // extern "C"

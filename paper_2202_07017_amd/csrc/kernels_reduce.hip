@@ -1,0 +1,404 @@
+// FP64 reductions over a state: norm, Pauli-sum expectation values
+// (Sec. 3, Hamiltonian primitives), inner products, and H psi.
+//
+// A Pauli string with masks (x, z) and y = #Y factors maps |i> to
+// i^y (-1)^popcount(i & z) |i xor x>.  Terms with x = 0 are diagonal and share
+// one streaming pass; terms with the same x != 0 share a pass that visits each
+// pair (i, i xor x) once, so every amplitude is read once per pass.
+//
+// Every reduction is deterministic: a fixed grid of reduce_blocks(n) blocks,
+// a fixed per-thread visiting order, a fixed in-block tree, per-block FP64
+// partials in device memory, and a one-block finalize that adds them in
+// index order.  Amplitudes are widened to FP64 before any product.
+#include "qsv_internal.h"
+
+namespace qsv {
+
+int reduce_blocks(int n, int dt)
+{
+    (void)dt;
+    const uint64_t N = 1ull << n;
+    uint64_t b = N / (kBlock * 16);
+    if (b < 1)
+        b = 1;
+    if (b > 1024)
+        b = 1024;
+    return (int)b;
+}
+
+namespace {
+
+__device__ __forceinline__ void block_sum_store(double v, double* out)
+{
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *out = red[0];
+    __syncthreads();
+}
+
+template <typename R>
+struct W;
+template <>
+struct W<float> {
+    using A = float2;
+};
+template <>
+struct W<double> {
+    using A = double2;
+};
+
+template <typename R>
+__device__ __forceinline__ double2 ld(const R* p, uint64_t i)
+{
+    const typename W<R>::A a = reinterpret_cast<const typename W<R>::A*>(p)[i];
+    return make_double2((double)a.x, (double)a.y);
+}
+
+template <typename R>
+__device__ __forceinline__ void st(R* p, uint64_t i, double2 v)
+{
+    typename W<R>::A a;
+    a.x = (R)v.x;
+    a.y = (R)v.y;
+    reinterpret_cast<typename W<R>::A*>(p)[i] = a;
+}
+
+__device__ __forceinline__ int popc64(uint64_t v)
+{
+    return __popcll(v);
+}
+
+// sum_j c_j (-1)^popcount(i & z_j)
+__device__ __forceinline__ double diag_weight(uint64_t i, const TermChunk& t)
+{
+    double w = 0.0;
+    for (int j = 0; j < t.nt; ++j)
+        w += (popc64(i & t.z[j]) & 1) ? -t.c[j] : t.c[j];
+    return w;
+}
+
+// f(i) = sum_j c_j i^(y_j + 2 popcount(i & z_j))
+__device__ __forceinline__ double2 phase_sum(uint64_t i, const TermChunk& t)
+{
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < t.nt; ++j) {
+        const int e = (t.ylo[j] + 2 * popc64(i & t.z[j])) & 3;
+        const double c = t.c[j];
+        re += e == 0 ? c : (e == 2 ? -c : 0.0);
+        im += e == 1 ? c : (e == 3 ? -c : 0.0);
+    }
+    return make_double2(re, im);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_norm2(const R* __restrict__ psi, uint64_t N,
+                                                  double* partials, int accumulate)
+{
+    double s = 0.0;
+    const uint64_t step = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
+        const double2 a = ld(psi, i);
+        s += a.x * a.x + a.y * a.y;
+    }
+    double* out = partials + blockIdx.x;
+    block_sum_store(s, out);
+    if (threadIdx.x == 0 && accumulate)
+        ;  // norm is always a single pass
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_expect_diag(const R* __restrict__ psi, uint64_t N,
+                                                        const TermChunk t, double* partials,
+                                                        int accumulate)
+{
+    double s = 0.0;
+    const uint64_t step = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
+        const double2 a = ld(psi, i);
+        s += diag_weight(i, t) * (a.x * a.x + a.y * a.y);
+    }
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* p = partials + blockIdx.x;
+        double* q = partials + gridDim.x + blockIdx.x;
+        *p = accumulate ? *p + red[0] : red[0];
+        if (!accumulate)
+            *q = 0.0;
+    }
+}
+
+// Pairs (i, j = i xor x), bit h (top bit of x) of i clear.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_expect_pair(const R* __restrict__ psi, uint64_t npairs,
+                                                        uint64_t x, uint64_t lowmask,
+                                                        const TermChunk t, double* partials,
+                                                        int accumulate)
+{
+    double sr = 0.0, si = 0.0;
+    const uint64_t step = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < npairs; g += step) {
+        const uint64_t i = ((g & ~lowmask) << 1) | (g & lowmask);
+        const uint64_t j = i ^ x;
+        const double2 a = ld(psi, i), b = ld(psi, j);
+        // w = conj(psi_j) psi_i
+        const double wr = b.x * a.x + b.y * a.y, wi = b.x * a.y - b.y * a.x;
+        const double2 fi = phase_sum(i, t), fj = phase_sum(j, t);
+        // Re[w (f(i) + conj f(j))], Im[w (f(i) - conj f(j))]
+        const double pr = fi.x + fj.x, pi = fi.y - fj.y;
+        const double qr = fi.x - fj.x, qi = fi.y + fj.y;
+        sr += wr * pr - wi * pi;
+        si += wr * qi + wi * qr;
+    }
+    __shared__ double red[2][kBlock];
+    red[0][threadIdx.x] = sr;
+    red[1][threadIdx.x] = si;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* p = partials + blockIdx.x;
+        double* q = partials + gridDim.x + blockIdx.x;
+        *p = accumulate ? *p + red[0][0] : red[0][0];
+        *q = accumulate ? *q + red[1][0] : red[1][0];
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_inner(const R* __restrict__ a, const R* __restrict__ b,
+                                                  uint64_t N, double* partials, int accumulate)
+{
+    double sr = 0.0, si = 0.0;
+    const uint64_t step = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
+        const double2 u = ld(a, i), v = ld(b, i);
+        sr += u.x * v.x + u.y * v.y;
+        si += u.x * v.y - u.y * v.x;
+    }
+    __shared__ double red[2][kBlock];
+    red[0][threadIdx.x] = sr;
+    red[1][threadIdx.x] = si;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* p = partials + blockIdx.x;
+        double* q = partials + gridDim.x + blockIdx.x;
+        *p = accumulate ? *p + red[0][0] : red[0][0];
+        *q = accumulate ? *q + red[1][0] : red[1][0];
+    }
+}
+
+// out[c] = sum_b partials[c * nb + b] in index order, c < ncomp.
+__global__ void __launch_bounds__(kBlock) k_finalize(const double* partials, int nb, int ncomp,
+                                                     double* out)
+{
+    __shared__ double red[kBlock];
+    for (int c = 0; c < ncomp; ++c) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += kBlock)
+            s += partials[c * nb + b];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            out[c] = red[0];
+        __syncthreads();
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_hpsi_diag(const R* __restrict__ psi, R* __restrict__ lam,
+                                                      uint64_t N, const TermChunk t, int accumulate)
+{
+    const uint64_t step = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
+        const double2 a = ld(psi, i);
+        const double w = diag_weight(i, t);
+        double2 o = make_double2(w * a.x, w * a.y);
+        if (accumulate) {
+            const double2 l = ld(lam, i);
+            o.x += l.x;
+            o.y += l.y;
+        }
+        st(lam, i, o);
+    }
+}
+
+// lam_i += f(j) psi_j, lam_j += f(i) psi_i for the pairs of mask x.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_hpsi_pair(const R* __restrict__ psi, R* __restrict__ lam,
+                                                      uint64_t npairs, uint64_t x, uint64_t lowmask,
+                                                      const TermChunk t)
+{
+    const uint64_t step = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < npairs; g += step) {
+        const uint64_t i = ((g & ~lowmask) << 1) | (g & lowmask);
+        const uint64_t j = i ^ x;
+        const double2 a = ld(psi, i), b = ld(psi, j);
+        const double2 fi = phase_sum(i, t), fj = phase_sum(j, t);
+        double2 li = ld(lam, i), lj = ld(lam, j);
+        li.x += fj.x * b.x - fj.y * b.y;
+        li.y += fj.x * b.y + fj.y * b.x;
+        lj.x += fi.x * a.x - fi.y * a.y;
+        lj.y += fi.x * a.y + fi.y * a.x;
+        st(lam, i, li);
+        st(lam, j, lj);
+    }
+}
+
+__global__ void k_fill_zero(double* p, uint64_t count)
+{
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += step)
+        p[i] = 0.0;
+}
+
+inline unsigned stream_grid(uint64_t items)
+{
+    uint64_t b = (items + kBlock * 4 - 1) / (kBlock * 4);
+    if (b < 1)
+        b = 1;
+    if (b > (1u << 20))
+        b = 1u << 20;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_norm2(const void* psi, int n, int dt, double* partials, int accumulate,
+                        hipStream_t s)
+{
+    const int nb = reduce_blocks(n, dt);
+    const uint64_t N = 1ull << n;
+    if (dt == C64)
+        hipLaunchKernelGGL(k_norm2<float>, dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const float*>(psi), N, partials, accumulate);
+    else
+        hipLaunchKernelGGL(k_norm2<double>, dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const double*>(psi), N, partials, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_expect_diag(const void* psi, int n, int dt, const TermChunk& t, double* partials,
+                              int accumulate, hipStream_t s)
+{
+    const int nb = reduce_blocks(n, dt);
+    const uint64_t N = 1ull << n;
+    if (dt == C64)
+        hipLaunchKernelGGL(k_expect_diag<float>, dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const float*>(psi), N, t, partials, accumulate);
+    else
+        hipLaunchKernelGGL(k_expect_diag<double>, dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const double*>(psi), N, t, partials, accumulate);
+    return hipGetLastError();
+}
+
+static uint64_t top_low_mask(uint64_t x)
+{
+    int h = 63;
+    while (h > 0 && !((x >> h) & 1ull))
+        --h;
+    return (1ull << h) - 1;
+}
+
+hipError_t launch_expect_pair(const void* psi, int n, int dt, uint64_t x, const TermChunk& t,
+                              double* partials, int accumulate, hipStream_t s)
+{
+    const int nb = reduce_blocks(n, dt);
+    const uint64_t np = 1ull << (n - 1);
+    const uint64_t lm = top_low_mask(x);
+    if (dt == C64)
+        hipLaunchKernelGGL(k_expect_pair<float>, dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const float*>(psi), np, x, lm, t, partials, accumulate);
+    else
+        hipLaunchKernelGGL(k_expect_pair<double>, dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const double*>(psi), np, x, lm, t, partials, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_inner(const void* a, const void* b, int n, int dt, double* partials2,
+                        int accumulate, hipStream_t s)
+{
+    const int nb = reduce_blocks(n, dt);
+    const uint64_t N = 1ull << n;
+    if (dt == C64)
+        hipLaunchKernelGGL(k_inner<float>, dim3(nb), dim3(kBlock), 0, s, static_cast<const float*>(a),
+                           static_cast<const float*>(b), N, partials2, accumulate);
+    else
+        hipLaunchKernelGGL(k_inner<double>, dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const double*>(a), static_cast<const double*>(b), N,
+                           partials2, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* partials, int nblocks, int ncomp, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partials, nblocks, ncomp, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hpsi_diag(const void* psi, void* lam, int n, int dt, const TermChunk& t,
+                            int accumulate, hipStream_t s)
+{
+    const uint64_t N = 1ull << n;
+    if (dt == C64)
+        hipLaunchKernelGGL(k_hpsi_diag<float>, dim3(stream_grid(N)), dim3(kBlock), 0, s,
+                           static_cast<const float*>(psi), static_cast<float*>(lam), N, t, accumulate);
+    else
+        hipLaunchKernelGGL(k_hpsi_diag<double>, dim3(stream_grid(N)), dim3(kBlock), 0, s,
+                           static_cast<const double*>(psi), static_cast<double*>(lam), N, t,
+                           accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_hpsi_pair(const void* psi, void* lam, int n, int dt, uint64_t x,
+                            const TermChunk& t, hipStream_t s)
+{
+    const uint64_t np = 1ull << (n - 1);
+    const uint64_t lm = top_low_mask(x);
+    if (dt == C64)
+        hipLaunchKernelGGL(k_hpsi_pair<float>, dim3(stream_grid(np)), dim3(kBlock), 0, s,
+                           static_cast<const float*>(psi), static_cast<float*>(lam), np, x, lm, t);
+    else
+        hipLaunchKernelGGL(k_hpsi_pair<double>, dim3(stream_grid(np)), dim3(kBlock), 0, s,
+                           static_cast<const double*>(psi), static_cast<double*>(lam), np, x, lm, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double* p, uint64_t count, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_fill_zero, dim3(stream_grid(count)), dim3(kBlock), 0, s, p, count);
+    return hipGetLastError();
+}
+
+}  // namespace qsv

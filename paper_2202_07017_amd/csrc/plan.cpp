@@ -1,0 +1,755 @@
+// Circuits: the fusion planner, plans (launch lists replayed through HIP
+// graphs) and the adjoint-gradient driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <set>
+#include <vector>
+
+#include "qsv.h"
+#include "qsv_host.h"
+#include "qsv_internal.h"
+
+using namespace qsv;
+
+namespace qsv {
+
+// ------------------------------------------------------------ op matrices
+
+// Matrix of a non-rotation kind, or of a rotation at angle theta (2x2 or 4x4,
+// row-major complex128, user target order).
+std::vector<double> op_matrix(const qsv_op& op, double theta)
+{
+    const double r2 = 1.0 / std::sqrt(2.0);
+    const double c = std::cos(0.5 * theta), s = std::sin(0.5 * theta);
+    switch (op.kind) {
+    case QSV_OP_H: return {r2, 0, r2, 0, r2, 0, -r2, 0};
+    case QSV_OP_X: return {0, 0, 1, 0, 1, 0, 0, 0};
+    case QSV_OP_Y: return {0, 0, 0, -1, 0, 1, 0, 0};
+    case QSV_OP_Z: return {1, 0, 0, 0, 0, 0, -1, 0};
+    case QSV_OP_RX: return {c, 0, 0, -s, 0, -s, c, 0};
+    case QSV_OP_RY: return {c, 0, -s, 0, s, 0, c, 0};
+    case QSV_OP_RZ: return {c, -s, 0, 0, 0, 0, c, s};
+    case QSV_OP_SWAP: {
+        std::vector<double> m(32, 0.0);
+        m[0] = 1;                 // |00> -> |00>
+        m[(1 * 4 + 2) * 2] = 1;   // row 1 <- col 2
+        m[(2 * 4 + 1) * 2] = 1;   // row 2 <- col 1
+        m[(3 * 4 + 3) * 2] = 1;
+        return m;
+    }
+    default: {
+        const int D = 1 << op.k;
+        return std::vector<double>(op.M, op.M + (size_t)2 * D * D);
+    }
+    }
+}
+
+static bool is_rotation(int kind)
+{
+    return kind == QSV_OP_RX || kind == QSV_OP_RY || kind == QSV_OP_RZ;
+}
+
+qsv_status check_circuit(const qsv_circuit* C, int max_n)
+{
+    if (!C || (C->nops > 0 && !C->ops) || C->nops < 0)
+        return fail(QSV_ERR_ARG, "circuit is NULL or has a NULL op list");
+    if (C->n < 1 || C->n > max_n)
+        return fail(QSV_ERR_ARG, "circuit n = %d outside [1, %d]", C->n, max_n);
+    if (C->nparams < 0)
+        return fail(QSV_ERR_ARG, "negative nparams");
+    for (int o = 0; o < C->nops; ++o) {
+        const qsv_op& op = C->ops[o];
+        if (op.kind < QSV_OP_MATRIX || op.kind > QSV_OP_SWAP)
+            return fail(QSV_ERR_ARG, "op %d: unknown kind %d", o, op.kind);
+        if (op.c < 0 || op.c > QSV_MAX_CONTROLS)
+            return fail(QSV_ERR_ARG, "op %d: control count %d outside [0, %d]", o, op.c,
+                        QSV_MAX_CONTROLS);
+        const int kneed = op.kind == QSV_OP_SWAP ? 2 : (op.kind == QSV_OP_MATRIX ? -1 : 1);
+        if (kneed > 0 && op.k != kneed)
+            return fail(QSV_ERR_ARG, "op %d: kind %d needs k = %d, got %d", o, op.kind, kneed, op.k);
+        qsv_status st = check_qubits(C->n, op.targets, op.k, QSV_MAX_TARGETS, op.controls, op.c);
+        if (st)
+            return fail(st, "op %d: %s", o, qsv_last_error());
+        if (op.kind == QSV_OP_MATRIX && !op.M)
+            return fail(QSV_ERR_ARG, "op %d: MATRIX op with NULL M", o);
+        if (is_rotation(op.kind) && (op.param < 0 || op.param >= C->nparams))
+            return fail(QSV_ERR_ARG, "op %d: parameter index %d outside [0, %d)", o, op.param,
+                        C->nparams);
+    }
+    return QSV_OK;
+}
+
+// ------------------------------------------------------------ the planner
+
+struct Item {
+    bool rotation = false;     // standalone unbound rotation
+    std::vector<int> ops;      // ops of the block (one op: emitted natively)
+    std::vector<int> qs;       // block qubits (ascending)
+};
+
+// Greedy DAG-aware fusion: each qubit is owned by at most one open block; a
+// gate joins (and merges) the open blocks owning its qubits when the union
+// has <= fuse_k qubits, otherwise those blocks are emitted.  Open blocks have
+// disjoint qubits, so their relative order is free.
+std::vector<Item> fuse_ops(const qsv_circuit* C, int fuse_k, bool rotations_standalone)
+{
+    struct Blk {
+        std::set<int> qs;
+        std::vector<int> ops;
+        bool open = true;
+    };
+    std::vector<Blk> blks;
+    std::vector<int> owner(C->n, -1);
+    std::vector<Item> out;
+    auto emit = [&](int b) {
+        Blk& B = blks[b];
+        if (!B.open)
+            return;
+        B.open = false;
+        for (int q : B.qs)
+            if (owner[q] == b)
+                owner[q] = -1;
+        Item it;
+        it.ops = B.ops;
+        it.qs.assign(B.qs.begin(), B.qs.end());
+        out.push_back(it);
+    };
+    for (int o = 0; o < C->nops; ++o) {
+        const qsv_op& op = C->ops[o];
+        std::vector<int> Q(op.targets, op.targets + op.k);
+        Q.insert(Q.end(), op.controls, op.controls + op.c);
+        std::set<int> owners;
+        for (int q : Q)
+            if (owner[q] >= 0)
+                owners.insert(owner[q]);
+        if (rotations_standalone && is_rotation(op.kind)) {
+            for (int b : owners)
+                emit(b);
+            Item it;
+            it.rotation = true;
+            it.ops = {o};
+            out.push_back(it);
+            continue;
+        }
+        std::set<int> U(Q.begin(), Q.end());
+        for (int b : owners)
+            U.insert(blks[b].qs.begin(), blks[b].qs.end());
+        if ((int)U.size() <= fuse_k) {
+            int tgt;
+            if (owners.empty()) {
+                blks.push_back(Blk{});
+                tgt = (int)blks.size() - 1;
+            } else {
+                tgt = *owners.begin();
+                for (int b : owners)
+                    if (b != tgt) {
+                        blks[tgt].ops.insert(blks[tgt].ops.end(), blks[b].ops.begin(),
+                                             blks[b].ops.end());
+                        blks[b].open = false;
+                    }
+            }
+            blks[tgt].ops.push_back(o);
+            blks[tgt].qs = U;
+            for (int q : U)
+                owner[q] = tgt;
+        } else {
+            for (int b : owners)
+                emit(b);
+            if ((int)Q.size() <= fuse_k) {
+                blks.push_back(Blk{});
+                const int tgt = (int)blks.size() - 1;
+                blks[tgt].ops = {o};
+                blks[tgt].qs = std::set<int>(Q.begin(), Q.end());
+                for (int q : Q)
+                    owner[q] = tgt;
+            } else {
+                Item it;
+                it.ops = {o};
+                out.push_back(it);
+            }
+        }
+    }
+    for (int b = 0; b < (int)blks.size(); ++b)
+        emit(b);
+    return out;
+}
+
+// Matrix of `op` embedded in the block on ascending qubits qs (bit j <-> qs[j]).
+static std::vector<double> embed(const qsv_op& op, const std::vector<double>& G,
+                                 const std::vector<int>& qs)
+{
+    const int m = (int)qs.size(), Dm = 1 << m, k = op.k, D = 1 << k;
+    auto pos = [&](int q) { return (int)(std::find(qs.begin(), qs.end(), q) - qs.begin()); };
+    std::vector<double> E((size_t)2 * Dm * Dm, 0.0);
+    int tp[QSV_MAX_TARGETS], cp[QSV_MAX_CONTROLS];
+    for (int i = 0; i < k; ++i)
+        tp[i] = pos(op.targets[i]);
+    for (int i = 0; i < op.c; ++i)
+        cp[i] = pos(op.controls[i]);
+    for (int b = 0; b < Dm; ++b) {
+        bool on = true;
+        for (int i = 0; i < op.c; ++i)
+            on = on && ((b >> cp[i]) & 1);
+        if (!on) {
+            E[((size_t)b * Dm + b) * 2] = 1.0;
+            continue;
+        }
+        int tin = 0, cleared = b;
+        for (int i = 0; i < k; ++i) {
+            tin |= ((b >> tp[i]) & 1) << (k - 1 - i);
+            cleared &= ~(1 << tp[i]);
+        }
+        for (int tau = 0; tau < D; ++tau) {
+            int r = cleared;
+            for (int i = 0; i < k; ++i)
+                r |= ((tau >> (k - 1 - i)) & 1) << tp[i];
+            E[((size_t)r * Dm + b) * 2] = G[((size_t)tau * D + tin) * 2];
+            E[((size_t)r * Dm + b) * 2 + 1] = G[((size_t)tau * D + tin) * 2 + 1];
+        }
+    }
+    return E;
+}
+
+static std::vector<double> matmul(const std::vector<double>& A, const std::vector<double>& B, int D)
+{
+    std::vector<double> C((size_t)2 * D * D, 0.0);
+    for (int i = 0; i < D; ++i)
+        for (int k = 0; k < D; ++k) {
+            const double ar = A[((size_t)i * D + k) * 2], ai = A[((size_t)i * D + k) * 2 + 1];
+            if (ar == 0.0 && ai == 0.0)
+                continue;
+            for (int j = 0; j < D; ++j) {
+                const double br = B[((size_t)k * D + j) * 2], bi = B[((size_t)k * D + j) * 2 + 1];
+                C[((size_t)i * D + j) * 2] += ar * br - ai * bi;
+                C[((size_t)i * D + j) * 2 + 1] += ar * bi + ai * br;
+            }
+        }
+    return C;
+}
+
+static std::vector<double> dagger(const std::vector<double>& A, int D)
+{
+    std::vector<double> B(A.size());
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            B[((size_t)i * D + j) * 2] = A[((size_t)j * D + i) * 2];
+            B[((size_t)i * D + j) * 2 + 1] = -A[((size_t)j * D + i) * 2 + 1];
+        }
+    return B;
+}
+
+static bool is_unitary(const std::vector<double>& A, int D)
+{
+    std::vector<double> P = matmul(A, dagger(A, D), D);
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            const double re = P[((size_t)i * D + j) * 2] - (i == j ? 1.0 : 0.0);
+            const double im = P[((size_t)i * D + j) * 2 + 1];
+            if (std::fabs(re) > 1e-9 || std::fabs(im) > 1e-9)
+                return false;
+        }
+    return true;
+}
+
+// Launch for an item (block or native op) with host-known matrices.
+// dag: build the launch for the conjugate transpose.
+static Built item_launch(const qsv_circuit* C, const Item& it, int dt, const double* params_host,
+                         bool dag)
+{
+    auto theta = [&](const qsv_op& op) {
+        return is_rotation(op.kind) && params_host ? params_host[op.param] : 0.0;
+    };
+    if (it.ops.size() == 1) {
+        const qsv_op& op = C->ops[it.ops[0]];
+        std::vector<double> G = op_matrix(op, theta(op));
+        if (dag)
+            G = dagger(G, 1 << op.k);
+        int ct[QSV_MAX_TARGETS];
+        std::vector<double> Gc;
+        canonicalize(op.targets, op.k, G.data(), ct, Gc);
+        return build_launch(C->n, dt, ct, op.k, op.controls, op.c, Gc.data(), true);
+    }
+    const int m = (int)it.qs.size(), Dm = 1 << m;
+    std::vector<double> M((size_t)2 * Dm * Dm, 0.0);
+    for (int i = 0; i < Dm; ++i)
+        M[((size_t)i * Dm + i) * 2] = 1.0;
+    for (int o : it.ops) {
+        const qsv_op& op = C->ops[o];
+        M = matmul(embed(op, op_matrix(op, theta(op)), it.qs), M, Dm);
+    }
+    if (dag)
+        M = dagger(M, Dm);
+    return build_launch(C->n, dt, it.qs.data(), m, nullptr, 0, M.data(), true);
+}
+
+// --------------------------------------------------------- graph caching
+
+struct GraphCache {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> key;
+    ~GraphCache() { reset(); }
+    void reset()
+    {
+        if (exec)
+            hipGraphExecDestroy(exec);
+        if (graph)
+            hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        key.clear();
+    }
+};
+
+static bool graphs_enabled()
+{
+    const char* e = getenv("QSV_NO_GRAPH");
+    return !(e && e[0] == '1');
+}
+
+// Run `enqueue` directly, or through a cached graph keyed by `key`.
+template <typename F>
+static qsv_status run_graph(GraphCache& gc, const std::vector<const void*>& key, hipStream_t s,
+                            F enqueue)
+{
+    if (!graphs_enabled())
+        return enqueue(s);
+    if (!gc.exec || gc.key != key) {
+        gc.reset();
+        hipStream_t cs;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "capture stream: %s", hipGetErrorString(e));
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            hipStreamDestroy(cs);
+            return fail(QSV_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
+        }
+        qsv_status st = enqueue(cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        hipStreamDestroy(cs);
+        if (st) {
+            if (g)
+                hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "end capture: %s", hipGetErrorString(e));
+        gc.graph = g;
+        e = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            gc.reset();
+            return fail(QSV_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        gc.key = key;
+    }
+    hipError_t e = hipGraphLaunch(gc.exec, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+    return QSV_OK;
+}
+
+// Device memory owned by a plan: all uploads packed at 256-byte offsets.
+struct DevPack {
+    void* mem = nullptr;
+    size_t bytes = 0;
+    std::vector<std::pair<size_t, std::vector<unsigned char>>> pending;
+    size_t add(std::vector<unsigned char> data)
+    {
+        const size_t off = (bytes + 255) & ~size_t(255);
+        bytes = off + data.size();
+        pending.push_back({off, std::move(data)});
+        return off;
+    }
+    qsv_status commit()
+    {
+        if (bytes == 0)
+            return QSV_OK;
+        if (hipMalloc(&mem, bytes) != hipSuccess)
+            return fail(QSV_ERR_NOMEM, "plan device allocation of %zu bytes failed", bytes);
+        std::vector<unsigned char> host(bytes, 0);
+        for (auto& p : pending)
+            std::memcpy(host.data() + p.first, p.second.data(), p.second.size());
+        hipError_t e = hipMemcpy(mem, host.data(), bytes, hipMemcpyHostToDevice);
+        pending.clear();
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "plan upload: %s", hipGetErrorString(e));
+        return QSV_OK;
+    }
+    const void* at(size_t off) const { return static_cast<const char*>(mem) + off; }
+    ~DevPack()
+    {
+        if (mem)
+            hipFree(mem);
+    }
+};
+
+}  // namespace qsv
+
+// ================================================================= plans
+
+struct qsv_plan {
+    int n = 0, dt = 0, nparams = 0;
+    std::vector<GateLaunch> launches;
+    std::vector<long long> upload_off;
+    DevPack dev;
+    GraphCache graph;
+    double bytes = 0, flops = 0;
+};
+
+struct AdjItem {
+    bool rotation;
+    int slot;
+    GateLaunch L;
+    long long uoff;
+};
+
+struct qsv_adjoint_plan {
+    int n = 0, dt = 0, nparams = 0, nslots = 0, nb = 0;
+    std::vector<GateLaunch> fwd;
+    std::vector<long long> fwd_off;
+    std::vector<AdjItem> rev;
+    std::vector<uint64_t> hx, hz;
+    std::vector<double> hc;
+    qsv_pauli_sum H{};
+    DevPack dev;
+    size_t off_csr = 0;
+    size_t off_lam = 0, off_part = 0, off_red = 0, work_bytes = 0;
+    GraphCache graph;
+    GraphCache egraph;
+};
+
+namespace {
+
+qsv_status build_plan(const qsv_circuit* circ, int dt, int fuse_k, const double* params_host,
+                      qsv_plan* P)
+{
+    P->n = circ->n;
+    P->dt = dt;
+    P->nparams = circ->nparams;
+    std::vector<Item> items = fuse_ops(circ, fuse_k, params_host == nullptr);
+    for (const Item& it : items) {
+        if (it.rotation) {
+            const qsv_op& op = circ->ops[it.ops[0]];
+            GateLaunch L = rotation_launch(circ->n, dt, op.kind, op.targets[0], op.controls, op.c,
+                                           op.param);
+            P->bytes += L.bytes;
+            P->flops += L.flops;
+            P->launches.push_back(L);
+            P->upload_off.push_back(-1);
+            continue;
+        }
+        Built b = item_launch(circ, it, dt, params_host, false);
+        if (b.noop)
+            continue;
+        P->bytes += b.L.bytes;
+        P->flops += b.L.flops;
+        P->upload_off.push_back(b.upload.empty() ? -1 : (long long)P->dev.add(std::move(b.upload)));
+        P->launches.push_back(b.L);
+    }
+    qsv_status st = P->dev.commit();
+    if (st)
+        return st;
+    for (size_t j = 0; j < P->launches.size(); ++j)
+        if (P->upload_off[j] >= 0)
+            P->launches[j].gdev = P->dev.at((size_t)P->upload_off[j]);
+    return QSV_OK;
+}
+
+qsv_status enqueue_launches(const std::vector<GateLaunch>& Ls, void* psi, const double* params,
+                            hipStream_t s)
+{
+    for (const GateLaunch& L0 : Ls) {
+        if (L0.rot != ROT_NONE) {
+            GateLaunch L = L0;
+            L.params = params;
+            qsv_status st = launch_checked(L, psi, nullptr, s);
+            if (st)
+                return st;
+        } else {
+            qsv_status st = launch_checked(L0, psi, nullptr, s);
+            if (st)
+                return st;
+        }
+    }
+    return QSV_OK;
+}
+
+bool has_rotation(const std::vector<GateLaunch>& Ls)
+{
+    for (const GateLaunch& L : Ls)
+        if (L.rot != ROT_NONE)
+            return true;
+    return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsv_status qsv_plan_create(const qsv_circuit* circ, qsv_dtype dt, int fuse_k,
+                           const double* params_host, qsv_plan** plan)
+{
+    qsv_status st = check_circuit(circ, QSV_MAX_QUBITS);
+    if (st)
+        return st;
+    if ((st = check_n_dt(circ->n, dt)))
+        return st;
+    if (fuse_k < 1 || fuse_k > QSV_MAX_TARGETS)
+        return fail(QSV_ERR_ARG, "fuse_k = %d outside [1, %d]", fuse_k, QSV_MAX_TARGETS);
+    if (!plan)
+        return fail(QSV_ERR_ARG, "plan is NULL");
+    std::unique_ptr<qsv_plan> P(new qsv_plan);
+    if ((st = build_plan(circ, dt, fuse_k, params_host, P.get())))
+        return st;
+    *plan = P.release();
+    return ok();
+}
+
+qsv_status qsv_plan_run(qsv_plan* plan, void* psi, const double* params_dev, void* stream)
+{
+    if (!plan)
+        return fail(QSV_ERR_ARG, "plan is NULL");
+    qsv_status st = check_state(psi, plan->n, plan->dt, "psi");
+    if (st)
+        return st;
+    if (has_rotation(plan->launches) && !params_dev)
+        return fail(QSV_ERR_ARG, "plan has unbound rotations but params_dev is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<const void*> key = {psi, params_dev};
+    if ((st = run_graph(plan->graph, key, s, [&](hipStream_t cs) {
+             return enqueue_launches(plan->launches, psi, params_dev, cs);
+         })))
+        return st;
+    return ok();
+}
+
+qsv_status qsv_plan_info(const qsv_plan* plan, int* nlaunches, double* bytes, double* flops)
+{
+    if (!plan)
+        return fail(QSV_ERR_ARG, "plan is NULL");
+    if (nlaunches)
+        *nlaunches = (int)plan->launches.size();
+    if (bytes)
+        *bytes = plan->bytes;
+    if (flops)
+        *flops = plan->flops;
+    return ok();
+}
+
+qsv_status qsv_plan_destroy(qsv_plan* plan)
+{
+    delete plan;
+    return ok();
+}
+
+// --------------------------------------------------------------- adjoint
+
+qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum* H, qsv_dtype dt,
+                                   int fuse_k, qsv_adjoint_plan** plan, size_t* work_bytes)
+{
+    qsv_status st = check_circuit(circ, QSV_MAX_QUBITS);
+    if (st)
+        return st;
+    if ((st = check_n_dt(circ->n, dt)))
+        return st;
+    if ((st = check_hamiltonian(H, circ->n)))
+        return st;
+    if (fuse_k < 1 || fuse_k > QSV_MAX_TARGETS)
+        return fail(QSV_ERR_ARG, "fuse_k = %d outside [1, %d]", fuse_k, QSV_MAX_TARGETS);
+    if (!plan || !work_bytes)
+        return fail(QSV_ERR_ARG, "plan or work_bytes is NULL");
+    const int n = circ->n;
+    std::unique_ptr<qsv_adjoint_plan> P(new qsv_adjoint_plan);
+    P->n = n;
+    P->dt = dt;
+    P->nparams = circ->nparams;
+    P->nb = reduce_blocks(n, dt);
+    P->hx.assign(H->x_mask, H->x_mask + H->nterms);
+    P->hz.assign(H->z_mask, H->z_mask + H->nterms);
+    P->hc.assign(H->coeff, H->coeff + H->nterms);
+    P->H = qsv_pauli_sum{H->nterms, P->hx.data(), P->hz.data(), P->hc.data()};
+
+    std::vector<Item> items = fuse_ops(circ, fuse_k, true);
+    std::vector<std::vector<int>> slots_of(circ->nparams);
+    std::vector<long long> rev_off;
+    for (const Item& it : items) {
+        if (it.rotation) {
+            const qsv_op& op = circ->ops[it.ops[0]];
+            GateLaunch L = rotation_launch(n, dt, op.kind, op.targets[0], op.controls, op.c, op.param);
+            P->fwd.push_back(L);
+            P->fwd_off.push_back(-1);
+            const int slot = P->nslots++;
+            slots_of[op.param].push_back(slot);
+            P->rev.push_back(AdjItem{true, slot, L, -1});
+            continue;
+        }
+        for (int o : it.ops) {
+            const qsv_op& op = circ->ops[o];
+            const int D = 1 << op.k;
+            if (op.kind == QSV_OP_MATRIX && !is_unitary(op_matrix(op, 0.0), D))
+                return fail(QSV_ERR_ARG, "op %d: MATRIX is not unitary (the adjoint uncomputes with "
+                                         "G^dagger)", o);
+        }
+        Built f = item_launch(circ, it, dt, nullptr, false);
+        if (f.noop)
+            continue;
+        P->fwd_off.push_back(f.upload.empty() ? -1 : (long long)P->dev.add(std::move(f.upload)));
+        P->fwd.push_back(f.L);
+        Built r = item_launch(circ, it, dt, nullptr, true);
+        const long long ro = r.upload.empty() ? -1 : (long long)P->dev.add(std::move(r.upload));
+        P->rev.push_back(AdjItem{false, -1, r.L, ro});
+    }
+    std::reverse(P->rev.begin(), P->rev.end());
+    // CSR of slots per parameter
+    std::vector<int> csr(circ->nparams + 1 + P->nslots + 1, 0);
+    int fill = 0;
+    for (int p = 0; p < circ->nparams; ++p) {
+        csr[p] = fill;
+        for (int sl : slots_of[p])
+            csr[circ->nparams + 1 + fill++] = sl;
+    }
+    csr[circ->nparams] = fill;
+    std::vector<unsigned char> cbytes(csr.size() * sizeof(int));
+    std::memcpy(cbytes.data(), csr.data(), cbytes.size());
+    P->off_csr = P->dev.add(std::move(cbytes));
+    if ((st = P->dev.commit()))
+        return st;
+    for (size_t j = 0; j < P->fwd.size(); ++j)
+        if (P->fwd_off[j] >= 0)
+            P->fwd[j].gdev = P->dev.at((size_t)P->fwd_off[j]);
+    for (AdjItem& a : P->rev)
+        if (a.uoff >= 0)
+            a.L.gdev = P->dev.at((size_t)a.uoff);
+    const size_t sb = amp_bytes(dt) << n;
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    P->off_lam = up(sb);
+    P->off_part = P->off_lam + up(sb);
+    P->off_red = P->off_part + up(sizeof(double) * (size_t)(P->nslots > 0 ? P->nslots : 1) * P->nb);
+    P->work_bytes = P->off_red + kReduceWorkBytes;
+    *work_bytes = P->work_bytes;
+    *plan = P.release();
+    return ok();
+}
+
+static qsv_status adjoint_enqueue(qsv_adjoint_plan* P, const double* params, void* work,
+                                  double* energy, double* grad, bool with_grad, hipStream_t s)
+{
+    char* w = static_cast<char*>(work);
+    void* psi = w;
+    void* lam = w + P->off_lam;
+    double* part = reinterpret_cast<double*>(w + P->off_part);
+    double* red = reinterpret_cast<double*>(w + P->off_red);
+    hipError_t e = launch_init_basis(psi, P->n, P->dt, 0, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "init launch: %s", hipGetErrorString(e));
+    qsv_status st = enqueue_launches(P->fwd, psi, params, s);
+    if (st)
+        return st;
+    if (!with_grad)
+        return enqueue_expectation(psi, P->n, P->dt, &P->H, energy, red, 1, s);
+    if ((st = enqueue_hpsi(psi, lam, P->n, P->dt, &P->H, s)))
+        return st;
+    e = launch_inner(psi, lam, P->n, P->dt, red, 0, s);
+    if (e == hipSuccess)
+        e = launch_finalize(red, P->nb, 1, energy, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "energy launch: %s", hipGetErrorString(e));
+    for (const AdjItem& a : P->rev) {
+        if (a.rotation) {
+            GateLaunch L = a.L;
+            L.params = params;
+            e = launch_adj_step(L, psi, lam, part + (size_t)a.slot * P->nb, P->nb, s);
+            if (e != hipSuccess)
+                return fail(QSV_ERR_HIP, "adjoint step launch: %s", hipGetErrorString(e));
+        } else if ((st = launch_checked(a.L, psi, lam, s))) {
+            return st;
+        }
+    }
+    const int* csr = static_cast<const int*>(P->dev.at(P->off_csr));
+    e = launch_grad_finalize(part, P->nb, csr, csr + P->nparams + 1, P->nparams, grad, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "gradient finalize launch: %s", hipGetErrorString(e));
+    return QSV_OK;
+}
+
+qsv_status qsv_adjoint_run(qsv_adjoint_plan* plan, const double* params_dev, void* work,
+                           double* energy_dev, double* grad_dev, void* stream)
+{
+    if (!plan)
+        return fail(QSV_ERR_ARG, "plan is NULL");
+    if (!work || !energy_dev || (plan->nparams > 0 && (!grad_dev || !params_dev)))
+        return fail(QSV_ERR_ARG, "NULL work, energy, gradient or parameter pointer");
+    if (reinterpret_cast<uintptr_t>(work) % 256)
+        return fail(QSV_ERR_ARG, "work is not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<const void*> key = {params_dev, work, energy_dev, grad_dev};
+    qsv_status st = run_graph(plan->graph, key, s, [&](hipStream_t cs) {
+        return adjoint_enqueue(plan, params_dev, work, energy_dev, grad_dev, true, cs);
+    });
+    if (st)
+        return st;
+    return ok();
+}
+
+qsv_status qsv_adjoint_energy(qsv_adjoint_plan* plan, const double* params_dev, void* work,
+                              double* energy_dev, void* stream)
+{
+    if (!plan)
+        return fail(QSV_ERR_ARG, "plan is NULL");
+    if (!work || !energy_dev || (plan->nparams > 0 && !params_dev))
+        return fail(QSV_ERR_ARG, "NULL work, energy or parameter pointer");
+    if (reinterpret_cast<uintptr_t>(work) % 256)
+        return fail(QSV_ERR_ARG, "work is not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<const void*> key = {params_dev, work, energy_dev};
+    qsv_status st = run_graph(plan->egraph, key, s, [&](hipStream_t cs) {
+        return adjoint_enqueue(plan, params_dev, work, energy_dev, nullptr, false, cs);
+    });
+    if (st)
+        return st;
+    return ok();
+}
+
+qsv_status qsv_adjoint_state(const qsv_adjoint_plan* plan, void* work, int slot, void** psi)
+{
+    if (!plan || !work || !psi || slot < 0 || slot > 1)
+        return fail(QSV_ERR_ARG, "bad argument");
+    *psi = static_cast<char*>(work) + (slot ? plan->off_lam : 0);
+    return ok();
+}
+
+qsv_status qsv_adjoint_plan_destroy(qsv_adjoint_plan* plan)
+{
+    delete plan;
+    return ok();
+}
+
+qsv_status qsv_adjoint_gradient(const qsv_circuit* circ, const double* params_dev,
+                                const qsv_pauli_sum* H, qsv_dtype dt, void* work,
+                                double* energy_dev, double* grad_dev, void* stream)
+{
+    qsv_adjoint_plan* P = nullptr;
+    size_t wb = 0;
+    qsv_status st = qsv_adjoint_plan_create(circ, H, dt, 5, &P, &wb);
+    if (st)
+        return st;
+    if (!work || !energy_dev || (P->nparams > 0 && (!grad_dev || !params_dev))) {
+        delete P;
+        return fail(QSV_ERR_ARG, "NULL work, energy, gradient or parameter pointer");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    st = adjoint_enqueue(P, params_dev, work, energy_dev, grad_dev, true, s);
+    hipStreamSynchronize(s);
+    delete P;
+    if (st)
+        return st;
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Internal declarations shared by the HIP kernel files and the host API of
+// libqsv.so.  Not part of the public ABI (that is include/qsv.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace qsv {
+
+constexpr int kMaxIns = 40;      // inserted (fixed) bit positions per launch
+constexpr int kBlock = 256;      // threads per block for streaming kernels
+constexpr int kMaxTermsPerLaunch = 32;
+
+enum Dt : int { C64 = 1, C128 = 2 };
+
+// How a thread reads the amplitudes of one group (c64 only uses W2/INTRA):
+//  W1    - one amplitude per load (float2 / double2);
+//  W2    - c64, qubit 0 untouched by the gate: a float4 holds amplitudes 2u,
+//          2u+1, which belong to two different groups with the same tau;
+//  INTRA - c64, qubit 0 is the lowest target: a float4 holds tau' = 2v, 2v+1
+//          of the same group.
+enum Mode : int { W1 = 0, W2 = 1, INTRA = 2 };
+
+enum LaunchType : int { L_DENSE = 0, L_DIAG = 1, L_PERM = 2, L_MFMA = 3 };
+
+// Rotation kinds read from a device parameter vector (values follow qsv_op_kind).
+enum Rot : int { ROT_NONE = 0, ROT_X = 5, ROT_Y = 6, ROT_Z = 7 };
+
+// Insert zero bits at ascending positions p (low[j] = 2^p - 1) into a group
+// index, then OR in `setmask` (controls = 1).  All positions are in "unit"
+// index space (amplitude index >> 1 for W2/INTRA).
+struct InsertSpec {
+    int nins;
+    uint64_t setmask;
+    uint64_t low[kMaxIns];
+};
+
+// A host-side description of one kernel launch on one (or two) states.
+struct GateLaunch {
+    int type = L_DENSE;
+    int dt = C128;
+    int n = 0;
+    int K = 0;          // dense: #targets; diag: #varying targets; mfma: K; perm: unused
+    int mode = W1;
+    uint64_t ngroups = 0;
+    InsertSpec ins{};
+    uint64_t off[32] = {};   // dense: unit offset per tau' (INTRA: per tau'>>1); perm: dst
+    uint64_t off2[32] = {};  // perm: src
+    int nmoved = 0;
+    int tpos[5] = {};        // diag: amplitude-space positions of varying targets (tau bit j)
+    std::vector<double> g;   // dense: canonical matrix (complex128, row-major); diag: d[tau]
+    const void* gdev = nullptr; // dense K>=4: matrix in state precision; mfma: A fragments
+    int rot = ROT_NONE;
+    int pidx = -1;
+    int dag = 0;
+    const double* params = nullptr; // device parameter vector (bound at run time)
+    // mfma tile geometry
+    int L = 0;
+    uint64_t ntiles = 0;
+    uint64_t choff[32] = {};
+    int tloc[5] = {};
+    int floc[6] = {};
+    // accounting
+    double bytes = 0.0;
+    double flops = 0.0;
+};
+
+// kernels_gate.hip
+hipError_t launch_gate(const GateLaunch& L, void* psi, void* psi2, hipStream_t s);
+hipError_t launch_init_basis(void* psi, int n, int dt, uint64_t index, hipStream_t s);
+hipError_t launch_init_random(void* psi, int n, int dt, uint64_t seed, double* work, hipStream_t s);
+
+// kernels_mfma.hip
+hipError_t launch_mfma(const GateLaunch& L, void* psi, void* psi2, hipStream_t s);
+// Fill the MFMA A-operand fragments of the real embedding of a canonical
+// k-qubit complex128 matrix, in state precision (host side).
+void mfma_fragments(const double* Gc, int K, int dt, std::vector<unsigned char>& out);
+
+// kernels_reduce.hip
+int reduce_blocks(int n, int dt);
+struct TermChunk {
+    int nt;
+    int ylo[kMaxTermsPerLaunch];          // number of Y factors mod 4
+    uint64_t z[kMaxTermsPerLaunch];
+    double c[kMaxTermsPerLaunch];
+};
+hipError_t launch_norm2(const void* psi, int n, int dt, double* partials, int accumulate, hipStream_t s);
+hipError_t launch_expect_diag(const void* psi, int n, int dt, const TermChunk& t, double* partials,
+                              int accumulate, hipStream_t s);
+hipError_t launch_expect_pair(const void* psi, int n, int dt, uint64_t x, const TermChunk& t,
+                              double* partials, int accumulate, hipStream_t s);
+hipError_t launch_inner(const void* a, const void* b, int n, int dt, double* partials2,
+                        int accumulate, hipStream_t s);
+hipError_t launch_finalize(const double* partials, int nblocks, int ncomp, double* out, hipStream_t s);
+hipError_t launch_hpsi_diag(const void* psi, void* lam, int n, int dt, const TermChunk& t,
+                            int accumulate, hipStream_t s);
+hipError_t launch_hpsi_pair(const void* psi, void* lam, int n, int dt, uint64_t x,
+                            const TermChunk& t, hipStream_t s);
+hipError_t launch_fill_zero(double* p, uint64_t count, hipStream_t s);
+
+// kernels_adjoint.hip
+// One reverse step of the adjoint sweep for the rotation described by L (a
+// dense K=1 launch with rot = ROT_X / ROT_Y, or a diag launch with
+// rot = ROT_Z): partials[b] (b < nb) = block sums of Im <lam|P phi>, then
+// phi and lam are replaced by U^dagger phi and U^dagger lam.
+hipError_t launch_adj_step(const GateLaunch& L, void* phi, void* lam, double* partials, int nb,
+                           hipStream_t s);
+// grad[p] = sum over slots s with slot_param[s] == p (CSR: pstart/plist) of
+// sum_b partials[s * nblocks + b].
+hipError_t launch_grad_finalize(const double* partials, int nblocks, const int* pstart,
+                                const int* plist, int nparams, double* grad, hipStream_t s);
+
+}  // namespace qsv

@@ -1,0 +1,391 @@
+"""ctypes binding of libqsv.so (include/qsv.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libqsv.so.  PyTorch supplies
+device memory (tensors) and streams (torch.cuda.current_stream()).  There is
+no CPU fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsv.so")
+
+C64, C128 = 1, 2
+OK, ERR_ARG, ERR_QUBIT, ERR_UNSUPPORTED, ERR_HIP, ERR_NOMEM = range(6)
+MAX_TARGETS, MAX_CONTROLS, MAX_QUBITS = 5, 4, 40
+KIND = {"matrix": 0, "h": 1, "x": 2, "y": 3, "z": 4, "rx": 5, "ry": 6, "rz": 7, "swap": 8}
+
+_D = ctypes.POINTER(ctypes.c_double)
+_U = ctypes.POINTER(ctypes.c_uint64)
+_I = ctypes.POINTER(ctypes.c_int)
+_vp = ctypes.c_void_p
+
+
+class QsvError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("qsv status %d: %s" % (status, message))
+        self.status = status
+
+
+class qsv_block(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("targets", ctypes.c_int * MAX_TARGETS), ("M", _D)]
+
+
+class qsv_pauli_sum(ctypes.Structure):
+    _fields_ = [("nterms", ctypes.c_int), ("x_mask", _U), ("z_mask", _U), ("coeff", _D)]
+
+
+class qsv_op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("k", ctypes.c_int),
+                ("targets", ctypes.c_int * MAX_TARGETS), ("c", ctypes.c_int),
+                ("controls", ctypes.c_int * MAX_CONTROLS), ("param", ctypes.c_int), ("M", _D)]
+
+
+class qsv_circuit(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("nops", ctypes.c_int), ("ops", ctypes.POINTER(qsv_op)),
+                ("nparams", ctypes.c_int)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+_SIGS = {
+    "qsv_last_error": ([], ctypes.c_char_p),
+    "qsv_version": ([], ctypes.c_char_p),
+    "qsv_state_bytes": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "qsv_state_alloc": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+    "qsv_state_free": ([_vp], ctypes.c_int),
+    "qsv_init_basis": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _vp], ctypes.c_int),
+    "qsv_init_random": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _vp, _vp], ctypes.c_int),
+    "qsv_apply_gate": ([_vp, ctypes.c_int, ctypes.c_int, _I, ctypes.c_int, _I, ctypes.c_int, _D,
+                        _vp], ctypes.c_int),
+    "qsv_apply_fused": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsv_block), ctypes.c_int,
+                         _vp], ctypes.c_int),
+    "qsv_reduce_workspace_bytes": ([ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "qsv_norm2": ([_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
+    "qsv_expectation": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsv_pauli_sum), _vp, _vp,
+                         _vp], ctypes.c_int),
+    "qsv_inner": ([_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
+    "qsv_apply_pauli_sum": ([_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsv_pauli_sum),
+                             _vp], ctypes.c_int),
+    "qsv_plan_create": ([ctypes.POINTER(qsv_circuit), ctypes.c_int, ctypes.c_int, _D,
+                         ctypes.POINTER(_vp)], ctypes.c_int),
+    "qsv_plan_run": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "qsv_plan_info": ([_vp, _I, _D, _D], ctypes.c_int),
+    "qsv_plan_destroy": ([_vp], ctypes.c_int),
+    "qsv_adjoint_plan_create": ([ctypes.POINTER(qsv_circuit), ctypes.POINTER(qsv_pauli_sum),
+                                 ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp),
+                                 ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "qsv_adjoint_run": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "qsv_adjoint_energy": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "qsv_adjoint_state": ([_vp, _vp, ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+    "qsv_adjoint_plan_destroy": ([_vp], ctypes.c_int),
+    "qsv_adjoint_gradient": ([ctypes.POINTER(qsv_circuit), _vp, ctypes.POINTER(qsv_pauli_sum),
+                              ctypes.c_int, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "qsv_batch_plan_create": ([ctypes.POINTER(qsv_circuit), ctypes.POINTER(qsv_pauli_sum),
+                               ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp),
+                               ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "qsv_batch_offsets": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "qsv_batch_run": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "qsv_batch_tune": ([_vp, _vp, _vp, _vp, _vp, _vp, _I], ctypes.c_int),
+    "qsv_batch_plan_destroy": ([_vp], ctypes.c_int),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libqsv.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libqsv.so is missing at %s: run __graft_entry__.build() "
+                                   "(the HIP library is required; there is no fallback)" % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (args, res) in _SIGS.items():
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = res
+            _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        raise QsvError(status, lib().qsv_last_error().decode())
+
+
+def dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.complex64:
+        return C64
+    if t.dtype == torch.complex128:
+        return C128
+    raise TypeError("state tensors must be complex64 or complex128, got %s" % t.dtype)
+
+
+def _nqubits(t) -> int:
+    n = int(t.numel()).bit_length() - 1
+    if t.numel() != (1 << n):
+        raise ValueError("state length %d is not a power of two" % t.numel())
+    return n
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else None
+
+
+def _ints(seq):
+    seq = list(seq)
+    arr = (ctypes.c_int * max(len(seq), 1))(*seq)
+    return arr
+
+
+def _mat(G):
+    G = np.ascontiguousarray(G, dtype=np.complex128)
+    return G, G.view(np.float64).ctypes.data_as(_D)
+
+
+# ---------------------------------------------------------------- states
+
+def state_empty(n: int, dtype, device="cuda"):
+    import torch
+    return torch.empty(1 << n, dtype=dtype, device=device)
+
+
+_work_cache = {}
+
+
+def reduce_workspace(device):
+    """A cached device buffer of qsv_reduce_workspace_bytes() bytes."""
+    import torch
+    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
+    w = _work_cache.get(key)
+    if w is None:
+        size = ctypes.c_size_t()
+        _check(lib().qsv_reduce_workspace_bytes(ctypes.byref(size)))
+        w = torch.empty(size.value // 8, dtype=torch.float64, device=device)
+        _work_cache[key] = w
+    return w
+
+
+def qsv_init_basis(psi, index: int = 0, stream=None):
+    _check(lib().qsv_init_basis(_ptr(psi), _nqubits(psi), dtype_code(psi), index, _stream(stream)))
+
+
+def qsv_init_random(psi, seed: int, stream=None):
+    work = reduce_workspace(psi.device)
+    _check(lib().qsv_init_random(_ptr(psi), _nqubits(psi), dtype_code(psi), seed, _ptr(work),
+                                 _stream(stream)))
+
+
+def qsv_apply_gate(psi, targets: Sequence[int], controls: Sequence[int], G, stream=None):
+    t, c = _ints(targets), _ints(controls)
+    _G, gp = _mat(G)
+    _check(lib().qsv_apply_gate(_ptr(psi), _nqubits(psi), dtype_code(psi), t, len(targets), c,
+                                len(controls), gp, _stream(stream)))
+
+
+def qsv_apply_fused(psi, blocks, stream=None):
+    """blocks: sequence of (targets, matrix)."""
+    arr = (qsv_block * max(len(blocks), 1))()
+    keep = []
+    for j, (targets, M) in enumerate(blocks):
+        Mc, mp = _mat(M)
+        keep.append(Mc)
+        arr[j].k = len(targets)
+        for i, q in enumerate(targets):
+            arr[j].targets[i] = q
+        arr[j].M = mp
+    _check(lib().qsv_apply_fused(_ptr(psi), _nqubits(psi), dtype_code(psi), arr, len(blocks),
+                                 _stream(stream)))
+
+
+class PauliSum:
+    """ctypes view of a Pauli sum (x_mask, z_mask, coeff arrays kept alive)."""
+
+    def __init__(self, H):
+        self.x = np.ascontiguousarray(H.x_mask, dtype=np.uint64)
+        self.z = np.ascontiguousarray(H.z_mask, dtype=np.uint64)
+        self.c = np.ascontiguousarray(H.coeff, dtype=np.float64)
+        self.s = qsv_pauli_sum(len(self.c), self.x.ctypes.data_as(_U), self.z.ctypes.data_as(_U),
+                               self.c.ctypes.data_as(_D))
+
+
+def qsv_norm2(psi, out=None, stream=None):
+    import torch
+    out = out if out is not None else torch.empty(1, dtype=torch.float64, device=psi.device)
+    _check(lib().qsv_norm2(_ptr(psi), _nqubits(psi), dtype_code(psi), _ptr(out),
+                           _ptr(reduce_workspace(psi.device)), _stream(stream)))
+    return out
+
+
+def qsv_expectation(psi, H, out=None, stream=None):
+    import torch
+    P = H if isinstance(H, PauliSum) else PauliSum(H)
+    out = out if out is not None else torch.empty(2, dtype=torch.float64, device=psi.device)
+    _check(lib().qsv_expectation(_ptr(psi), _nqubits(psi), dtype_code(psi), ctypes.byref(P.s),
+                                 _ptr(out), _ptr(reduce_workspace(psi.device)), _stream(stream)))
+    return out
+
+
+def qsv_inner(a, b, out=None, stream=None):
+    import torch
+    out = out if out is not None else torch.empty(2, dtype=torch.float64, device=a.device)
+    _check(lib().qsv_inner(_ptr(a), _ptr(b), _nqubits(a), dtype_code(a), _ptr(out),
+                           _ptr(reduce_workspace(a.device)), _stream(stream)))
+    return out
+
+
+def qsv_apply_pauli_sum(psi, out, H, stream=None):
+    P = H if isinstance(H, PauliSum) else PauliSum(H)
+    _check(lib().qsv_apply_pauli_sum(_ptr(psi), _ptr(out), _nqubits(psi), dtype_code(psi),
+                                     ctypes.byref(P.s), _stream(stream)))
+
+
+# -------------------------------------------------------------- circuits
+
+class CircuitC:
+    """ctypes form of a circuit (any object with n, ops, nparams whose ops
+    have kind, targets, controls, param, matrix)."""
+
+    def __init__(self, circ):
+        self.mats = []
+        ops = (qsv_op * max(len(circ.ops), 1))()
+        for j, op in enumerate(circ.ops):
+            o = ops[j]
+            o.kind = KIND[op.kind]
+            o.k = len(op.targets)
+            for i, q in enumerate(op.targets):
+                o.targets[i] = q
+            o.c = len(op.controls)
+            for i, q in enumerate(op.controls):
+                o.controls[i] = q
+            o.param = op.param
+            if op.kind == "matrix":
+                M, mp = _mat(op.matrix)
+                self.mats.append(M)
+                o.M = mp
+        self.ops = ops
+        self.s = qsv_circuit(circ.n, len(circ.ops), ops, circ.nparams)
+        self.n = circ.n
+        self.nparams = circ.nparams
+
+
+class Plan:
+    """qsv_plan: fused launch list, replayed through a HIP graph."""
+
+    def __init__(self, circ, dtype_code_: int, fuse_k: int = 5, params_host=None):
+        self.c = circ if isinstance(circ, CircuitC) else CircuitC(circ)
+        self.h = _vp()
+        ph = None
+        if params_host is not None:
+            self._ph = np.ascontiguousarray(params_host, dtype=np.float64)
+            ph = self._ph.ctypes.data_as(_D)
+        _check(lib().qsv_plan_create(ctypes.byref(self.c.s), dtype_code_, fuse_k, ph,
+                                     ctypes.byref(self.h)))
+
+    def run(self, psi, params_dev=None, stream=None):
+        _check(lib().qsv_plan_run(self.h, _ptr(psi), _ptr(params_dev), _stream(stream)))
+
+    def info(self):
+        n = ctypes.c_int()
+        b = ctypes.c_double()
+        f = ctypes.c_double()
+        _check(lib().qsv_plan_info(self.h, ctypes.byref(n), ctypes.byref(b), ctypes.byref(f)))
+        return n.value, b.value, f.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            _lib.qsv_plan_destroy(self.h)
+
+
+class AdjointPlan:
+    """qsv_adjoint_plan with its device workspace (a torch tensor)."""
+
+    def __init__(self, circ, H, dtype_code_: int, fuse_k: int = 5, device="cuda"):
+        import torch
+        self.c = circ if isinstance(circ, CircuitC) else CircuitC(circ)
+        self.H = H if isinstance(H, PauliSum) else PauliSum(H)
+        self.h = _vp()
+        wb = ctypes.c_size_t()
+        _check(lib().qsv_adjoint_plan_create(ctypes.byref(self.c.s), ctypes.byref(self.H.s),
+                                             dtype_code_, fuse_k, ctypes.byref(self.h),
+                                             ctypes.byref(wb)))
+        self.work_bytes = wb.value
+        self.work = torch.empty((wb.value + 255) // 256 * 32, dtype=torch.float64, device=device)
+        self.nparams = self.c.nparams
+        self.device = device
+
+    def run(self, params_dev, energy=None, grad=None, stream=None):
+        import torch
+        energy = energy if energy is not None else torch.empty(1, dtype=torch.float64,
+                                                               device=self.device)
+        grad = grad if grad is not None else torch.empty(max(self.nparams, 1), dtype=torch.float64,
+                                                         device=self.device)
+        _check(lib().qsv_adjoint_run(self.h, _ptr(params_dev), _ptr(self.work), _ptr(energy),
+                                     _ptr(grad), _stream(stream)))
+        return energy, grad[:self.nparams]
+
+    def energy(self, params_dev, energy=None, stream=None):
+        import torch
+        energy = energy if energy is not None else torch.empty(1, dtype=torch.float64,
+                                                               device=self.device)
+        _check(lib().qsv_adjoint_energy(self.h, _ptr(params_dev), _ptr(self.work), _ptr(energy),
+                                        _stream(stream)))
+        return energy
+
+    def state_ptr(self, slot=0):
+        p = _vp()
+        _check(lib().qsv_adjoint_state(self.h, _ptr(self.work), slot, ctypes.byref(p)))
+        return p.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            _lib.qsv_adjoint_plan_destroy(self.h)
+
+
+def _autograd_function():
+    import torch
+
+    class AdjointEnergy(torch.autograd.Function):
+        """E(theta) = <psi(theta)|H|psi(theta)> with the gradient from the
+        library's adjoint sweep (computed in forward, scaled in backward)."""
+
+        @staticmethod
+        def forward(ctx, params, plan):
+            p = params.detach().to(torch.float64).contiguous()
+            e, g = plan.run(p)
+            ctx.save_for_backward(g.clone())
+            return e[0].clone()
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return grad_out * g, None
+
+    return AdjointEnergy
+
+
+_AE = None
+
+
+def adjoint_energy(params, plan):
+    """Differentiable energy: torch.autograd sees dE/dtheta from the adjoint."""
+    global _AE
+    if _AE is None:
+        _AE = _autograd_function()
+    return _AE.apply(params, plan)

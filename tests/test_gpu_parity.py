@@ -1,0 +1,337 @@
+"""GPU parity of libqsv.so against the CPU oracle, through the C ABI.
+
+Floating point: max |amplitude difference| <= 1e-12 (complex128) and
+<= 1e-5 (complex64) against the complex128 oracle run on the same input
+(for complex64 the input is the complex64 state widened exactly).
+Permutation gates: bit-exact.  Expectation values: |dE| <= 1e-10 sum|c|.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import TOL, rand_state, raw_bits, say, to_gpu, to_np, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = ["c64", "c128"]
+X2 = np.array([[0, 1], [1, 0]], np.complex128)
+Z2 = np.array([[1, 0], [0, -1]], np.complex128)
+SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], np.complex128)
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2202_07017_amd import qsv
+    qsv.lib()
+    return qsv
+
+
+def check_close(got, ref, name, what=""):
+    err = np.max(np.abs(got - ref)) if got.size else 0.0
+    assert err <= TOL[name], "%s %s: max|d| = %.3e" % (what, name, err)
+
+
+def gate_case(q, orc, psi, name, t, c, G):
+    d = to_gpu(psi, name)
+    q.qsv_apply_gate(d, t, c, G)
+    got = to_np(d)
+    ref = orc.apply(psi, t, c, G)
+    check_close(got, ref, name, "t=%s c=%s" % (t, c))
+
+
+def test_init_basis(q):
+    import torch
+    for name in DTYPES:
+        for n in [1, 2, 5, 13]:
+            for index in sorted({0, 1, (1 << n) - 1, (1 << n) // 3}):
+                say("init_basis", name, n, index)
+                d = torch.empty(1 << n, dtype=torch_dtype(name), device="cuda")
+                d.fill_(complex(7, 7))
+                q.qsv_init_basis(d, index)
+                ref = np.zeros(1 << n, d.cpu().numpy().dtype)
+                ref[index] = 1
+                assert np.array_equal(raw_bits(d.cpu().numpy()), raw_bits(ref))
+
+
+def test_init_random(q, orc):
+    import torch
+    for name in DTYPES:
+        for n, seed in [(1, 3), (10, 5), (17, 1001)]:
+            say("init_random", name, n, seed)
+            d = torch.empty(1 << n, dtype=torch_dtype(name), device="cuda")
+            q.qsv_init_random(d, seed)
+            ref = orc.random_state(n, seed)
+            got = to_np(d)
+            rel = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+            assert rel <= (1e-14 if name == "c128" else 1e-7), rel
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7])
+def test_dense_gates_all_placements(q, orc, n):
+    """Every (sampled) ordered placement of k <= 3 targets and c <= 2 controls."""
+    rng = np.random.default_rng(100 + n)
+    for name in DTYPES:
+        psi = rand_state(n, rng, name)
+        for k in range(1, min(n, 3) + 1):
+            for c in range(0, min(n - k, 2) + 1):
+                places = list(itertools.permutations(range(n), k + c))
+                rng.shuffle(places)
+                for qs in places[:24]:
+                    say("dense", name, n, qs[:k], qs[k:])
+                    gate_case(q, orc, psi, name, qs[:k], qs[k:], W.haar_unitary(rng, 2 ** k))
+
+
+def test_permutations_bit_exact(q, orc):
+    rng = np.random.default_rng(5)
+    for name in DTYPES:
+        for n in [1, 2, 3, 6, 9]:
+            psi = rand_state(n, rng, name)
+            psi[min(3, (1 << n) - 1)] = -0.0  # a signed zero must survive
+            cases = [((j,), (), X2) for j in range(n)]
+            if n >= 2:
+                cases += [((1,), (0,), X2), ((0,), (n - 1,), X2), ((0, n - 1), (), SWAP),
+                          ((n - 1, 0), (), SWAP)]
+            if n >= 3:
+                cases += [((2,), (0, 1), X2), ((0,), (1, 2), X2)]
+                P = np.eye(8)[rng.permutation(8)].astype(np.complex128)
+                cases += [((2, 0, 1), (), P), ((n - 1, 1, 0), (), P)]
+            for t, c, G in cases:
+                say("perm", name, n, t, c)
+                d = to_gpu(psi, name)
+                q.qsv_apply_gate(d, t, c, G)
+                ref = orc.apply(psi, t, c, G).astype(np.complex64 if name == "c64" else np.complex128)
+                assert np.array_equal(raw_bits(d.cpu().numpy()), raw_bits(ref)), (name, n, t, c)
+
+
+def test_diagonal_gates(q, orc):
+    rng = np.random.default_rng(6)
+    for name in DTYPES:
+        for n in [1, 2, 5, 9]:
+            psi = rand_state(n, rng, name)
+            cases = [((j,), (), Z2) for j in range(n)]
+            cases += [((j,), (), np.diag(np.exp(1j * rng.uniform(0, 6, 2)))) for j in range(n)]
+            if n >= 2:
+                cases += [((1,), (0,), Z2), ((0,), (n - 1,), np.diag(np.exp([-0.3j, 0.3j]))),
+                          ((0, n - 1), (), np.diag(np.exp(1j * rng.uniform(0, 6, 4)))),
+                          ((n - 1, 0), (), np.diag([1, 1, 1, -1]).astype(np.complex128)),
+                          ((0, 1), (), np.diag([1, 1j, 1, 1]).astype(np.complex128))]
+            if n >= 5:
+                cases += [((4, 0, 2), (1,), np.diag(np.exp(1j * rng.uniform(0, 6, 8))))]
+            for t, c, G in cases:
+                say("diag", name, n, t, c)
+                gate_case(q, orc, psi, name, t, c, G)
+
+
+@pytest.mark.parametrize("n", [10, 11, 12, 14])
+def test_four_and_five_qubit_gates(q, orc, n):
+    """k = 4, 5: matrix cores (uncontrolled, n >= k + 6) and the VALU path."""
+    rng = np.random.default_rng(200 + n)
+    for name in DTYPES:
+        psi = rand_state(n, rng, name)
+        for k in [4, 5]:
+            places = [tuple(range(k)), tuple(range(n - k, n)), tuple(reversed(range(k))),
+                      (0, n - 1, 3, 7, 5)[:k], (1, 2, 9, 6, n - 2)[:k],
+                      tuple(int(v) for v in rng.choice(n, k, replace=False))]
+            for t in places:
+                G = W.haar_unitary(rng, 2 ** k)
+                for mfma in ["1", "0"]:
+                    os.environ["QSV_NO_MFMA"] = "0" if mfma == "1" else "1"
+                    say("k45", name, n, t, "mfma" if mfma == "1" else "valu")
+                    gate_case(q, orc, psi, name, t, (), G)
+                ctl = [v for v in range(n) if v not in t][:1]
+                say("k45 controlled", name, n, t, ctl)
+                gate_case(q, orc, psi, name, t, tuple(ctl), G)
+    os.environ.pop("QSV_NO_MFMA", None)
+
+
+def test_apply_fused(q, orc):
+    rng = np.random.default_rng(8)
+    for name in DTYPES:
+        n = 13
+        psi = rand_state(n, rng, name)
+        blocks = []
+        for k in [1, 2, 3, 4, 5, 5, 4, 2]:
+            t = tuple(int(v) for v in rng.choice(n, k, replace=False))
+            blocks.append((t, W.haar_unitary(rng, 2 ** k)))
+        say("fused", name, [b[0] for b in blocks])
+        d = to_gpu(psi, name)
+        q.qsv_apply_fused(d, blocks)
+        ref = psi
+        for t, G in blocks:
+            ref = orc.apply(ref, t, (), G)
+        check_close(to_np(d), ref, name)
+
+
+def test_observables(q, orc):
+    rng = np.random.default_rng(9)
+    for name in DTYPES:
+        for n in [1, 3, 8, 12]:
+            psi = rand_state(n, rng, name)
+            d = to_gpu(psi, name)
+            Hs = [W.random_pauli_sum(n, 11, seed=n), W.tfim_chain(n, 0.7)]
+            if n >= 2:
+                Hs.append(W.xxz_chain(n, 0.4))
+            for H in Hs:
+                say("expectation", name, n, len(H.coeff))
+                e = q.qsv_expectation(d, H).cpu().numpy()
+                ref = orc.expect(psi, H)
+                scale = np.sum(np.abs(H.coeff))
+                assert abs(e[0] - ref.real) <= 1e-10 * scale, (e, ref)
+                assert abs(e[1]) <= 1e-10 * scale
+                out = to_gpu(np.zeros_like(psi), name)
+                q.qsv_apply_pauli_sum(d, out, H)
+                check_close(to_np(out) / max(scale, 1), orc.apply_hamiltonian(psi, H) / max(scale, 1),
+                            name, "H psi")
+            say("norm/inner", name, n)
+            nrm = q.qsv_norm2(d).cpu().numpy()[0]
+            assert abs(nrm - orc.norm2(psi)) <= 1e-12
+            phi = rand_state(n, rng, name)
+            ip = q.qsv_inner(d, to_gpu(phi, name)).cpu().numpy()
+            ref = orc.inner(psi, phi)
+            assert abs(ip[0] - ref.real) <= 1e-12 and abs(ip[1] - ref.imag) <= 1e-12
+
+
+def test_plan_random_circuit(q, orc):
+    """Random U(2) layers with CZ pairs (n = 20, depth 10): every fusion width
+    and graph replay against the oracle, plus <Z_0>."""
+    import torch
+    circ = W.random_u2_cz(n=20, depth=10, seed=1000)
+    ref = orc.run(circ)
+    Z0 = W.pauli_sum(20, [("Z", (0,), 1.0)])
+    ez = orc.expect(ref, Z0).real
+    for name in DTYPES:
+        for fuse in [1, 2, 3, 5]:
+            say("plan u2cz", name, "fuse", fuse)
+            plan = q.Plan(circ, 1 if name == "c64" else 2, fuse)
+            d = torch.empty(1 << 20, dtype=torch_dtype(name), device="cuda")
+            outs = []
+            for rep in range(2):
+                q.qsv_init_basis(d, 0)
+                plan.run(d)
+                outs.append(d.clone())
+            assert torch.equal(outs[0], outs[1]), "graph replay differs from capture run"
+            check_close(to_np(d), ref, name, "fuse=%d" % fuse)
+            e = q.qsv_expectation(d, Z0).cpu().numpy()[0]
+            assert abs(e - ez) <= (1e-12 if name == "c128" else 1e-5)
+
+
+def test_plan_rotations_and_pairs(q, orc):
+    """Random pairs circuit (CNOT/CZ/CRZ) and the ansatz with device-side
+    rotation angles (unbound) or host-bound angles (fused)."""
+    import torch
+    circ, params = W.random_u2_pairs(n=12, depth=6, seed=1001)
+    ref = orc.run(circ, params)
+    hea = W.hea(9, 3)
+    hp = W.random_params(hea.nparams, 3)
+    href = orc.run(hea, hp)
+    for name in DTYPES:
+        dc = 1 if name == "c64" else 2
+        pd = torch.from_numpy(params).cuda()
+        for fuse, bound in [(1, False), (5, False), (5, True), (3, True)]:
+            say("plan pairs", name, fuse, bound)
+            plan = q.Plan(circ, dc, fuse, params if bound else None)
+            d = torch.empty(1 << 12, dtype=torch_dtype(name), device="cuda")
+            q.qsv_init_basis(d, 0)
+            plan.run(d, pd)
+            check_close(to_np(d), ref, name)
+            say("plan hea", name, fuse, bound)
+            plan = q.Plan(hea, dc, fuse, hp if bound else None)
+            d = torch.empty(1 << 9, dtype=torch_dtype(name), device="cuda")
+            q.qsv_init_basis(d, 0)
+            plan.run(d, torch.from_numpy(hp).cuda())
+            check_close(to_np(d), href, name)
+
+
+def test_adjoint_gradient(q, orc):
+    import torch
+    cases = [(W.hea(6, 3), W.tfim_chain(6)), (W.hea(11, 2), W.tfim_chain(11))]
+    # controlled rotation, RX, shared parameter, fixed gates, Y terms
+    c = W.Circuit(5, [W.Op("h", (0,)), W.Op("rx", (1,), param=0), W.Op("ry", (2,), param=1),
+                      W.Op("rz", (3,), controls=(0,), param=2), W.Op("x", (4,), controls=(2,)),
+                      W.Op("rx", (4,), param=0), W.Op("matrix", (1, 3), matrix=W.haar_unitary(
+                          np.random.default_rng(1), 4)), W.Op("ry", (0,), controls=(1, 2), param=3),
+                      W.Op("rz", (0,), param=1)], 4)
+    cases.append((c, W.pauli_sum(5, [("XY", (0, 1), 0.7), ("ZZ", (2, 4), -1.1), ("Y", (3,), 0.4),
+                                     ("X", (4,), 0.9)])))
+    for circ, H in cases:
+        p = W.random_params(circ.nparams, 17)
+        E_ref, g_ref = orc.adjoint(circ, p, H)
+        g_fd = orc.grad_finite_diff(circ, p, H)
+        assert np.max(np.abs(g_fd - g_ref)) < 1e-6
+        for name in DTYPES:
+            for fuse in [1, 5]:
+                say("adjoint", name, circ.n, circ.nparams, fuse)
+                plan = q.AdjointPlan(circ, H, 1 if name == "c64" else 2, fuse)
+                pd = torch.from_numpy(p).cuda()
+                e, g = plan.run(pd)
+                e, g = e.cpu().numpy()[0], g.cpu().numpy()
+                if name == "c128":
+                    assert abs(e - E_ref) < 1e-11
+                    assert np.max(np.abs(g - g_ref)) < 1e-10
+                    assert np.max(np.abs(g - g_fd)) < 1e-6
+                else:
+                    assert abs(e - E_ref) < 1e-4
+                    assert np.max(np.abs(g - g_ref)) < 1e-4
+                e2, g2 = plan.run(pd)  # graph replay, identical
+                assert e2.cpu().numpy()[0] == e and np.array_equal(g2.cpu().numpy(), g)
+                en = plan.energy(pd).cpu().numpy()[0]
+                assert abs(en - E_ref) < (1e-11 if name == "c128" else 1e-4)
+
+
+def test_adjoint_autograd(q, orc):
+    import torch
+    circ, H = W.hea(5, 2), W.tfim_chain(5)
+    p = W.random_params(circ.nparams, 4)
+    plan = q.AdjointPlan(circ, H, 2, 5)
+    theta = torch.tensor(p, device="cuda", requires_grad=True)
+    say("autograd")
+    E = q.adjoint_energy(theta, plan)
+    (2.0 * E).backward()
+    _, g_ref = orc.adjoint(circ, p, H)
+    assert np.max(np.abs(theta.grad.cpu().numpy() - 2.0 * g_ref)) < 1e-10
+
+
+def test_full_size_sampled(q, orc):
+    """n = 30 (8 GiB complex64, 16 GiB complex128): each gate applied to the
+    seeded random state, 96 output amplitudes compared with the oracle
+    evaluated one by one on the same seeded input."""
+    import torch
+    n, seed = 30, 4242
+    scale = 1.0 / np.sqrt(orc.random_norm2(n, seed))
+    rng = np.random.default_rng(77)
+    idx = np.concatenate([rng.integers(0, 1 << n, 90), [0, 1, (1 << n) - 1, (1 << n) - 2,
+                                                       1 << 29, (1 << 29) - 1]]).astype(np.uint64)
+    gates = [((t,), ()) for t in [0, 1, 2, 7, 15, 28, 29]]
+    gates += [((0, 29), ()), ((3, 1), ()), ((29, 17), ()), ((0, 1, 2), ()), ((2, 28, 14), ()),
+              ((29,), (0,)), ((0,), (29,)), ((5,), (3,)), ((0, 1, 2, 3, 4), ()),
+              ((25, 26, 27, 28, 29), ()), ((0, 29, 9, 3, 20), ())]
+    for name in DTYPES:
+        d = torch.empty(1 << n, dtype=torch_dtype(name), device="cuda")
+        for t, c in gates:
+            G = W.haar_unitary(rng, 2 ** len(t))
+            say("n30", name, t, c)
+            q.qsv_init_random(d, seed)
+            q.qsv_apply_gate(d, t, c, G)
+            got = d[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().astype(np.complex128)
+            ref = orc.apply_sampled_random(n, seed, scale, t, c, G, idx)
+            err = np.max(np.abs(got - ref))
+            assert err <= TOL[name] and err / np.max(np.abs(ref)) <= 1e-5, (name, t, c, err)
+        # permutations at full size: out[i] == in[pi(i)] bit for bit
+        for t, c in [((29,), ()), ((0,), ()), ((29,), (0,))]:
+            say("n30 perm", name, t, c)
+            q.qsv_init_random(d, seed)
+            before = d[torch.from_numpy(idx.astype(np.int64)).cuda()].clone()
+            q.qsv_apply_gate(d, t, c, X2)
+            cm = sum(1 << v for v in c)
+            src = np.where((idx & np.uint64(cm)) == np.uint64(cm), idx ^ np.uint64(1 << t[0]), idx)
+            after = d[torch.from_numpy(src.astype(np.int64)).cuda()]
+            assert torch.equal(torch.view_as_real(after), torch.view_as_real(before))
+        norm = q.qsv_norm2(d).cpu().numpy()[0]
+        assert abs(norm - 1.0) < (1e-12 if name == "c128" else 1e-5)
+        del d
+        torch.cuda.empty_cache()

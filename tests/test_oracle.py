@@ -393,3 +393,12 @@ def test_random_state_generator_definition(orc):
     assert a0.real == (6457827717110365317 >> 11) / 2.0 ** 53 - 0.5
     psi = orc.random_state(n, seed) * np.sqrt(s2)
     assert abs(psi.real.mean()) < 0.02 and abs(psi.imag.mean()) < 0.02
+
+
+def test_apply_hamiltonian_against_dense(orc):
+    n = 6
+    H = W.random_pauli_sum(n, 9, seed=4)
+    psi = rand_state(n)
+    got = orc.apply_hamiltonian(psi, H)
+    ref = brute.hamiltonian_dense(H) @ psi
+    assert np.max(np.abs(got - ref)) < 1e-13
