@@ -60,24 +60,55 @@ def event_time(fn, reps, stream):
     return a.elapsed_time(b) / 1e3 / reps
 
 
-def cpu_baseline():
+def cpu_baseline(min_seconds=10.0, max_gates=120):
+    """The CPU oracle (never tuned) on a bounded sample of the same sweep:
+    Haar U(2) gates cycling over the targets of a 28-qubit complex128 random
+    state, until about min_seconds of host time have passed."""
     import numpy as np
 
     import oracle
     import workloads as W
-    n = 26
+    n = 28
     rng = np.random.default_rng(1000)
     psi = oracle.random_state(n, 7)
     t0 = time.perf_counter()
     nbytes = 0.0
-    for t in [0, 13, 25]:
-        psi = oracle.apply(psi, (t,), (), W.haar_unitary(rng, 2))
+    gates = 0
+    while gates < max_gates and (gates < 3 or time.perf_counter() - t0 < min_seconds):
+        psi = oracle.apply(psi, ((gates * 11) % n,), (), W.haar_unitary(rng, 2))
         nbytes += 2.0 * 16 * (1 << n)
+        gates += 1
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
-            "sample": "oracle eq.(1) complex128 out of place, Haar U(2) at targets 0, 13, 25 of a "
-                      "26-qubit random state (1 GiB); %.1f s" % dt}
+            "sample": "oracle eq.(1), complex128, out of place: %d Haar U(2) gates on a 28-qubit "
+                      "random state (4 GiB), %.1f s of host time; GB/s counts 2 x 16 B per "
+                      "amplitude per gate like the GPU figure" % (gates, dt)}
+
+
+def profile_kernels():
+    """Short run for rocprofv3 counter passes: a 4 GiB torch copy (the
+    calibration kernel of known traffic) twice, then the single-qubit sweep
+    (n = 30, complex64, target 15) ten times."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_07017_amd import qsv
+    dev = torch.device("cuda:0")
+    src = torch.empty(1 << 29, dtype=torch.float64, device=dev)
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    del src, dst
+    psi = torch.empty(1 << 30, dtype=torch.complex64, device=dev)
+    qsv.qsv_init_random(psi, 5)
+    G = W.haar_unitary(np.random.default_rng(1), 2)
+    for _ in range(10):
+        qsv.qsv_apply_gate(psi, (15,), (), G)
+    torch.cuda.synchronize()
+    print("profile run done: 2 x 4 GiB copy, 10 x single-qubit sweep n=30 c64 t=15", flush=True)
 
 
 def main():
@@ -87,11 +118,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--skip-side", action="store_true", help="only the timed step")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only the dominant kernel and a copy of known size (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X and this build has no "
               "multi-GPU mode (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.profile_kernels:
+        profile_kernels()
+        return
 
     import numpy as np
     import torch

@@ -7,7 +7,10 @@
 // 2^(k+1) x 2^(k+1) real matrix with 2x2 blocks [[Re g, -Im g], [Im g, Re g]].
 // That real product runs on v_mfma_f32_16x16x4f32 (complex64 states) or
 // v_mfma_f64_16x16x4f64 (complex128 states); R(G) stays in registers as the
-// A operand for the whole kernel.
+// A operand for the whole kernel.  Both shapes take A[i][k] from lane
+// i + 16 k and B[k][j] from lane j + 16 k; their results differ: the f32 form
+// returns rows 4 (lane / 16) + r, the f64 form rows lane / 16 + 4 r (column
+// lane % 16, register r), as measured on gfx950.
 //
 // A workgroup handles tiles of 2^(k+6) amplitudes: all targets plus the six
 // lowest non-target qubits (64 groups).  Because those six bits and every
@@ -56,6 +59,8 @@ struct MfmaT<float> {
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    // result register r of lane l holds row 4 (l / 16) + r, column l % 16
+    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 template <>
 struct MfmaT<double> {
@@ -66,6 +71,8 @@ struct MfmaT<double> {
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    // result register r of lane l holds row l / 16 + 4 r, column l % 16
+    __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
 constexpr int kRow = 65;  // LDS row length in amplitudes (64 groups + 1 pad)
@@ -165,16 +172,15 @@ __global__ void __launch_bounds__(256) k_mfma(R* __restrict__ psi0, R* __restric
             for (int kk = 0; kk < KS; ++kk)
                 acc[rb] = T::mfma(afr[rb][kk], bfr[kk], acc[rb]);
         }
-        // D: lane holds real rows 16rb + 4(lane/16) + {0..3} of group `grp`,
-        // i.e. amplitudes tau = 8rb + 2(lane/16) and tau + 1.
+        // D: register r of each lane holds real row 16 rb + T::row(lane, r) of
+        // group `grp`; real row 2 tau + c is component c of amplitude tau.
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            const int t0 = 8 * rb + 2 * (lane >> 4);
-            lds[(t0 * kRow + grp) * 2] = acc[rb][0];
-            lds[(t0 * kRow + grp) * 2 + 1] = acc[rb][1];
-            lds[((t0 + 1) * kRow + grp) * 2] = acc[rb][2];
-            lds[((t0 + 1) * kRow + grp) * 2 + 1] = acc[rb][3];
-        }
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = 16 * rb + T::row(lane, r);
+                lds[((rr >> 1) * kRow + grp) * 2 + (rr & 1)] = acc[rb][r];
+            }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < VPT; ++r) {
