@@ -10,6 +10,8 @@
 // For complex64 states two adjacent amplitudes are moved as one 16-byte
 // float4 (modes W2 / INTRA), which keeps 16-byte accesses for every target
 // position including qubit 0.
+#include <cstdlib>
+
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -41,6 +43,62 @@ template <typename R>
 struct Cx {
     R re, im;
 };
+
+typedef float nv4f __attribute__((ext_vector_type(4)));
+typedef double nv2d __attribute__((ext_vector_type(2)));
+
+// 16-byte loads and stores, optionally with the nontemporal hint (streaming
+// sweeps touch every line once).
+template <bool NT>
+__device__ __forceinline__ float4 ldv(const float4* p)
+{
+    if constexpr (NT) {
+        const nv4f v = __builtin_nontemporal_load(reinterpret_cast<const nv4f*>(p));
+        return make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ double2 ldv(const double2* p)
+{
+    if constexpr (NT) {
+        const nv2d v = __builtin_nontemporal_load(reinterpret_cast<const nv2d*>(p));
+        return make_double2(v[0], v[1]);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ float2 ldv(const float2* p)
+{
+    return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void stv(float4* p, float4 v)
+{
+    if constexpr (NT) {
+        nv4f w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<nv4f*>(p));
+    } else {
+        *p = v;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void stv(double2* p, double2 v)
+{
+    if constexpr (NT) {
+        nv2d w = {v.x, v.y};
+        __builtin_nontemporal_store(w, reinterpret_cast<nv2d*>(p));
+    } else {
+        *p = v;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void stv(float2* p, float2 v)
+{
+    *p = v;
+}
 
 template <typename R>
 __device__ __forceinline__ void cmac(Cx<R>& acc, R gr, R gi, R xr, R xi)
@@ -85,7 +143,7 @@ __device__ __forceinline__ void rotation_matrix(int rot, double theta, R* m)
         m[j] = (R)v[j];
 }
 
-template <typename R, int K, int MODE, bool ROT, int UNR>
+template <typename R, int K, int MODE, bool ROT, int UNR, bool NT>
 __global__ void __launch_bounds__(kBlock) k_dense(R* __restrict__ psi0, R* __restrict__ psi1,
                                                   const DenseK<R, K> a)
 {
@@ -134,7 +192,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(R* __restrict__ psi0, R* __res
 #pragma unroll
                 for (int v = 0; v < NU; ++v)
                     if (ok[u])
-                        x[u][v] = p[base[u] + a.off[v]];
+                        x[u][v] = ldv<NT>(&p[base[u] + a.off[v]]);
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 if (!ok[u])
@@ -148,7 +206,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(R* __restrict__ psi0, R* __res
                     A o;
                     o.x = acc.re;
                     o.y = acc.im;
-                    p[base[u] + a.off[r]] = o;
+                    stv<NT>(&p[base[u] + a.off[r]], o);
                 }
             }
         } else {
@@ -160,7 +218,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(R* __restrict__ psi0, R* __res
 #pragma unroll
                 for (int v = 0; v < NU; ++v)
                     if (ok[u])
-                        x[u][v] = p[base[u] + a.off[v]];
+                        x[u][v] = ldv<NT>(&p[base[u] + a.off[v]]);
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 if (!ok[u])
@@ -175,7 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(R* __restrict__ psi0, R* __res
                             cmac(a0, gr, gi, x[u][c].x, x[u][c].y);
                             cmac(a1, gr, gi, x[u][c].z, x[u][c].w);
                         }
-                        p[base[u] + a.off[r]] = make_float4(a0.re, a0.im, a1.re, a1.im);
+                        stv<NT>(&p[base[u] + a.off[r]], make_float4(a0.re, a0.im, a1.re, a1.im));
                     }
                 } else {  // INTRA: x[u][v] holds tau' = 2v (xy) and 2v+1 (zw)
 #pragma unroll
@@ -192,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(R* __restrict__ psi0, R* __res
                                      x[u][cv].w);
                             }
                         }
-                        p[base[u] + a.off[rv]] = make_float4(o[0].re, o[0].im, o[1].re, o[1].im);
+                        stv<NT>(&p[base[u] + a.off[rv]], make_float4(o[0].re, o[0].im, o[1].re, o[1].im));
                     }
                 }
             }
@@ -431,14 +489,48 @@ DenseK<R, K> dense_args(const GateLaunch& L)
     return a;
 }
 
+// Groups per thread (UNR) and the nontemporal hint of the single-qubit
+// sweep; QSV_SWEEP_UNROLL / QSV_SWEEP_NT override the defaults.
+struct SweepTune {
+    int unr = 2;
+    bool nt = false;
+};
+
+SweepTune sweep_tune()
+{
+    SweepTune t;
+    if (const char* e = getenv("QSV_SWEEP_UNROLL"))
+        t.unr = atoi(e) == 1 ? 1 : (atoi(e) >= 4 ? 4 : 2);
+    if (const char* e = getenv("QSV_SWEEP_NT"))
+        t.nt = e[0] == '1';
+    return t;
+}
+
+template <typename R, int K, int MODE, bool ROT, int UNR, bool NT>
+hipError_t dense_launch(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
+{
+    dim3 grid(grid_for(L.ngroups, UNR), p1 ? 2 : 1);
+    hipLaunchKernelGGL((k_dense<R, K, MODE, ROT, UNR, NT>), grid, dim3(kBlock), 0, s,
+                       static_cast<R*>(p0), static_cast<R*>(p1 ? p1 : p0), dense_args<R, K>(L));
+    return hipGetLastError();
+}
+
 template <typename R, int K, int MODE, bool ROT>
 hipError_t dense_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
 {
-    constexpr int UNR = K == 1 ? 2 : 1;
-    dim3 grid(grid_for(L.ngroups, UNR), p1 ? 2 : 1);
-    hipLaunchKernelGGL((k_dense<R, K, MODE, ROT, UNR>), grid, dim3(kBlock), 0, s,
-                       static_cast<R*>(p0), static_cast<R*>(p1 ? p1 : p0), dense_args<R, K>(L));
-    return hipGetLastError();
+    if constexpr (K == 1) {
+        const SweepTune t = sweep_tune();
+        if (t.unr == 1)
+            return t.nt ? dense_launch<R, 1, MODE, ROT, 1, true>(L, p0, p1, s)
+                        : dense_launch<R, 1, MODE, ROT, 1, false>(L, p0, p1, s);
+        if (t.unr == 4)
+            return t.nt ? dense_launch<R, 1, MODE, ROT, 4, true>(L, p0, p1, s)
+                        : dense_launch<R, 1, MODE, ROT, 4, false>(L, p0, p1, s);
+        return t.nt ? dense_launch<R, 1, MODE, ROT, 2, true>(L, p0, p1, s)
+                    : dense_launch<R, 1, MODE, ROT, 2, false>(L, p0, p1, s);
+    } else {
+        return dense_launch<R, K, MODE, ROT, 1, false>(L, p0, p1, s);
+    }
 }
 
 template <typename R, int K>

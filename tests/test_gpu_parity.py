@@ -135,7 +135,7 @@ def test_four_and_five_qubit_gates(q, orc, n):
         psi = rand_state(n, rng, name)
         for k in [4, 5]:
             places = [tuple(range(k)), tuple(range(n - k, n)), tuple(reversed(range(k))),
-                      (0, n - 1, 3, 7, 5)[:k], (1, 2, 9, 6, n - 2)[:k],
+                      (0, n - 1, 3, 7, 5)[:k], (1, 2, n - 1, 6, n - 3)[:k],
                       tuple(int(v) for v in rng.choice(n, k, replace=False))]
             for t in places:
                 G = W.haar_unitary(rng, 2 ** k)
