@@ -161,6 +161,9 @@ Built build_launch(int n, int dt, const int* ct, int k, const int* ctl, int c, c
     GateLaunch& L = b.L;
     L.dt = dt;
     L.n = n;
+    L.lowq = ct[0];
+    for (int j = 0; j < c; ++j)
+        L.lowq = std::min(L.lowq, ctl[j]);
     const int D = 1 << k;
     const size_t S = amp_bytes(dt);
     uint64_t cmask = 0;
@@ -354,6 +357,9 @@ GateLaunch rotation_launch(int n, int dt, int rot, int target, const int* ctl, i
     L.n = n;
     L.rot = rot;
     L.pidx = pidx;
+    L.lowq = target;
+    for (int j = 0; j < c; ++j)
+        L.lowq = std::min(L.lowq, ctl[j]);
     const size_t S = amp_bytes(dt);
     uint64_t cmask = 0;
     bool ctl0 = false;

@@ -489,18 +489,22 @@ DenseK<R, K> dense_args(const GateLaunch& L)
     return a;
 }
 
-// Groups per thread (UNR) and the nontemporal hint of the single-qubit
-// sweep; QSV_SWEEP_UNROLL / QSV_SWEEP_NT override the defaults.
+// Groups per thread (UNR) and the nontemporal hint of the sweeps.  Measured
+// on MI355X at n = 30: one group per thread is fastest, and the nontemporal
+// hint gains up to 10% once the lowest touched qubit is >= 2 (the two halves
+// of a pair then sit in different 32-byte sectors) but not below.
+// QSV_SWEEP_UNROLL / QSV_SWEEP_NT (0/1) override the choice.
 struct SweepTune {
-    int unr = 2;
+    int unr = 1;
     bool nt = false;
 };
 
-SweepTune sweep_tune()
+SweepTune sweep_tune(int lowest_qubit)
 {
     SweepTune t;
+    t.nt = lowest_qubit >= 2;
     if (const char* e = getenv("QSV_SWEEP_UNROLL"))
-        t.unr = atoi(e) == 1 ? 1 : (atoi(e) >= 4 ? 4 : 2);
+        t.unr = atoi(e) <= 1 ? 1 : (atoi(e) >= 4 ? 4 : 2);
     if (const char* e = getenv("QSV_SWEEP_NT"))
         t.nt = e[0] == '1';
     return t;
@@ -518,16 +522,16 @@ hipError_t dense_launch(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
 template <typename R, int K, int MODE, bool ROT>
 hipError_t dense_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
 {
-    if constexpr (K == 1) {
-        const SweepTune t = sweep_tune();
-        if (t.unr == 1)
-            return t.nt ? dense_launch<R, 1, MODE, ROT, 1, true>(L, p0, p1, s)
-                        : dense_launch<R, 1, MODE, ROT, 1, false>(L, p0, p1, s);
-        if (t.unr == 4)
-            return t.nt ? dense_launch<R, 1, MODE, ROT, 4, true>(L, p0, p1, s)
-                        : dense_launch<R, 1, MODE, ROT, 4, false>(L, p0, p1, s);
-        return t.nt ? dense_launch<R, 1, MODE, ROT, 2, true>(L, p0, p1, s)
-                    : dense_launch<R, 1, MODE, ROT, 2, false>(L, p0, p1, s);
+    const SweepTune t = sweep_tune(L.lowq);
+    if constexpr (K <= 3) {
+        if (t.unr == 2)
+            return t.nt ? dense_launch<R, K, MODE, ROT, 2, true>(L, p0, p1, s)
+                        : dense_launch<R, K, MODE, ROT, 2, false>(L, p0, p1, s);
+        if (t.unr == 4 && K == 1)
+            return t.nt ? dense_launch<R, K, MODE, ROT, 4, true>(L, p0, p1, s)
+                        : dense_launch<R, K, MODE, ROT, 4, false>(L, p0, p1, s);
+        return t.nt ? dense_launch<R, K, MODE, ROT, 1, true>(L, p0, p1, s)
+                    : dense_launch<R, K, MODE, ROT, 1, false>(L, p0, p1, s);
     } else {
         return dense_launch<R, K, MODE, ROT, 1, false>(L, p0, p1, s);
     }

@@ -166,12 +166,15 @@ __global__ void __launch_bounds__(256) k_mfma(R* __restrict__ psi0, R* __restric
         }
         typename T::Acc acc[RB];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
+        for (int rb = 0; rb < RB; ++rb)
             acc[rb] = typename T::Acc{0, 0, 0, 0};
+        // k-steps outermost: the RB accumulators are independent chains that
+        // the matrix core can overlap.
 #pragma unroll
-            for (int kk = 0; kk < KS; ++kk)
+        for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
                 acc[rb] = T::mfma(afr[rb][kk], bfr[kk], acc[rb]);
-        }
         // D: register r of each lane holds real row 16 rb + T::row(lane, r) of
         // group `grp`; real row 2 tau + c is component c of amplitude tau.
 #pragma unroll

@@ -70,6 +70,14 @@ __device__ __forceinline__ void st(R* p, uint64_t i, double2 v)
     reinterpret_cast<typename W<R>::A*>(p)[i] = a;
 }
 
+// Two adjacent complex64 amplitudes (one 16-byte load), widened to FP64.
+__device__ __forceinline__ void ld_pair(const float* p, uint64_t v, double2& a0, double2& a1)
+{
+    const float4 f = reinterpret_cast<const float4*>(p)[v];
+    a0 = make_double2((double)f.x, (double)f.y);
+    a1 = make_double2((double)f.z, (double)f.w);
+}
+
 __device__ __forceinline__ int popc64(uint64_t v)
 {
     return __popcll(v);
@@ -101,16 +109,26 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_norm2(const R* __restrict__ psi, uint64_t N,
                                                   double* partials, int accumulate)
 {
+    (void)accumulate;
     double s = 0.0;
     const uint64_t step = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
-        const double2 a = ld(psi, i);
-        s += a.x * a.x + a.y * a.y;
+    if constexpr (sizeof(R) == 4) {
+        for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < N / 2; v += step) {
+            double2 a, b;
+            ld_pair(psi, v, a, b);
+            s += a.x * a.x + a.y * a.y + (b.x * b.x + b.y * b.y);
+        }
+        if (N == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+            const double2 a = ld(psi, 0);
+            s += a.x * a.x + a.y * a.y;
+        }
+    } else {
+        for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
+            const double2 a = ld(psi, i);
+            s += a.x * a.x + a.y * a.y;
+        }
     }
-    double* out = partials + blockIdx.x;
-    block_sum_store(s, out);
-    if (threadIdx.x == 0 && accumulate)
-        ;  // norm is always a single pass
+    block_sum_store(s, partials + blockIdx.x);
 }
 
 template <typename R>
@@ -120,9 +138,22 @@ __global__ void __launch_bounds__(kBlock) k_expect_diag(const R* __restrict__ ps
 {
     double s = 0.0;
     const uint64_t step = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
-        const double2 a = ld(psi, i);
-        s += diag_weight(i, t) * (a.x * a.x + a.y * a.y);
+    if constexpr (sizeof(R) == 4) {
+        for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < N / 2; v += step) {
+            double2 a, b;
+            ld_pair(psi, v, a, b);
+            s += diag_weight(2 * v, t) * (a.x * a.x + a.y * a.y) +
+                 diag_weight(2 * v + 1, t) * (b.x * b.x + b.y * b.y);
+        }
+        if (N == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+            const double2 a = ld(psi, 0);
+            s += diag_weight(0, t) * (a.x * a.x + a.y * a.y);
+        }
+    } else {
+        for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
+            const double2 a = ld(psi, i);
+            s += diag_weight(i, t) * (a.x * a.x + a.y * a.y);
+        }
     }
     __shared__ double red[kBlock];
     red[threadIdx.x] = s;
@@ -188,10 +219,25 @@ __global__ void __launch_bounds__(kBlock) k_inner(const R* __restrict__ a, const
 {
     double sr = 0.0, si = 0.0;
     const uint64_t step = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
-        const double2 u = ld(a, i), v = ld(b, i);
-        sr += u.x * v.x + u.y * v.y;
-        si += u.x * v.y - u.y * v.x;
+    if constexpr (sizeof(R) == 4) {
+        for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < N / 2; v += step) {
+            double2 u0, u1, v0, v1;
+            ld_pair(a, v, u0, u1);
+            ld_pair(b, v, v0, v1);
+            sr += (u0.x * v0.x + u0.y * v0.y) + (u1.x * v1.x + u1.y * v1.y);
+            si += (u0.x * v0.y - u0.y * v0.x) + (u1.x * v1.y - u1.y * v1.x);
+        }
+        if (N == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+            const double2 u = ld(a, 0), v = ld(b, 0);
+            sr += u.x * v.x + u.y * v.y;
+            si += u.x * v.y - u.y * v.x;
+        }
+    } else {
+        for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
+            const double2 u = ld(a, i), v = ld(b, i);
+            sr += u.x * v.x + u.y * v.y;
+            si += u.x * v.y - u.y * v.x;
+        }
     }
     __shared__ double red[2][kBlock];
     red[0][threadIdx.x] = sr;

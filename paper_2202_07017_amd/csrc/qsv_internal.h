@@ -44,6 +44,7 @@ struct GateLaunch {
     int n = 0;
     int K = 0;          // dense: #targets; diag: #varying targets; mfma: K; perm: unused
     int mode = W1;
+    int lowq = 0;       // lowest qubit the launch touches (targets and controls)
     uint64_t ngroups = 0;
     InsertSpec ins{};
     uint64_t off[32] = {};   // dense: unit offset per tau' (INTRA: per tau'>>1); perm: dst
