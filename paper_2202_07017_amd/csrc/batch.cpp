@@ -1,35 +1,447 @@
-// Batched evaluation of many small rotation circuits (energies and adjoint
-// gradients) -- placeholder entry points until the persistent kernel lands.
+// Host side of the batched mode: validation, the cache-blocking pass
+// scheduler, device tables, graph replay and the autotuner.
+#include <algorithm>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "qsv.h"
+#include "qsv_batch.h"
 #include "qsv_host.h"
 
 using namespace qsv;
 
-struct qsv_batch_plan {
-    int ninst = 0;
+namespace {
+
+struct HOp {
+    int kind;  // 0 fixed matrix, 5/6/7 rotation
+    int t, nc, c0, c1;
+    int param;
+    int mat;
 };
+
+struct HInst {
+    int n = 0;
+    int nparam = 0;
+    std::vector<HOp> ops;
+    std::vector<BTerm> terms;
+};
+
+struct HPass {
+    uint32_t bmask;
+    std::vector<int> ops;
+};
+
+// Schedule the gates into passes whose qubits fit a tile of m qubits.  A
+// pass takes every remaining gate, in circuit order, whose qubits are tile
+// qubits and that no unscheduled earlier gate blocks (a gate blocks its
+// qubits for all later gates), so one pass can cover several layers on the
+// tile's qubits.  Tile qubits: 0, 1, 2 (contiguous 64-byte chunks), then the
+// qubits of the remaining gates in order of first appearance.
+std::vector<HPass> schedule(const HInst& I, int m)
+{
+    std::vector<HPass> out;
+    const int nops = (int)I.ops.size();
+    auto qubits = [&](const HOp& o) {
+        uint32_t q = 1u << o.t;
+        if (o.nc > 0)
+            q |= 1u << o.c0;
+        if (o.nc > 1)
+            q |= 1u << o.c1;
+        return q;
+    };
+    if (I.n <= m) {
+        for (int s = 0; s < nops; s += kMaxPassOps) {
+            HPass p{(1u << I.n) - 1, {}};
+            for (int o = s; o < nops && o < s + kMaxPassOps; ++o)
+                p.ops.push_back(o);
+            out.push_back(p);
+        }
+        return out;
+    }
+    std::vector<bool> done(nops, false);
+    int left = nops;
+    while (left > 0) {
+        uint32_t B = 0x7;
+        for (int o = 0; o < nops && __builtin_popcount(B) < m; ++o) {
+            if (done[o])
+                continue;
+            uint32_t q = qubits(I.ops[o]) & ~B;
+            while (q && __builtin_popcount(B) < m) {
+                B |= q & (~q + 1);
+                q &= q - 1;
+            }
+        }
+        for (int b = 0; b < I.n && __builtin_popcount(B) < m; ++b)
+            B |= 1u << b;
+        HPass p{B, {}};
+        uint32_t blocked = 0;
+        for (int o = 0; o < nops; ++o) {
+            if (done[o])
+                continue;
+            const uint32_t q = qubits(I.ops[o]);
+            if ((q & ~B) == 0 && (q & blocked) == 0 && (int)p.ops.size() < kMaxPassOps) {
+                p.ops.push_back(o);
+                done[o] = true;
+                --left;
+            } else {
+                blocked |= q;
+            }
+        }
+        out.push_back(p);
+    }
+    return out;
+}
+
+int local_bit(uint32_t B, int q)
+{
+    return __builtin_popcount(B & ((1u << q) - 1));
+}
+
+}  // namespace
+
+struct qsv_batch_plan {
+    int dt = 0;
+    int ninst = 0;
+    std::vector<HInst> inst;
+    std::vector<double> mats;  // fixed 2x2 matrices, 8 doubles each
+    std::vector<long long> param_off;
+    std::vector<int> order;
+    long long work_bytes = 0;
+    std::vector<long long> work_off;
+    // configuration
+    int m = 0, threads = 0, blocks = 0;
+    int cfg_m = -1;
+    DevPack dev;
+    size_t o_inst = 0, o_order = 0, o_pass = 0, o_pops = 0, o_mats = 0, o_terms = 0;
+    GraphCache graph;
+    std::string key;
+};
+
+namespace {
+
+constexpr int kWorkMinQubits = 11;  // instances with n >= this get a workspace region
+
+qsv_status configure(qsv_batch_plan* P, int m, int threads)
+{
+    if (P->cfg_m == m && P->threads == threads && P->dev.mem)
+        return QSV_OK;
+    P->graph.reset();
+    P->dev.reset();
+    std::vector<BInst> bi(P->ninst);
+    std::vector<BPass> passes;
+    std::vector<BPOp> pops;
+    std::vector<BTerm> terms;
+    for (int i = 0; i < P->ninst; ++i) {
+        const HInst& I = P->inst[i];
+        std::vector<HPass> hp = schedule(I, m);
+        BInst& b = bi[i];
+        b.n = I.n;
+        b.npass = (int)hp.size();
+        b.pass_off = (int)passes.size();
+        b.nterm = (int)I.terms.size();
+        b.term_off = (int)terms.size();
+        b.nparam = I.nparam;
+        b.param_off = P->param_off[i];
+        b.work_off = P->work_off[i];
+        for (const HPass& p : hp) {
+            BPass q{p.bmask, (int)p.ops.size(), (int)pops.size(), 0};
+            for (int o : p.ops) {
+                const HOp& h = I.ops[o];
+                BPOp x{};
+                x.kind = (uint8_t)h.kind;
+                x.tloc = (uint8_t)local_bit(p.bmask, h.t);
+                x.nc = (uint8_t)h.nc;
+                x.c0 = (uint8_t)(h.nc > 0 ? local_bit(p.bmask, h.c0) : 0);
+                x.c1 = (uint8_t)(h.nc > 1 ? local_bit(p.bmask, h.c1) : 0);
+                x.param = h.param;
+                x.mat = h.mat;
+                pops.push_back(x);
+            }
+            passes.push_back(q);
+        }
+        terms.insert(terms.end(), I.terms.begin(), I.terms.end());
+    }
+    auto bytes_of = [](const void* p, size_t n) {
+        return std::vector<unsigned char>(static_cast<const unsigned char*>(p),
+                                          static_cast<const unsigned char*>(p) + n);
+    };
+    P->o_inst = P->dev.add(bytes_of(bi.data(), bi.size() * sizeof(BInst)));
+    P->o_order = P->dev.add(bytes_of(P->order.data(), P->order.size() * sizeof(int)));
+    P->o_pass = P->dev.add(bytes_of(passes.data(), passes.size() * sizeof(BPass)));
+    P->o_pops = P->dev.add(bytes_of(pops.data(), std::max<size_t>(pops.size(), 1) * sizeof(BPOp)));
+    P->o_mats = P->dev.add(bytes_of(P->mats.data(), std::max<size_t>(P->mats.size(), 8) * sizeof(double)));
+    P->o_terms = P->dev.add(bytes_of(terms.data(), terms.size() * sizeof(BTerm)));
+    qsv_status st = P->dev.commit();
+    if (st)
+        return st;
+    const int res = batch_resident_blocks(P->dt, m, threads);
+    if (res <= 0)
+        return fail(QSV_ERR_UNSUPPORTED, "batch kernel does not fit (m = %d, %d threads)", m, threads);
+    P->blocks = std::min(res, P->ninst);
+    P->m = m;
+    P->threads = threads;
+    P->cfg_m = m;
+    return QSV_OK;
+}
+
+qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* energies,
+                   double* grads, hipStream_t s)
+{
+    BatchArgs a{};
+    a.inst = static_cast<const BInst*>(P->dev.at(P->o_inst));
+    a.order = static_cast<const int*>(P->dev.at(P->o_order));
+    a.ninst = P->ninst;
+    a.m = P->m;
+    a.passes = static_cast<const BPass*>(P->dev.at(P->o_pass));
+    a.pops = static_cast<const BPOp*>(P->dev.at(P->o_pops));
+    a.mats = static_cast<const double*>(P->dev.at(P->o_mats));
+    a.terms = static_cast<const BTerm*>(P->dev.at(P->o_terms));
+    a.params = params;
+    a.grads = grads;
+    a.energies = energies;
+    a.work = static_cast<char*>(work);
+    a.counter = static_cast<int*>(work);
+    hipError_t e = launch_batch(a, P->dt, P->threads, P->blocks, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+    return QSV_OK;
+}
+
+std::vector<std::pair<int, int>> candidates(int dt)
+{
+    if (dt == QSV_C64)
+        return {{12, 512}, {12, 256}, {11, 256}, {11, 512}, {13, 1024}, {13, 512}};
+    return {{11, 512}, {11, 256}, {10, 256}, {12, 1024}, {12, 512}};
+}
+
+bool read_cache(const std::string& key, int* m, int* threads)
+{
+    const char* path = getenv("QSV_TUNE_CACHE");
+    if (!path)
+        return false;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        // one entry per line:  "key": [m, threads, ms],
+        const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
+        if (q0 == std::string::npos || q1 == std::string::npos || line.substr(q0 + 1, q1 - q0 - 1) != key)
+            continue;
+        int a = 0, b = 0;
+        if (sscanf(line.c_str() + line.find('[', q1), "[%d, %d", &a, &b) == 2) {
+            *m = a;
+            *threads = b;
+            return true;
+        }
+    }
+    return false;
+}
+
+void write_cache(const std::string& key, int m, int threads, double ms)
+{
+    const char* path = getenv("QSV_TUNE_CACHE");
+    if (!path)
+        return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line))
+            if (line.find('"') != std::string::npos && line.find("\"" + key + "\"") == std::string::npos)
+                keep.push_back(line.back() == ',' ? line.substr(0, line.size() - 1) : line);
+    }
+    char buf[256];
+    snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %.3f]", key.c_str(), m, threads, ms);
+    keep.push_back(buf);
+    std::ofstream o(path);
+    o << "{\n";
+    for (size_t j = 0; j < keep.size(); ++j)
+        o << keep[j] << (j + 1 < keep.size() ? ",\n" : "\n");
+    o << "}\n";
+}
+
+}  // namespace
 
 extern "C" {
 
-qsv_status qsv_batch_plan_create(const qsv_circuit*, const qsv_pauli_sum*, int, qsv_dtype,
-                                 qsv_batch_plan**, size_t*)
+qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* Hs, int ninst,
+                                 qsv_dtype dt, qsv_batch_plan** plan, size_t* work_bytes)
 {
-    return fail(QSV_ERR_UNSUPPORTED, "batched evaluation is not available in this build");
+    if (!circs || !Hs || ninst < 1 || !plan || !work_bytes)
+        return fail(QSV_ERR_ARG, "NULL circuit list, Hamiltonian list, plan or size, or ninst < 1");
+    qsv_status st = check_n_dt(1, dt);
+    if (st)
+        return st;
+    std::unique_ptr<qsv_batch_plan> P(new qsv_batch_plan);
+    P->dt = dt;
+    P->ninst = ninst;
+    P->inst.resize(ninst);
+    P->param_off.resize(ninst + 1, 0);
+    P->work_off.assign(ninst, 0);
+    long long woff = 256;  // the queue counter lives at offset 0
+    std::ostringstream sig;
+    sig << "gfx950/" << (dt == QSV_C64 ? "c64" : "c128") << "/" << ninst;
+    unsigned long long h = 1469598103934665603ull;
+    for (int i = 0; i < ninst; ++i) {
+        const qsv_circuit* C = &circs[i];
+        if ((st = check_circuit(C, QSV_BATCH_MAX_QUBITS)))
+            return fail(st, "instance %d: %s", i, qsv_last_error());
+        if ((st = check_hamiltonian(&Hs[i], C->n)))
+            return fail(st, "instance %d: %s", i, qsv_last_error());
+        HInst& I = P->inst[i];
+        I.n = C->n;
+        I.nparam = C->nparams;
+        for (int o = 0; o < C->nops; ++o) {
+            const qsv_op& op = C->ops[o];
+            if (op.k != 1 || op.c > 2 || op.kind == QSV_OP_SWAP)
+                return fail(QSV_ERR_UNSUPPORTED,
+                            "instance %d op %d: batches take single-target gates with <= 2 controls",
+                            i, o);
+            HOp x{};
+            x.t = op.targets[0];
+            x.nc = op.c;
+            x.c0 = op.c > 0 ? op.controls[0] : 0;
+            x.c1 = op.c > 1 ? op.controls[1] : 0;
+            x.param = -1;
+            x.mat = -1;
+            if (op.kind == QSV_OP_RX || op.kind == QSV_OP_RY || op.kind == QSV_OP_RZ) {
+                x.kind = op.kind;
+                x.param = op.param;
+            } else {
+                x.kind = 0;
+                x.mat = (int)(P->mats.size() / 8);
+                std::vector<double> m = op_matrix(op, 0.0);
+                P->mats.insert(P->mats.end(), m.begin(), m.end());
+            }
+            I.ops.push_back(x);
+        }
+        for (int t = 0; t < Hs[i].nterms; ++t) {
+            BTerm b{};
+            b.x = Hs[i].x_mask[t];
+            b.z = Hs[i].z_mask[t];
+            b.c = Hs[i].coeff[t];
+            b.ylo = __builtin_popcountll(b.x & b.z) & 3;
+            I.terms.push_back(b);
+        }
+        P->param_off[i + 1] = P->param_off[i] + C->nparams;
+        if (I.n >= kWorkMinQubits) {
+            P->work_off[i] = woff;
+            woff += (long long)(2 * amp_bytes(dt)) << I.n;
+            woff = (woff + 255) & ~255ll;
+        }
+        h = (h ^ (unsigned long long)(I.n * 1000003 + C->nops)) * 1099511628211ull;
+    }
+    sig << "/" << std::hex << h;
+    P->key = sig.str();
+    P->work_bytes = woff;
+    // largest estimated work first
+    P->order.resize(ninst);
+    for (int i = 0; i < ninst; ++i)
+        P->order[i] = i;
+    std::stable_sort(P->order.begin(), P->order.end(), [&](int a, int b) {
+        const double ca = std::ldexp((double)P->inst[a].ops.size() + 1, P->inst[a].n);
+        const double cb = std::ldexp((double)P->inst[b].ops.size() + 1, P->inst[b].n);
+        return ca > cb;
+    });
+    int m = dt == QSV_C64 ? 12 : 11, threads = 512;
+    read_cache(P->key, &m, &threads);
+    if (const char* e = getenv("QSV_BATCH_SHAPE")) {  // "m,threads" (tests of every shape)
+        int a = 0, b = 0;
+        if (sscanf(e, "%d,%d", &a, &b) == 2 && a >= 3 && a <= 14 && (b == 256 || b == 512 || b == 1024)) {
+            m = a;
+            threads = b;
+        }
+    }
+    P->m = m;
+    P->threads = threads;
+    *work_bytes = (size_t)P->work_bytes;
+    *plan = P.release();
+    return ok();
 }
 
-qsv_status qsv_batch_offsets(const qsv_batch_plan*, int64_t*)
+qsv_status qsv_batch_offsets(const qsv_batch_plan* plan, int64_t* offsets)
 {
-    return fail(QSV_ERR_UNSUPPORTED, "batched evaluation is not available in this build");
+    if (!plan || !offsets)
+        return fail(QSV_ERR_ARG, "plan or offsets is NULL");
+    for (int i = 0; i <= plan->ninst; ++i)
+        offsets[i] = plan->param_off[i];
+    return ok();
 }
 
-qsv_status qsv_batch_run(qsv_batch_plan*, const double*, void*, double*, double*, void*)
+qsv_status qsv_batch_run(qsv_batch_plan* plan, const double* params_dev, void* work,
+                         double* energies_dev, double* grads_dev, void* stream)
 {
-    return fail(QSV_ERR_UNSUPPORTED, "batched evaluation is not available in this build");
+    if (!plan || !work || !energies_dev || (plan->param_off.back() > 0 && (!params_dev || !grads_dev)))
+        return fail(QSV_ERR_ARG, "NULL plan, work, energies, gradients or parameters");
+    if (reinterpret_cast<uintptr_t>(work) % 256)
+        return fail(QSV_ERR_ARG, "work is not 256-byte aligned");
+    qsv_status st = configure(plan, plan->m, plan->threads);
+    if (st) {
+        // the requested tile does not fit this device: take the first candidate that does
+        for (auto c : candidates(plan->dt))
+            if ((st = configure(plan, c.first, c.second)) == QSV_OK)
+                break;
+        if (st)
+            return st;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<const void*> key = {params_dev, work, energies_dev, grads_dev};
+    st = run_graph(plan->graph, key, s, [&](hipStream_t cs) {
+        return enqueue(plan, params_dev, work, energies_dev, grads_dev, cs);
+    });
+    if (st)
+        return st;
+    return ok();
 }
 
-qsv_status qsv_batch_tune(qsv_batch_plan*, const double*, void*, double*, double*, void*, int*)
+qsv_status qsv_batch_tune(qsv_batch_plan* plan, const double* params_dev, void* work,
+                          double* energies_dev, double* grads_dev, void* stream, int* chosen)
 {
-    return fail(QSV_ERR_UNSUPPORTED, "batched evaluation is not available in this build");
+    if (!plan || !work || !energies_dev)
+        return fail(QSV_ERR_ARG, "NULL plan, work or energies");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(QSV_ERR_HIP, "event creation failed");
+    double best = 1e300;
+    int bm = plan->m, bt = plan->threads;
+    qsv_status st = QSV_OK;
+    for (auto c : candidates(plan->dt)) {
+        hipStreamSynchronize(s);
+        if (configure(plan, c.first, c.second) != QSV_OK)
+            continue;
+        if (enqueue(plan, params_dev, work, energies_dev, grads_dev, s) != QSV_OK)
+            continue;  // this shape does not launch here
+        hipEventRecord(e0, s);
+        for (int r = 0; r < 2 && !st; ++r)
+            st = enqueue(plan, params_dev, work, energies_dev, grads_dev, s);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms / 2 < best) {
+            best = ms / 2;
+            bm = c.first;
+            bt = c.second;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st)
+        return st;
+    hipStreamSynchronize(s);
+    if ((st = configure(plan, bm, bt)))
+        return st;
+    write_cache(plan->key, bm, bt, best);
+    if (chosen) {
+        chosen[0] = bm;
+        chosen[1] = bt;
+    }
+    return ok();
 }
 
 qsv_status qsv_batch_plan_destroy(qsv_batch_plan* plan)

@@ -1,6 +1,8 @@
 // Host-side helpers shared by the C-ABI translation units of libqsv.so.
 #pragma once
 
+#include <cstdlib>
+#include <cstring>
 #include <string>
 #include <utility>
 #include <vector>
@@ -38,5 +40,114 @@ qsv_status enqueue_expectation(const void* psi, int n, int dt, const qsv_pauli_s
                                double* work, int ncomp, hipStream_t s);
 qsv_status enqueue_hpsi(const void* psi, void* lam, int n, int dt, const qsv_pauli_sum* H,
                         hipStream_t s);
+qsv_status check_circuit(const qsv_circuit* C, int max_n);
+std::vector<double> op_matrix(const qsv_op& op, double theta);
+
+// --------------------------------------------------------- graph caching
+
+struct GraphCache {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> key;
+    ~GraphCache() { reset(); }
+    void reset()
+    {
+        if (exec)
+            hipGraphExecDestroy(exec);
+        if (graph)
+            hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        key.clear();
+    }
+};
+
+inline bool graphs_enabled()
+{
+    const char* e = getenv("QSV_NO_GRAPH");
+    return !(e && e[0] == '1');
+}
+
+// Run `enqueue` directly, or through a cached graph keyed by `key`.
+template <typename F>
+qsv_status run_graph(GraphCache& gc, const std::vector<const void*>& key, hipStream_t s,
+                            F enqueue)
+{
+    if (!graphs_enabled())
+        return enqueue(s);
+    if (!gc.exec || gc.key != key) {
+        gc.reset();
+        hipStream_t cs;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "capture stream: %s", hipGetErrorString(e));
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            hipStreamDestroy(cs);
+            return fail(QSV_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
+        }
+        qsv_status st = enqueue(cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        hipStreamDestroy(cs);
+        if (st) {
+            if (g)
+                hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "end capture: %s", hipGetErrorString(e));
+        gc.graph = g;
+        e = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            gc.reset();
+            return fail(QSV_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        gc.key = key;
+    }
+    hipError_t e = hipGraphLaunch(gc.exec, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+    return QSV_OK;
+}
+
+// Device memory owned by a plan: all uploads packed at 256-byte offsets.
+struct DevPack {
+    void* mem = nullptr;
+    size_t bytes = 0;
+    std::vector<std::pair<size_t, std::vector<unsigned char>>> pending;
+    size_t add(std::vector<unsigned char> data)
+    {
+        const size_t off = (bytes + 255) & ~size_t(255);
+        bytes = off + data.size();
+        pending.push_back({off, std::move(data)});
+        return off;
+    }
+    qsv_status commit()
+    {
+        if (bytes == 0)
+            return QSV_OK;
+        if (hipMalloc(&mem, bytes) != hipSuccess)
+            return fail(QSV_ERR_NOMEM, "plan device allocation of %zu bytes failed", bytes);
+        std::vector<unsigned char> host(bytes, 0);
+        for (auto& p : pending)
+            std::memcpy(host.data() + p.first, p.second.data(), p.second.size());
+        hipError_t e = hipMemcpy(mem, host.data(), bytes, hipMemcpyHostToDevice);
+        pending.clear();
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "plan upload: %s", hipGetErrorString(e));
+        return QSV_OK;
+    }
+    const void* at(size_t off) const { return static_cast<const char*>(mem) + off; }
+    void reset()
+    {
+        if (mem)
+            hipFree(mem);
+        mem = nullptr;
+        bytes = 0;
+        pending.clear();
+    }
+    ~DevPack() { reset(); }
+};
 
 }  // namespace qsv

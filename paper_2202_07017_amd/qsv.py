@@ -389,3 +389,47 @@ def adjoint_energy(params, plan):
     if _AE is None:
         _AE = _autograd_function()
     return _AE.apply(params, plan)
+
+
+class BatchPlan:
+    """qsv_batch_plan over a list of (circuit, Hamiltonian) instances, with its
+    device workspace (a torch tensor).  Parameters and gradients of instance i
+    are params[offsets[i]:offsets[i+1]] of the concatenated vectors."""
+
+    def __init__(self, instances, dtype_code_: int, device="cuda"):
+        import torch
+        self.cs = [CircuitC(inst.circuit) for inst in instances]
+        self.Hs = [PauliSum(inst.hamiltonian) for inst in instances]
+        ca = (qsv_circuit * len(self.cs))(*[c.s for c in self.cs])
+        ha = (qsv_pauli_sum * len(self.Hs))(*[h.s for h in self.Hs])
+        self._ca, self._ha = ca, ha
+        self.h = _vp()
+        wb = ctypes.c_size_t()
+        _check(lib().qsv_batch_plan_create(ca, ha, len(self.cs), dtype_code_, ctypes.byref(self.h),
+                                           ctypes.byref(wb)))
+        self.ninst = len(self.cs)
+        off = (ctypes.c_int64 * (self.ninst + 1))()
+        _check(lib().qsv_batch_offsets(self.h, off))
+        self.offsets = np.array(off[:], dtype=np.int64)
+        self.work = torch.empty((wb.value + 255) // 256 * 32, dtype=torch.float64, device=device)
+        self.device = device
+
+    def run(self, params_dev, energies=None, grads=None, stream=None):
+        import torch
+        energies = energies if energies is not None else torch.empty(
+            self.ninst, dtype=torch.float64, device=self.device)
+        grads = grads if grads is not None else torch.empty(
+            max(int(self.offsets[-1]), 1), dtype=torch.float64, device=self.device)
+        _check(lib().qsv_batch_run(self.h, _ptr(params_dev), _ptr(self.work), _ptr(energies),
+                                   _ptr(grads), _stream(stream)))
+        return energies, grads
+
+    def tune(self, params_dev, energies, grads, stream=None):
+        chosen = (ctypes.c_int * 2)()
+        _check(lib().qsv_batch_tune(self.h, _ptr(params_dev), _ptr(self.work), _ptr(energies),
+                                    _ptr(grads), _stream(stream), chosen))
+        return chosen[0], chosen[1]
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            _lib.qsv_batch_plan_destroy(self.h)

@@ -1,0 +1,122 @@
+"""Batched energies and adjoint gradients (one persistent launch) against the
+oracle's adjoint, instance by instance, for every tile shape the autotuner may
+pick; plus the tuner itself and a sample of the full 1024-instance workload."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {1: ["12,512", "12,256", "11,256", "11,512", "13,1024", "13,512"],
+          2: ["11,512", "11,256", "10,256", "12,1024", "12,512"]}
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2202_07017_amd import qsv
+    qsv.lib()
+    return qsv
+
+
+def mixed_instances(seed, count, nmin, nmax):
+    """Ansatz instances plus instances with fixed, controlled and X/Y/Z-rotation
+    gates and Y / XZ Pauli terms."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        if j % 2 == 0:
+            c = W.hea(n, int(rng.integers(1, 4)))
+            H = W.tfim_chain(n)
+        else:
+            ops, np_ = [], 0
+            for _ in range(3 * n):
+                kind = rng.choice(["rx", "ry", "rz", "h", "x", "matrix", "crz", "ccx"])
+                qs = [int(v) for v in rng.choice(n, 3, replace=False)]
+                if kind in ("rx", "ry", "rz"):
+                    ops.append(W.Op(kind, (qs[0],), param=np_)); np_ += 1
+                elif kind == "crz":
+                    ops.append(W.Op("rz", (qs[0],), controls=(qs[1],), param=np_)); np_ += 1
+                elif kind == "ccx":
+                    ops.append(W.Op("x", (qs[0],), controls=(qs[1], qs[2])))
+                elif kind == "matrix":
+                    ops.append(W.Op("matrix", (qs[0],), matrix=W.haar_unitary(rng, 2)))
+                else:
+                    ops.append(W.Op(kind, (qs[0],)))
+            c = W.Circuit(n, ops, np_)
+            H = W.pauli_sum(n, [("Y", (0,), 0.5), ("XZ", (1, n - 1), -0.8), ("ZZ", (0, 2), 1.2),
+                                ("X", (n - 1,), 0.3)])
+        out.append(W.BatchInstance(c, rng.uniform(0, 2 * np.pi, c.nparams), H))
+    return out
+
+
+def check_batch(q, orc, insts, code, shape, tol_e, tol_g, refs=None):
+    import torch
+    if shape:
+        os.environ["QSV_BATCH_SHAPE"] = shape
+    try:
+        plan = q.BatchPlan(insts, code)
+    finally:
+        os.environ.pop("QSV_BATCH_SHAPE", None)
+    params = torch.from_numpy(np.concatenate([i.params for i in insts])).cuda()
+    e, g = plan.run(params)
+    e, g = e.cpu().numpy(), g.cpu().numpy()
+    for j, inst in enumerate(insts):
+        E_ref, g_ref = refs[j] if refs else orc.adjoint(inst.circuit, inst.params, inst.hamiltonian)
+        gj = g[plan.offsets[j]:plan.offsets[j + 1]]
+        assert abs(e[j] - E_ref) <= tol_e, (j, inst.circuit.n, e[j], E_ref)
+        if len(gj):
+            assert np.max(np.abs(gj - g_ref)) <= tol_g, (j, inst.circuit.n, np.max(np.abs(gj - g_ref)))
+    return plan, params, e, g
+
+
+@pytest.mark.parametrize("code", [1, 2])
+def test_batch_every_shape(q, orc, code):
+    insts = mixed_instances(11 + code, 14, 3, 14)
+    refs = [orc.adjoint(i.circuit, i.params, i.hamiltonian) for i in insts]
+    for shape in SHAPES[code]:
+        say("batch", code, shape)
+        check_batch(q, orc, insts, code, shape, 1e-10 if code == 2 else 2e-4,
+                    1e-9 if code == 2 else 2e-4, refs)
+
+
+def test_batch_tune_and_replay(q, orc):
+    import torch
+    insts = mixed_instances(5, 20, 4, 15)
+    plan, params, e, g = check_batch(q, orc, insts, 2, None, 1e-10, 1e-9)
+    en = torch.empty(plan.ninst, dtype=torch.float64, device="cuda")
+    gr = torch.empty(max(int(plan.offsets[-1]), 1), dtype=torch.float64, device="cuda")
+    say("batch tune")
+    m, t = plan.tune(params, en, gr)
+    assert (str(m) + "," + str(t)) in SHAPES[2]
+    for rep in range(3):
+        e2, g2 = plan.run(params, en, gr)
+        assert np.array_equal(e2.cpu().numpy(), e) and np.array_equal(g2.cpu().numpy()[:len(g)], g)
+
+
+def test_batch_full_workload_sample(q, orc):
+    """The 1024-instance workload (n ~ U{12..22}, L ~ U{2..10}, complex64): all
+    instances with n <= 13 and three larger ones checked against the oracle."""
+    import torch
+    insts = W.batched_hea()
+    say("batch full")
+    plan = q.BatchPlan(insts, 1)
+    params = torch.from_numpy(np.concatenate([i.params for i in insts])).cuda()
+    e, g = plan.run(params)
+    e, g = e.cpu().numpy(), g.cpu().numpy()
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
+    picks = [j for j, i in enumerate(insts) if i.circuit.n <= 13]
+    picks += [j for j, i in enumerate(insts) if i.circuit.n in (16, 18)][:2]
+    picks += [j for j, i in enumerate(insts) if i.circuit.n == 20][:1]
+    for j in picks:
+        inst = insts[j]
+        E_ref, g_ref = orc.adjoint(inst.circuit, inst.params, inst.hamiltonian)
+        gj = g[plan.offsets[j]:plan.offsets[j + 1]]
+        assert abs(e[j] - E_ref) <= 2e-4 * inst.circuit.n, (j, inst.circuit.n)
+        assert np.max(np.abs(gj - g_ref)) <= 2e-4 * inst.circuit.n, (j, inst.circuit.n)
