@@ -16,6 +16,7 @@
 
 #include "qsv.h"
 #include "qsv_internal.h"
+#include "qsv_expect.h"
 #include "qsv_host.h"
 
 using namespace qsv;
@@ -517,26 +518,177 @@ void group_terms(const qsv_pauli_sum* H, std::vector<TermChunk>& diag,
     }
 }
 
+// Split a Pauli sum into tiled passes (n >= kTileQubits).  Pass 0 uses the
+// low 12 qubits and takes every diagonal term plus every term whose x mask
+// lies there; later passes use qubits [0, L) with L >= 6 plus up to 12 - L
+// higher qubits chosen greedily from the x masks left.  A term whose x mask
+// has more than 6 qubits above 5 goes to `leftover` (per-mask pair kernel).
+void plan_tiles(const qsv_pauli_sum* H, int n, std::vector<TileExpK>& out,
+                std::vector<std::pair<uint64_t, TermChunk>>& leftover)
+{
+    struct T {
+        uint64_t x, z;
+        double c;
+        int ylo;
+    };
+    std::vector<T> all;
+    for (int j = 0; j < H->nterms; ++j)
+        all.push_back(T{H->x_mask[j], H->z_mask[j], H->coeff[j],
+                        __builtin_popcountll(H->x_mask[j] & H->z_mask[j]) & 3});
+    std::vector<std::pair<uint32_t, std::vector<T>>> passes;  // (tile mask, terms)
+    const uint64_t low12 = (1ull << kTileQubits) - 1;
+    std::vector<T> p0, rest;
+    for (const T& t : all)
+        (((t.x & ~low12) == 0) ? p0 : rest).push_back(t);
+    passes.push_back({(uint32_t)low12, p0});
+    std::vector<bool> used(rest.size(), false);
+    size_t left = rest.size();
+    while (left > 0) {
+        uint64_t Hm = 0;
+        std::vector<T> take;
+        for (size_t j = 0; j < rest.size(); ++j) {
+            if (used[j])
+                continue;
+            const uint64_t hb = rest[j].x & ~0x3Full;
+            if (__builtin_popcountll(Hm | hb) <= kTileQubits - 6) {
+                Hm |= hb;
+                take.push_back(rest[j]);
+                used[j] = true;
+                --left;
+            }
+        }
+        if (take.empty()) {  // the first unused term cannot fit any tile
+            for (size_t j = 0; j < rest.size(); ++j)
+                if (!used[j]) {
+                    TermChunk tc{};
+                    tc.nt = 1;
+                    tc.z[0] = rest[j].z;
+                    tc.c[0] = rest[j].c;
+                    tc.ylo[0] = rest[j].ylo;
+                    leftover.push_back({rest[j].x, tc});
+                    used[j] = true;
+                    --left;
+                    break;
+                }
+            continue;
+        }
+        uint64_t B = 0x3Full | Hm;
+        for (int b = 6; b < n && __builtin_popcountll(B) < kTileQubits; ++b)
+            B |= 1ull << b;
+        passes.push_back({(uint32_t)B, take});
+    }
+    for (auto& pr : passes) {
+        const uint64_t B = pr.first;
+        std::vector<int> pos;
+        for (int b = 0; b < 64; ++b)
+            if ((B >> b) & 1)
+                pos.push_back(b);
+        auto compress = [&](uint64_t v) {
+            uint32_t o = 0;
+            for (size_t j = 0; j < pos.size(); ++j)
+                if ((v >> pos[j]) & 1)
+                    o |= 1u << j;
+            return o;
+        };
+        int L = 0;
+        while (L < (int)pos.size() && pos[L] == L)
+            ++L;
+        std::vector<XTerm> str, tab, pairs;
+        for (const T& t : pr.second) {
+            XTerm x{};
+            x.z = t.z;
+            x.c = t.c;
+            x.zloc = compress(t.z);
+            x.ylo = (int16_t)t.ylo;
+            if (t.x == 0) {
+                x.kind = 0;
+                const bool lo = (x.zloc & 63) != 0, hi = (x.zloc >> 6) != 0;
+                x.dpart = (int8_t)(lo && hi ? 3 : (hi ? 2 : 1));
+                (x.dpart == 3 ? str : tab).push_back(x);
+            } else {
+                x.xloc = compress(t.x);
+                x.hloc = 1u << (31 - __builtin_clz(x.xloc));
+                x.kind = (int8_t)((t.z == 0 && t.ylo == 0) ? 2 : 1);
+                pairs.push_back(x);
+            }
+        }
+        // launches of <= kMaxTileTerms terms: straddlers and table terms ride
+        // with the first launch(es), pair terms fill the rest
+        std::vector<XTerm> diag = str;
+        const int nstr_total = (int)str.size();
+        diag.insert(diag.end(), tab.begin(), tab.end());
+        size_t di = 0, pi = 0;
+        bool first = true;
+        while (first || di < diag.size() || pi < pairs.size()) {
+            first = false;
+            TileExpK k{};
+            k.ntiles = 1ull << (n - kTileQubits);
+            k.ins = make_ins(pos, 0);
+            k.L = L;
+            const int nch = 1 << (kTileQubits - L);
+            for (int c = 0; c < nch; ++c) {
+                uint64_t o = 0;
+                for (int m = 0; m < kTileQubits - L; ++m)
+                    if ((c >> m) & 1)
+                        o |= 1ull << pos[L + m];
+                k.choff[c] = o;
+            }
+            int nt = 0;
+            int nstr = 0;
+            while (di < diag.size() && nt < kMaxTileTerms) {
+                if ((int)di < nstr_total)
+                    ++nstr;
+                k.t[nt++] = diag[di++];
+            }
+            k.nstr = nstr;
+            k.pstart = nt;
+            k.ndiag = nt;
+            while (pi < pairs.size() && nt < kMaxTileTerms)
+                k.t[nt++] = pairs[pi++];
+            k.nt = nt;
+            out.push_back(k);
+        }
+    }
+}
+
 qsv_status enqueue_expectation(const void* psi, int n, int dt, const qsv_pauli_sum* H, double* out,
                                double* work, int ncomp, hipStream_t s)
 {
-    std::vector<TermChunk> diag;
-    std::vector<std::pair<uint64_t, TermChunk>> pairs;
-    group_terms(H, diag, pairs);
     int acc = 0;
-    for (const TermChunk& t : diag) {
-        hipError_t e = launch_expect_diag(psi, n, dt, t, work, acc, s);
-        if (e != hipSuccess)
-            return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
-        acc = 1;
+    const int nb = reduce_blocks(n, dt);
+    if (n >= kTileQubits) {
+        std::vector<TileExpK> tiles;
+        std::vector<std::pair<uint64_t, TermChunk>> leftover;
+        plan_tiles(H, n, tiles, leftover);
+        for (const TileExpK& k : tiles) {
+            hipError_t e = launch_tile_pass(k, psi, nullptr, dt, false, work, nb, acc, s);
+            if (e != hipSuccess)
+                return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
+            acc = 1;
+        }
+        for (const auto& pr : leftover) {
+            hipError_t e = launch_expect_pair(psi, n, dt, pr.first, pr.second, work, acc, s);
+            if (e != hipSuccess)
+                return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
+        }
+    } else {
+        std::vector<TermChunk> diag;
+        std::vector<std::pair<uint64_t, TermChunk>> pairs;
+        group_terms(H, diag, pairs);
+        for (const TermChunk& t : diag) {
+            hipError_t e = launch_expect_diag(psi, n, dt, t, work, acc, s);
+            if (e != hipSuccess)
+                return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
+            acc = 1;
+        }
+        for (const auto& pr : pairs) {
+            hipError_t e = launch_expect_pair(psi, n, dt, pr.first, pr.second, work, acc, s);
+            if (e != hipSuccess)
+                return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
+            acc = 1;
+        }
     }
-    for (const auto& pr : pairs) {
-        hipError_t e = launch_expect_pair(psi, n, dt, pr.first, pr.second, work, acc, s);
-        if (e != hipSuccess)
-            return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
-        acc = 1;
-    }
-    hipError_t e = launch_finalize(work, reduce_blocks(n, dt), ncomp, out, s);
+    hipError_t e = launch_finalize(work, nb, ncomp, out, s);
     if (e != hipSuccess)
         return fail(QSV_ERR_HIP, "finalize launch: %s", hipGetErrorString(e));
     return QSV_OK;
@@ -545,6 +697,24 @@ qsv_status enqueue_expectation(const void* psi, int n, int dt, const qsv_pauli_s
 qsv_status enqueue_hpsi(const void* psi, void* lam, int n, int dt, const qsv_pauli_sum* H,
                         hipStream_t s)
 {
+    if (n >= kTileQubits) {
+        std::vector<TileExpK> tiles;
+        std::vector<std::pair<uint64_t, TermChunk>> leftover;
+        plan_tiles(H, n, tiles, leftover);
+        int acc = 0;
+        for (const TileExpK& k : tiles) {
+            hipError_t e = launch_tile_pass(k, psi, lam, dt, true, nullptr, 0, acc, s);
+            if (e != hipSuccess)
+                return fail(QSV_ERR_HIP, "H psi launch: %s", hipGetErrorString(e));
+            acc = 1;
+        }
+        for (const auto& pr : leftover) {
+            hipError_t e = launch_hpsi_pair(psi, lam, n, dt, pr.first, pr.second, s);
+            if (e != hipSuccess)
+                return fail(QSV_ERR_HIP, "H psi launch: %s", hipGetErrorString(e));
+        }
+        return QSV_OK;
+    }
     std::vector<TermChunk> diag;
     std::vector<std::pair<uint64_t, TermChunk>> pairs;
     group_terms(H, diag, pairs);

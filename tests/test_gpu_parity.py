@@ -196,6 +196,29 @@ def test_observables(q, orc):
             assert abs(ip[0] - ref.real) <= 1e-12 and abs(ip[1] - ref.imag) <= 1e-12
 
 
+@pytest.mark.parametrize("n", [13, 14, 17, 20])
+def test_observables_tiled(q, orc, n):
+    """n >= 12 runs the tiled passes: pass 0 on the low 12 qubits, further
+    passes on high-qubit tiles, and the pair kernel for x masks wider than a
+    tile (random Pauli strings)."""
+    rng = np.random.default_rng(300 + n)
+    for name in DTYPES:
+        psi = rand_state(n, rng, name)
+        d = to_gpu(psi, name)
+        Hs = [W.tfim_chain(n, 0.9), W.xxz_chain(n, -0.6), W.random_pauli_sum(n, 40, seed=n),
+              W.maxcut(n, [(0, n - 1), (3, 9), (n - 2, 1)])]
+        for H in Hs:
+            say("tiled expectation", name, n, len(H.coeff))
+            e = q.qsv_expectation(d, H).cpu().numpy()
+            ref = orc.expect(psi, H)
+            scale = np.sum(np.abs(H.coeff))
+            assert abs(e[0] - ref.real) <= 1e-10 * scale, (e, ref)
+            assert abs(e[1]) <= 1e-10 * scale
+            out = to_gpu(np.zeros_like(psi), name)
+            q.qsv_apply_pauli_sum(d, out, H)
+            check_close(to_np(out) / scale, orc.apply_hamiltonian(psi, H) / scale, name, "H psi")
+
+
 def test_plan_random_circuit(q, orc):
     """Random U(2) layers with CZ pairs (n = 20, depth 10): every fusion width
     and graph replay against the oracle, plus <Z_0>."""
