@@ -12,95 +12,18 @@
 #include "qsv.h"
 #include "qsv_batch.h"
 #include "qsv_host.h"
+#include "qsv_tileprog.h"
 
 using namespace qsv;
 
 namespace {
 
-struct HOp {
-    int kind;  // 0 fixed matrix, 5/6/7 rotation
-    int t, nc, c0, c1;
-    int param;
-    int mat;
-};
-
 struct HInst {
     int n = 0;
     int nparam = 0;
-    std::vector<HOp> ops;
+    std::vector<HGate> ops;
     std::vector<BTerm> terms;
 };
-
-struct HPass {
-    uint32_t bmask;
-    std::vector<int> ops;
-};
-
-// Schedule the gates into passes whose qubits fit a tile of m qubits.  A
-// pass takes every remaining gate, in circuit order, whose qubits are tile
-// qubits and that no unscheduled earlier gate blocks (a gate blocks its
-// qubits for all later gates), so one pass can cover several layers on the
-// tile's qubits.  Tile qubits: 0, 1, 2 (contiguous 64-byte chunks), then the
-// qubits of the remaining gates in order of first appearance.
-std::vector<HPass> schedule(const HInst& I, int m)
-{
-    std::vector<HPass> out;
-    const int nops = (int)I.ops.size();
-    auto qubits = [&](const HOp& o) {
-        uint32_t q = 1u << o.t;
-        if (o.nc > 0)
-            q |= 1u << o.c0;
-        if (o.nc > 1)
-            q |= 1u << o.c1;
-        return q;
-    };
-    if (I.n <= m) {
-        for (int s = 0; s < nops; s += kMaxPassOps) {
-            HPass p{(1u << I.n) - 1, {}};
-            for (int o = s; o < nops && o < s + kMaxPassOps; ++o)
-                p.ops.push_back(o);
-            out.push_back(p);
-        }
-        return out;
-    }
-    std::vector<bool> done(nops, false);
-    int left = nops;
-    while (left > 0) {
-        uint32_t B = 0x7;
-        for (int o = 0; o < nops && __builtin_popcount(B) < m; ++o) {
-            if (done[o])
-                continue;
-            uint32_t q = qubits(I.ops[o]) & ~B;
-            while (q && __builtin_popcount(B) < m) {
-                B |= q & (~q + 1);
-                q &= q - 1;
-            }
-        }
-        for (int b = 0; b < I.n && __builtin_popcount(B) < m; ++b)
-            B |= 1u << b;
-        HPass p{B, {}};
-        uint32_t blocked = 0;
-        for (int o = 0; o < nops; ++o) {
-            if (done[o])
-                continue;
-            const uint32_t q = qubits(I.ops[o]);
-            if ((q & ~B) == 0 && (q & blocked) == 0 && (int)p.ops.size() < kMaxPassOps) {
-                p.ops.push_back(o);
-                done[o] = true;
-                --left;
-            } else {
-                blocked |= q;
-            }
-        }
-        out.push_back(p);
-    }
-    return out;
-}
-
-int local_bit(uint32_t B, int q)
-{
-    return __builtin_popcount(B & ((1u << q) - 1));
-}
 
 }  // namespace
 
@@ -117,7 +40,7 @@ struct qsv_batch_plan {
     int m = 0, threads = 0, blocks = 0;
     int cfg_m = -1;
     DevPack dev;
-    size_t o_inst = 0, o_order = 0, o_pass = 0, o_pops = 0, o_mats = 0, o_terms = 0;
+    size_t o_inst = 0, o_order = 0, o_pass = 0, o_steps = 0, o_pops = 0, o_mats = 0, o_terms = 0;
     GraphCache graph;
     std::string key;
 };
@@ -133,37 +56,30 @@ qsv_status configure(qsv_batch_plan* P, int m, int threads)
     P->graph.reset();
     P->dev.reset();
     std::vector<BInst> bi(P->ninst);
-    std::vector<BPass> passes;
-    std::vector<BPOp> pops;
+    std::vector<DPass> passes;
+    std::vector<DStep> steps;
+    std::vector<DOp> dops;
     std::vector<BTerm> terms;
     for (int i = 0; i < P->ninst; ++i) {
         const HInst& I = P->inst[i];
-        std::vector<HPass> hp = schedule(I, m);
+        TileProgram tp;
+        compile_tile_program(I.ops, I.n, m, tp);
         BInst& b = bi[i];
         b.n = I.n;
-        b.npass = (int)hp.size();
+        b.npass = (int)tp.passes.size();
         b.pass_off = (int)passes.size();
         b.nterm = (int)I.terms.size();
         b.term_off = (int)terms.size();
         b.nparam = I.nparam;
         b.param_off = P->param_off[i];
         b.work_off = P->work_off[i];
-        for (const HPass& p : hp) {
-            BPass q{p.bmask, (int)p.ops.size(), (int)pops.size(), 0};
-            for (int o : p.ops) {
-                const HOp& h = I.ops[o];
-                BPOp x{};
-                x.kind = (uint8_t)h.kind;
-                x.tloc = (uint8_t)local_bit(p.bmask, h.t);
-                x.nc = (uint8_t)h.nc;
-                x.c0 = (uint8_t)(h.nc > 0 ? local_bit(p.bmask, h.c0) : 0);
-                x.c1 = (uint8_t)(h.nc > 1 ? local_bit(p.bmask, h.c1) : 0);
-                x.param = h.param;
-                x.mat = h.mat;
-                pops.push_back(x);
-            }
+        for (DPass q : tp.passes) {
+            q.step_off += (int)steps.size();
+            q.op_off += (int)dops.size();
             passes.push_back(q);
         }
+        steps.insert(steps.end(), tp.steps.begin(), tp.steps.end());
+        dops.insert(dops.end(), tp.ops.begin(), tp.ops.end());
         terms.insert(terms.end(), I.terms.begin(), I.terms.end());
     }
     auto bytes_of = [](const void* p, size_t n) {
@@ -172,8 +88,9 @@ qsv_status configure(qsv_batch_plan* P, int m, int threads)
     };
     P->o_inst = P->dev.add(bytes_of(bi.data(), bi.size() * sizeof(BInst)));
     P->o_order = P->dev.add(bytes_of(P->order.data(), P->order.size() * sizeof(int)));
-    P->o_pass = P->dev.add(bytes_of(passes.data(), passes.size() * sizeof(BPass)));
-    P->o_pops = P->dev.add(bytes_of(pops.data(), std::max<size_t>(pops.size(), 1) * sizeof(BPOp)));
+    P->o_pass = P->dev.add(bytes_of(passes.data(), passes.size() * sizeof(DPass)));
+    P->o_steps = P->dev.add(bytes_of(steps.data(), std::max<size_t>(steps.size(), 1) * sizeof(DStep)));
+    P->o_pops = P->dev.add(bytes_of(dops.data(), std::max<size_t>(dops.size(), 1) * sizeof(DOp)));
     P->o_mats = P->dev.add(bytes_of(P->mats.data(), std::max<size_t>(P->mats.size(), 8) * sizeof(double)));
     P->o_terms = P->dev.add(bytes_of(terms.data(), terms.size() * sizeof(BTerm)));
     qsv_status st = P->dev.commit();
@@ -197,8 +114,9 @@ qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* 
     a.order = static_cast<const int*>(P->dev.at(P->o_order));
     a.ninst = P->ninst;
     a.m = P->m;
-    a.passes = static_cast<const BPass*>(P->dev.at(P->o_pass));
-    a.pops = static_cast<const BPOp*>(P->dev.at(P->o_pops));
+    a.passes = static_cast<const DPass*>(P->dev.at(P->o_pass));
+    a.steps = static_cast<const DStep*>(P->dev.at(P->o_steps));
+    a.ops = static_cast<const DOp*>(P->dev.at(P->o_pops));
     a.mats = static_cast<const double*>(P->dev.at(P->o_mats));
     a.terms = static_cast<const BTerm*>(P->dev.at(P->o_terms));
     a.params = params;
@@ -215,8 +133,8 @@ qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* 
 std::vector<std::pair<int, int>> candidates(int dt)
 {
     if (dt == QSV_C64)
-        return {{12, 512}, {12, 256}, {11, 256}, {11, 512}, {13, 1024}, {13, 512}};
-    return {{11, 512}, {11, 256}, {10, 256}, {12, 1024}, {12, 512}};
+        return {{12, 512}, {12, 256}, {11, 256}, {11, 512}, {13, 512}};
+    return {{11, 512}, {11, 256}, {10, 256}, {12, 512}};
 }
 
 bool read_cache(const std::string& key, int* m, int* threads)
@@ -301,7 +219,7 @@ qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* 
                 return fail(QSV_ERR_UNSUPPORTED,
                             "instance %d op %d: batches take single-target gates with <= 2 controls",
                             i, o);
-            HOp x{};
+            HGate x{};
             x.t = op.targets[0];
             x.nc = op.c;
             x.c0 = op.c > 0 ? op.controls[0] : 0;
@@ -351,7 +269,7 @@ qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* 
     read_cache(P->key, &m, &threads);
     if (const char* e = getenv("QSV_BATCH_SHAPE")) {  // "m,threads" (tests of every shape)
         int a = 0, b = 0;
-        if (sscanf(e, "%d,%d", &a, &b) == 2 && a >= 3 && a <= 14 && (b == 256 || b == 512 || b == 1024)) {
+        if (sscanf(e, "%d,%d", &a, &b) == 2 && a >= 3 && a <= 14 && (b == 256 || b == 512)) {
             m = a;
             threads = b;
         }

@@ -12,6 +12,8 @@
 #include "qsv.h"
 #include "qsv_host.h"
 #include "qsv_internal.h"
+#include "qsv_tileprog.h"
+#include "qsv_tpass.h"
 
 using namespace qsv;
 
@@ -319,6 +321,12 @@ struct qsv_adjoint_plan {
     size_t off_lam = 0, off_part = 0, off_red = 0, work_bytes = 0;
     GraphCache graph;
     GraphCache egraph;
+    // cache-blocked mode (every gate single-target with <= 2 controls)
+    bool tiled = false;
+    TileProgram tp;
+    int tm = 0;       // tile qubits
+    int tblocks = 0;  // blocks per pass launch (= partial columns)
+    size_t o_steps = 0, o_ops = 0, o_mats = 0;
 };
 
 namespace {
@@ -472,6 +480,81 @@ qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum*
     P->hc.assign(H->coeff, H->coeff + H->nterms);
     P->H = qsv_pauli_sum{H->nterms, P->hx.data(), P->hz.data(), P->hc.data()};
 
+    bool tileable = getenv("QSV_NO_TILES") == nullptr || getenv("QSV_NO_TILES")[0] != '1';
+    for (int o = 0; o < circ->nops && tileable; ++o) {
+        const qsv_op& op = circ->ops[o];
+        tileable = op.k == 1 && op.c <= 2 && op.kind != QSV_OP_SWAP;
+        if (tileable && op.kind == QSV_OP_MATRIX && !is_unitary(op_matrix(op, 0.0), 2))
+            return fail(QSV_ERR_ARG, "op %d: MATRIX is not unitary (the adjoint uncomputes with "
+                                     "G^dagger)", o);
+    }
+    if (tileable) {
+        std::vector<HGate> gates;
+        std::vector<double> mats;
+        for (int o = 0; o < circ->nops; ++o) {
+            const qsv_op& op = circ->ops[o];
+            HGate g{};
+            g.t = op.targets[0];
+            g.nc = op.c;
+            g.c0 = op.c > 0 ? op.controls[0] : 0;
+            g.c1 = op.c > 1 ? op.controls[1] : 0;
+            g.param = -1;
+            g.mat = -1;
+            if (is_rotation(op.kind)) {
+                g.kind = op.kind;
+                g.param = op.param;
+            } else {
+                g.kind = 0;
+                g.mat = (int)(mats.size() / 8);
+                std::vector<double> m = op_matrix(op, 0.0);
+                mats.insert(mats.end(), m.begin(), m.end());
+            }
+            gates.push_back(g);
+        }
+        P->tm = std::min(n, dt == QSV_C64 ? 12 : 11);
+        compile_tile_program(gates, n, P->tm, P->tp);
+        const int res = tpass_resident_blocks(dt, P->tm, true);
+        if (res <= 0)
+            return fail(QSV_ERR_UNSUPPORTED, "tile pass kernel does not fit this device");
+        const uint64_t ntiles = 1ull << (n - P->tm);
+        P->tblocks = (int)std::min<uint64_t>(ntiles, (uint64_t)res);
+        P->tiled = true;
+        P->nslots = (int)P->tp.slot_param.size();
+        auto bytes_of = [](const void* p, size_t nb) {
+            return std::vector<unsigned char>(static_cast<const unsigned char*>(p),
+                                              static_cast<const unsigned char*>(p) + nb);
+        };
+        P->o_steps = P->dev.add(bytes_of(P->tp.steps.data(), std::max<size_t>(P->tp.steps.size(), 1) * sizeof(DStep)));
+        P->o_ops = P->dev.add(bytes_of(P->tp.ops.data(), std::max<size_t>(P->tp.ops.size(), 1) * sizeof(DOp)));
+        if (mats.empty())
+            mats.assign(8, 0.0);
+        P->o_mats = P->dev.add(bytes_of(mats.data(), mats.size() * sizeof(double)));
+        std::vector<std::vector<int>> sl(circ->nparams);
+        for (int sidx = 0; sidx < P->nslots; ++sidx)
+            sl[P->tp.slot_param[sidx]].push_back(sidx);
+        std::vector<int> csr(circ->nparams + 1 + P->nslots + 1, 0);
+        int fill = 0;
+        for (int p = 0; p < circ->nparams; ++p) {
+            csr[p] = fill;
+            for (int v : sl[p])
+                csr[circ->nparams + 1 + fill++] = v;
+        }
+        csr[circ->nparams] = fill;
+        P->off_csr = P->dev.add(bytes_of(csr.data(), csr.size() * sizeof(int)));
+        if ((st = P->dev.commit()))
+            return st;
+        const size_t sb = amp_bytes(dt) << n;
+        auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+        P->off_lam = up(sb);
+        P->off_part = P->off_lam + up(sb);
+        P->off_red = P->off_part +
+                     up(sizeof(double) * (size_t)std::max(P->nslots, 1) * (size_t)P->tblocks);
+        P->work_bytes = P->off_red + kReduceWorkBytes;
+        *work_bytes = P->work_bytes;
+        *plan = P.release();
+        return ok();
+    }
+
     std::vector<Item> items = fuse_ops(circ, fuse_k, true);
     std::vector<std::vector<int>> slots_of(circ->nparams);
     std::vector<long long> rev_off;
@@ -534,6 +617,47 @@ qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum*
     return ok();
 }
 
+static qsv_status adjoint_enqueue_tiled(qsv_adjoint_plan* P, const double* params, void* psi,
+                                        void* lam, double* part, double* red, double* energy,
+                                        double* grad, bool with_grad, hipStream_t s)
+{
+    TPassArgs a{};
+    a.steps = static_cast<const DStep*>(P->dev.at(P->o_steps));
+    a.ops = static_cast<const DOp*>(P->dev.at(P->o_ops));
+    a.mats = static_cast<const double*>(P->dev.at(P->o_mats));
+    a.params = params;
+    a.partials = part;
+    a.n = P->n;
+    a.m = P->tm;
+    for (const DPass& pass : P->tp.passes) {
+        a.pass = pass;
+        hipError_t e = launch_tpass(a, P->dt, false, psi, nullptr, P->tblocks, s);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "tile pass launch: %s", hipGetErrorString(e));
+    }
+    if (!with_grad)
+        return enqueue_expectation(psi, P->n, P->dt, &P->H, energy, red, 1, s);
+    qsv_status st = enqueue_hpsi(psi, lam, P->n, P->dt, &P->H, s);
+    if (st)
+        return st;
+    hipError_t e = launch_inner(psi, lam, P->n, P->dt, red, 0, s);
+    if (e == hipSuccess)
+        e = launch_finalize(red, reduce_blocks(P->n, P->dt), 1, energy, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "energy launch: %s", hipGetErrorString(e));
+    for (int p = (int)P->tp.passes.size() - 1; p >= 0; --p) {
+        a.pass = P->tp.passes[p];
+        e = launch_tpass(a, P->dt, true, psi, lam, P->tblocks, s);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "tile pass launch: %s", hipGetErrorString(e));
+    }
+    const int* csr = static_cast<const int*>(P->dev.at(P->off_csr));
+    e = launch_grad_finalize(part, P->tblocks, csr, csr + P->nparams + 1, P->nparams, grad, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "gradient finalize launch: %s", hipGetErrorString(e));
+    return QSV_OK;
+}
+
 static qsv_status adjoint_enqueue(qsv_adjoint_plan* P, const double* params, void* work,
                                   double* energy, double* grad, bool with_grad, hipStream_t s)
 {
@@ -545,6 +669,8 @@ static qsv_status adjoint_enqueue(qsv_adjoint_plan* P, const double* params, voi
     hipError_t e = launch_init_basis(psi, P->n, P->dt, 0, s);
     if (e != hipSuccess)
         return fail(QSV_ERR_HIP, "init launch: %s", hipGetErrorString(e));
+    if (P->tiled)
+        return adjoint_enqueue_tiled(P, params, psi, lam, part, red, energy, grad, with_grad, s);
     qsv_status st = enqueue_launches(P->fwd, psi, params, s);
     if (st)
         return st;

@@ -11,8 +11,8 @@ from gpu_util import say
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = {1: ["12,512", "12,256", "11,256", "11,512", "13,1024", "13,512"],
-          2: ["11,512", "11,256", "10,256", "12,1024", "12,512"]}
+SHAPES = {1: ["12,512", "12,256", "11,256", "11,512", "13,512"],
+          2: ["11,512", "11,256", "10,256", "12,512"]}
 
 
 @pytest.fixture(scope="module")

@@ -306,6 +306,30 @@ def test_adjoint_gradient(q, orc):
                 assert abs(en - E_ref) < (1e-11 if name == "c128" else 1e-4)
 
 
+@pytest.mark.parametrize("n", [14, 16])
+def test_adjoint_tiled_multi_tile(q, orc, n):
+    """Cache-blocked adjoint (several tiles per pass, staircase passes) and the
+    per-gate adjoint (QSV_NO_TILES=1) against the oracle's adjoint."""
+    import torch
+    circ, H = W.hea(n, 3), W.tfim_chain(n)
+    circ.ops.insert(5, W.Op("rx", (n - 1,), controls=(2,), param=1))
+    p = W.random_params(circ.nparams, 19 + n)
+    E_ref, g_ref = orc.adjoint(circ, p, H)
+    for name in DTYPES:
+        for tiles in ["1", "0"]:
+            os.environ["QSV_NO_TILES"] = "0" if tiles == "1" else "1"
+            try:
+                say("adjoint tiled" if tiles == "1" else "adjoint per-gate", name, n)
+                plan = q.AdjointPlan(circ, H, 1 if name == "c64" else 2, 5)
+            finally:
+                os.environ.pop("QSV_NO_TILES", None)
+            e, g = plan.run(torch.from_numpy(p).cuda())
+            e, g = e.cpu().numpy()[0], g.cpu().numpy()
+            tol = (1e-10, 1e-9) if name == "c128" else (2e-4 * n, 2e-4 * n)
+            assert abs(e - E_ref) < tol[0], (e, E_ref)
+            assert np.max(np.abs(g - g_ref)) < tol[1], np.max(np.abs(g - g_ref))
+
+
 def test_adjoint_autograd(q, orc):
     import torch
     circ, H = W.hea(5, 2), W.tfim_chain(5)
