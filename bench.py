@@ -237,7 +237,7 @@ def batched_leg(qsv, W, torch, np, dev):
         unfused += 6.0 * len(i.circuit.ops) * N * 8
     return {"workload": "1024 HEA instances, n~U{12..22}, L~U{2..10}, TFIM, complex64",
             "instance_grads_per_s": round(plan.ninst / t, 1), "ms_per_batch": round(t * 1e3, 2),
-            "tile_qubits_and_threads": list(shape),
+            "tuned_tile_qubits_threads_split": list(shape),
             "unfused_hbm_reference_ms": round(unfused / HBM_PEAK_GBS / 1e6, 1)}
 
 

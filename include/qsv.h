@@ -270,13 +270,18 @@ qsv_status qsv_adjoint_gradient(const qsv_circuit* circ, const double* params_de
 typedef struct qsv_batch_plan qsv_batch_plan;
 
 /* Many independent (circuit, Hamiltonian) instances of uneven size
- * (n <= QSV_BATCH_MAX_QUBITS, rotation circuits as for the adjoint plan)
- * evaluated together: energies and adjoint gradients of all instances in one
- * persistent kernel launch.  Instances whose two state vectors fit one
- * compute unit's LDS run entirely there; larger ones sweep their own region
- * of the workspace.  Parameters and gradients of instance i live at
- * offsets[i] .. offsets[i+1]-1 of the concatenated vectors
- * (qsv_batch_offsets).  *work_bytes = workspace size. */
+ * (n <= QSV_BATCH_MAX_QUBITS; single-target gates with at most 2 controls;
+ * rotations as for the adjoint plan) evaluated together: energies and adjoint
+ * gradients of all instances.  Instances below a split size run in one
+ * persistent kernel launch, one workgroup per instance, taken from a queue
+ * largest first: those whose two state vectors fit the workgroup's LDS tile
+ * stay there for the whole evaluation, the others stream cache-blocked tiles
+ * of their own workspace region.  Instances at or above the split size (16 or
+ * more qubits) run after it, one at a time across the whole GPU, with the
+ * cache-blocked adjoint.  The tile size, workgroup size and split size come
+ * from the autotuner (qsv_batch_tune) or its cache.  Parameters and
+ * gradients of instance i live at offsets[i] .. offsets[i+1]-1 of the
+ * concatenated vectors (qsv_batch_offsets).  *work_bytes = workspace size. */
 #define QSV_BATCH_MAX_QUBITS 24
 qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* Hs, int ninst,
                                  qsv_dtype dt, qsv_batch_plan** plan, size_t* work_bytes);
@@ -288,10 +293,11 @@ qsv_status qsv_batch_offsets(const qsv_batch_plan* plan, int64_t* offsets);
 qsv_status qsv_batch_run(qsv_batch_plan* plan, const double* params_dev, void* work,
                          double* energies_dev, double* grads_dev, void* stream);
 
-/* Autotuner: times candidate launch shapes (LDS-tier threshold, workgroup
- * size) on this batch with these inputs, keeps the fastest, and records it in
- * the JSON cache named by QSV_TUNE_CACHE (if set).  Synchronises the stream.
- * chosen (optional, host, 2 ints) receives (lds_max_qubits, threads). */
+/* Autotuner: times candidate shapes on this batch with these inputs (tile
+ * qubits = the largest instance kept wholly in LDS, workgroup size, then the
+ * split size of the large tier), keeps the fastest, and records it in the
+ * JSON cache named by QSV_TUNE_CACHE (if set).  Synchronises the stream.
+ * chosen (optional, host, 3 ints) receives (tile qubits, threads, split). */
 qsv_status qsv_batch_tune(qsv_batch_plan* plan, const double* params_dev, void* work,
                           double* energies_dev, double* grads_dev, void* stream, int* chosen);
 

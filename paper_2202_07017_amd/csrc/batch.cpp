@@ -36,9 +36,20 @@ struct qsv_batch_plan {
     std::vector<int> order;
     long long work_bytes = 0;
     std::vector<long long> work_off;
+    // large instances (n >= split) run one at a time across the whole GPU
+    std::vector<qsv_adjoint_plan*> sub;  // per instance with n >= kSplitMin, else nullptr
+    long long big_off = 0;               // shared workspace region of the large tier
+    int split = 99;
+    ~qsv_batch_plan()
+    {
+        for (qsv_adjoint_plan* p : sub)
+            if (p)
+                qsv_adjoint_plan_destroy(p);
+    }
     // configuration
     int m = 0, threads = 0, blocks = 0;
     int cfg_m = -1;
+    int nsmall = 0;
     DevPack dev;
     size_t o_inst = 0, o_order = 0, o_pass = 0, o_steps = 0, o_pops = 0, o_mats = 0, o_terms = 0;
     GraphCache graph;
@@ -48,11 +59,17 @@ struct qsv_batch_plan {
 namespace {
 
 constexpr int kWorkMinQubits = 11;  // instances with n >= this get a workspace region
+constexpr int kSplitMin = 16;       // smallest size the large tier may take
 
-qsv_status configure(qsv_batch_plan* P, int m, int threads)
+qsv_status configure(qsv_batch_plan* P, int m, int threads, int split)
 {
-    if (P->cfg_m == m && P->threads == threads && P->dev.mem)
+    if (P->cfg_m == m && P->threads == threads && P->split == split && P->dev.mem)
         return QSV_OK;
+    P->split = split;
+    std::vector<int> small;
+    for (int i : P->order)
+        if (P->inst[i].n < split || !P->sub[i])
+            small.push_back(i);
     P->graph.reset();
     P->dev.reset();
     std::vector<BInst> bi(P->ninst);
@@ -87,7 +104,8 @@ qsv_status configure(qsv_batch_plan* P, int m, int threads)
                                           static_cast<const unsigned char*>(p) + n);
     };
     P->o_inst = P->dev.add(bytes_of(bi.data(), bi.size() * sizeof(BInst)));
-    P->o_order = P->dev.add(bytes_of(P->order.data(), P->order.size() * sizeof(int)));
+    P->o_order = P->dev.add(bytes_of(small.data(), std::max<size_t>(small.size(), 1) * sizeof(int)));
+    P->nsmall = (int)small.size();
     P->o_pass = P->dev.add(bytes_of(passes.data(), passes.size() * sizeof(DPass)));
     P->o_steps = P->dev.add(bytes_of(steps.data(), std::max<size_t>(steps.size(), 1) * sizeof(DStep)));
     P->o_pops = P->dev.add(bytes_of(dops.data(), std::max<size_t>(dops.size(), 1) * sizeof(DOp)));
@@ -99,7 +117,7 @@ qsv_status configure(qsv_batch_plan* P, int m, int threads)
     const int res = batch_resident_blocks(P->dt, m, threads);
     if (res <= 0)
         return fail(QSV_ERR_UNSUPPORTED, "batch kernel does not fit (m = %d, %d threads)", m, threads);
-    P->blocks = std::min(res, P->ninst);
+    P->blocks = std::max(1, std::min(res, P->nsmall));
     P->m = m;
     P->threads = threads;
     P->cfg_m = m;
@@ -112,7 +130,7 @@ qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* 
     BatchArgs a{};
     a.inst = static_cast<const BInst*>(P->dev.at(P->o_inst));
     a.order = static_cast<const int*>(P->dev.at(P->o_order));
-    a.ninst = P->ninst;
+    a.ninst = P->nsmall;
     a.m = P->m;
     a.passes = static_cast<const DPass*>(P->dev.at(P->o_pass));
     a.steps = static_cast<const DStep*>(P->dev.at(P->o_steps));
@@ -124,9 +142,19 @@ qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* 
     a.energies = energies;
     a.work = static_cast<char*>(work);
     a.counter = static_cast<int*>(work);
-    hipError_t e = launch_batch(a, P->dt, P->threads, P->blocks, s);
-    if (e != hipSuccess)
-        return fail(QSV_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+    if (P->nsmall > 0) {
+        hipError_t e = launch_batch(a, P->dt, P->threads, P->blocks, s);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+    }
+    for (int i : P->order)
+        if (P->inst[i].n >= P->split && P->sub[i]) {
+            qsv_status st = adjoint_enqueue_direct(P->sub[i], params + P->param_off[i],
+                                                   static_cast<char*>(work) + P->big_off,
+                                                   energies + i, grads + P->param_off[i], s);
+            if (st)
+                return st;
+        }
     return QSV_OK;
 }
 
@@ -137,7 +165,12 @@ std::vector<std::pair<int, int>> candidates(int dt)
     return {{11, 512}, {11, 256}, {10, 256}, {12, 512}};
 }
 
-bool read_cache(const std::string& key, int* m, int* threads)
+std::vector<int> split_candidates()
+{
+    return {17, 19, 21, 99};
+}
+
+bool read_cache(const std::string& key, int* m, int* threads, int* split)
 {
     const char* path = getenv("QSV_TUNE_CACHE");
     if (!path)
@@ -149,17 +182,18 @@ bool read_cache(const std::string& key, int* m, int* threads)
         const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
         if (q0 == std::string::npos || q1 == std::string::npos || line.substr(q0 + 1, q1 - q0 - 1) != key)
             continue;
-        int a = 0, b = 0;
-        if (sscanf(line.c_str() + line.find('[', q1), "[%d, %d", &a, &b) == 2) {
+        int a = 0, b = 0, c = 0;
+        if (sscanf(line.c_str() + line.find('[', q1), "[%d, %d, %d", &a, &b, &c) == 3) {
             *m = a;
             *threads = b;
+            *split = c;
             return true;
         }
     }
     return false;
 }
 
-void write_cache(const std::string& key, int m, int threads, double ms)
+void write_cache(const std::string& key, int m, int threads, int split, double ms)
 {
     const char* path = getenv("QSV_TUNE_CACHE");
     if (!path)
@@ -173,7 +207,7 @@ void write_cache(const std::string& key, int m, int threads, double ms)
                 keep.push_back(line.back() == ',' ? line.substr(0, line.size() - 1) : line);
     }
     char buf[256];
-    snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %.3f]", key.c_str(), m, threads, ms);
+    snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %d, %.3f]", key.c_str(), m, threads, split, ms);
     keep.push_back(buf);
     std::ofstream o(path);
     o << "{\n";
@@ -255,6 +289,22 @@ qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* 
     }
     sig << "/" << std::hex << h;
     P->key = sig.str();
+    // the large tier: an adjoint plan per instance of >= kSplitMin qubits, all
+    // sharing one workspace region (they run one after another)
+    P->sub.assign(ninst, nullptr);
+    size_t big = 0;
+    for (int i = 0; i < ninst; ++i) {
+        if (P->inst[i].n < kSplitMin)
+            continue;
+        size_t wb = 0;
+        qsv_adjoint_plan* ap = nullptr;
+        if ((st = qsv_adjoint_plan_create(&circs[i], &Hs[i], dt, 5, &ap, &wb)))
+            return fail(st, "instance %d: %s", i, qsv_last_error());
+        P->sub[i] = ap;
+        big = std::max(big, wb);
+    }
+    P->big_off = woff;
+    woff += (long long)((big + 255) & ~size_t(255));
     P->work_bytes = woff;
     // largest estimated work first
     P->order.resize(ninst);
@@ -265,17 +315,19 @@ qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* 
         const double cb = std::ldexp((double)P->inst[b].ops.size() + 1, P->inst[b].n);
         return ca > cb;
     });
-    int m = dt == QSV_C64 ? 12 : 11, threads = 512;
-    read_cache(P->key, &m, &threads);
-    if (const char* e = getenv("QSV_BATCH_SHAPE")) {  // "m,threads" (tests of every shape)
-        int a = 0, b = 0;
-        if (sscanf(e, "%d,%d", &a, &b) == 2 && a >= 3 && a <= 14 && (b == 256 || b == 512)) {
+    int m = dt == QSV_C64 ? 12 : 11, threads = 512, split = 19;
+    read_cache(P->key, &m, &threads, &split);
+    if (const char* e = getenv("QSV_BATCH_SHAPE")) {  // "m,threads[,split]" (tests of every shape)
+        int a = 0, b = 0, c = split;
+        if (sscanf(e, "%d,%d,%d", &a, &b, &c) >= 2 && a >= 3 && a <= 14 && (b == 256 || b == 512)) {
             m = a;
             threads = b;
+            split = c;
         }
     }
     P->m = m;
     P->threads = threads;
+    P->split = split;
     *work_bytes = (size_t)P->work_bytes;
     *plan = P.release();
     return ok();
@@ -297,11 +349,11 @@ qsv_status qsv_batch_run(qsv_batch_plan* plan, const double* params_dev, void* w
         return fail(QSV_ERR_ARG, "NULL plan, work, energies, gradients or parameters");
     if (reinterpret_cast<uintptr_t>(work) % 256)
         return fail(QSV_ERR_ARG, "work is not 256-byte aligned");
-    qsv_status st = configure(plan, plan->m, plan->threads);
+    qsv_status st = configure(plan, plan->m, plan->threads, plan->split);
     if (st) {
         // the requested tile does not fit this device: take the first candidate that does
         for (auto c : candidates(plan->dt))
-            if ((st = configure(plan, c.first, c.second)) == QSV_OK)
+            if ((st = configure(plan, c.first, c.second, plan->split)) == QSV_OK)
                 break;
         if (st)
             return st;
@@ -325,39 +377,53 @@ qsv_status qsv_batch_tune(qsv_batch_plan* plan, const double* params_dev, void* 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(QSV_ERR_HIP, "event creation failed");
-    double best = 1e300;
-    int bm = plan->m, bt = plan->threads;
-    qsv_status st = QSV_OK;
-    for (auto c : candidates(plan->dt)) {
+    // time one configuration: a warm-up run, then the mean of two
+    auto measure = [&](int m, int t, int split, double* ms) -> bool {
         hipStreamSynchronize(s);
-        if (configure(plan, c.first, c.second) != QSV_OK)
-            continue;
+        if (configure(plan, m, t, split) != QSV_OK)
+            return false;
         if (enqueue(plan, params_dev, work, energies_dev, grads_dev, s) != QSV_OK)
-            continue;  // this shape does not launch here
+            return false;
         hipEventRecord(e0, s);
-        for (int r = 0; r < 2 && !st; ++r)
-            st = enqueue(plan, params_dev, work, energies_dev, grads_dev, s);
+        for (int r = 0; r < 2; ++r)
+            if (enqueue(plan, params_dev, work, energies_dev, grads_dev, s) != QSV_OK)
+                return false;
         hipEventRecord(e1, s);
         hipEventSynchronize(e1);
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (ms / 2 < best) {
-            best = ms / 2;
+        float f = 0.f;
+        hipEventElapsedTime(&f, e0, e1);
+        *ms = f / 2;
+        return true;
+    };
+    double best = 1e300;
+    int bm = plan->m, bt = plan->threads, bs = plan->split;
+    // 1) tile shape at the current split, 2) split at the best shape
+    for (auto c : candidates(plan->dt)) {
+        double ms;
+        if (measure(c.first, c.second, bs, &ms) && ms < best) {
+            best = ms;
             bm = c.first;
             bt = c.second;
         }
     }
+    for (int sp : split_candidates()) {
+        double ms;
+        if (sp != bs && measure(bm, bt, sp, &ms) && ms < best) {
+            best = ms;
+            bs = sp;
+        }
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    hipStreamSynchronize(s);
+    qsv_status st = configure(plan, bm, bt, bs);
     if (st)
         return st;
-    hipStreamSynchronize(s);
-    if ((st = configure(plan, bm, bt)))
-        return st;
-    write_cache(plan->key, bm, bt, best);
+    write_cache(plan->key, bm, bt, bs, best);
     if (chosen) {
         chosen[0] = bm;
         chosen[1] = bt;
+        chosen[2] = bs;
     }
     return ok();
 }

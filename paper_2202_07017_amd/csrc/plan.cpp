@@ -701,6 +701,22 @@ static qsv_status adjoint_enqueue(qsv_adjoint_plan* P, const double* params, voi
     return QSV_OK;
 }
 
+}  // extern "C"
+
+namespace qsv {
+qsv_status adjoint_enqueue_direct(qsv_adjoint_plan* P, const double* params, void* work,
+                                  double* energy, double* grad, hipStream_t s)
+{
+    return adjoint_enqueue(P, params, work, energy, grad, true, s);
+}
+size_t adjoint_work_bytes(const qsv_adjoint_plan* P)
+{
+    return P->work_bytes;
+}
+}  // namespace qsv
+
+extern "C" {
+
 qsv_status qsv_adjoint_run(qsv_adjoint_plan* plan, const double* params_dev, void* work,
                            double* energy_dev, double* grad_dev, void* stream)
 {

@@ -41,6 +41,10 @@ qsv_status enqueue_expectation(const void* psi, int n, int dt, const qsv_pauli_s
 qsv_status enqueue_hpsi(const void* psi, void* lam, int n, int dt, const qsv_pauli_sum* H,
                         hipStream_t s);
 qsv_status check_circuit(const qsv_circuit* C, int max_n);
+// Enqueue a full adjoint evaluation of a plan directly on `s` (no graph).
+qsv_status adjoint_enqueue_direct(qsv_adjoint_plan* P, const double* params, void* work,
+                                  double* energy, double* grad, hipStream_t s);
+size_t adjoint_work_bytes(const qsv_adjoint_plan* P);
 std::vector<double> op_matrix(const qsv_op& op, double theta);
 
 // --------------------------------------------------------- graph caching

@@ -130,11 +130,17 @@ __device__ void exec_tile(const LOp<R>* ops, const DStep* steps, int nsteps, int
                           ExecShared& sh, int& parity)
 {
     for (int si = 0; si < nsteps; ++si) {
+        // Step and gate descriptors are the same for every lane; readfirstlane
+        // keeps them in scalar registers so the guards below are scalar
+        // branches rather than masked execution of every case.
         const DStep st = steps[REV ? nsteps - 1 - si : si];
-        const int nq = st.nq;
+        const int nq = __builtin_amdgcn_readfirstlane(st.nq);
         const int na = 1 << nq;
-        const int nop = st.o1 - st.o0;
-        const int qp[3] = {st.q[0], st.q[1], st.q[2]};
+        const int o0 = __builtin_amdgcn_readfirstlane(st.o0);
+        const int nop = __builtin_amdgcn_readfirstlane(st.o1) - o0;
+        const int qp[3] = {__builtin_amdgcn_readfirstlane(st.q[0]),
+                           __builtin_amdgcn_readfirstlane(st.q[1]),
+                           __builtin_amdgcn_readfirstlane(st.q[2])};
         uint32_t off[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -174,8 +180,10 @@ __device__ void exec_tile(const LOp<R>* ops, const DStep* steps, int nsteps, int
                 if (kk >= nop)
                     break;
                 const int k = REV ? nop - 1 - kk : kk;
-                const LOp<R>& o = ops[st.o0 + k];
-                const int tb = 1 << o.tq, cm = o.cm, gen = o.gen;
+                const LOp<R>& o = ops[o0 + k];
+                const int tb = 1 << __builtin_amdgcn_readfirstlane(o.tq);
+                const int cm = __builtin_amdgcn_readfirstlane(o.cm);
+                const int gen = __builtin_amdgcn_readfirstlane(o.gen);
 #pragma unroll
                 for (int u0 = 0; u0 < 8; ++u0) {
                     if (u0 >= na || (u0 & tb) || (u0 & cm) != cm)
@@ -208,7 +216,7 @@ __device__ void exec_tile(const LOp<R>* ops, const DStep* steps, int nsteps, int
             for (int kk = 0; kk < kMaxStepOps; ++kk) {
                 if (kk >= nop)
                     break;
-                if (ops[st.o0 + nop - 1 - kk].gen) {
+                if (__builtin_amdgcn_readfirstlane(ops[o0 + nop - 1 - kk].gen)) {
                     const double v = wave_sum(acc[kk]);
                     if ((threadIdx.x & 63) == 0)
                         sh.red[parity][kk][threadIdx.x >> 6] = v;
@@ -218,11 +226,11 @@ __device__ void exec_tile(const LOp<R>* ops, const DStep* steps, int nsteps, int
         __syncthreads();
         if (REV) {
             const int kk = threadIdx.x;
-            if (kk < nop && ops[st.o0 + nop - 1 - kk].gen) {
+            if (kk < nop && ops[o0 + nop - 1 - kk].gen) {
                 double s = 0.0;
                 for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
                     s += sh.red[parity][kk][w];
-                sh.pacc[ops[st.o0 + nop - 1 - kk].slot] += s;
+                sh.pacc[ops[o0 + nop - 1 - kk].slot] += s;
             }
             parity ^= 1;
         }

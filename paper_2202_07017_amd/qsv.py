@@ -425,10 +425,10 @@ class BatchPlan:
         return energies, grads
 
     def tune(self, params_dev, energies, grads, stream=None):
-        chosen = (ctypes.c_int * 2)()
+        chosen = (ctypes.c_int * 3)()
         _check(lib().qsv_batch_tune(self.h, _ptr(params_dev), _ptr(self.work), _ptr(energies),
                                     _ptr(grads), _stream(stream), chosen))
-        return chosen[0], chosen[1]
+        return chosen[0], chosen[1], chosen[2]
 
     def __del__(self):
         if getattr(self, "h", None) and self.h.value and _lib is not None:

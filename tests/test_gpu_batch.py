@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = {1: ["12,512", "12,256", "11,256", "11,512", "13,512"],
           2: ["11,512", "11,256", "10,256", "12,512"]}
+SPLITS = ["16", "99"]  # large tier from 16 qubits, or every instance in the persistent kernel
 
 
 @pytest.fixture(scope="module")
@@ -78,12 +79,13 @@ def check_batch(q, orc, insts, code, shape, tol_e, tol_g, refs=None):
 
 @pytest.mark.parametrize("code", [1, 2])
 def test_batch_every_shape(q, orc, code):
-    insts = mixed_instances(11 + code, 14, 3, 14)
+    insts = mixed_instances(11 + code, 14, 3, 17)
     refs = [orc.adjoint(i.circuit, i.params, i.hamiltonian) for i in insts]
     for shape in SHAPES[code]:
-        say("batch", code, shape)
-        check_batch(q, orc, insts, code, shape, 1e-10 if code == 2 else 2e-4,
-                    1e-9 if code == 2 else 2e-4, refs)
+        for split in SPLITS:
+            say("batch", code, shape, split)
+            check_batch(q, orc, insts, code, shape + "," + split, 1e-10 if code == 2 else 2e-4,
+                        1e-9 if code == 2 else 2e-4, refs)
 
 
 def test_batch_tune_and_replay(q, orc):
@@ -93,8 +95,8 @@ def test_batch_tune_and_replay(q, orc):
     en = torch.empty(plan.ninst, dtype=torch.float64, device="cuda")
     gr = torch.empty(max(int(plan.offsets[-1]), 1), dtype=torch.float64, device="cuda")
     say("batch tune")
-    m, t = plan.tune(params, en, gr)
-    assert (str(m) + "," + str(t)) in SHAPES[2]
+    m, t, sp = plan.tune(params, en, gr)
+    assert (str(m) + "," + str(t)) in SHAPES[2] and sp in (17, 19, 21, 99)
     # the tuned shape may sum in another order: compare replays with each other
     # (bit for bit) and with the first run within the parity tolerance
     e1, g1 = [x.cpu().numpy().copy() for x in plan.run(params, en, gr)]
