@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--skip-side", action="store_true", help="only the timed step")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only the dominant kernel and a copy of known size (counter runs)")
+    ap.add_argument("--legs", default="",
+                    help="comma list of side legs to run alone (adjoint, batched): profiling runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X and this build has no "
@@ -129,6 +131,20 @@ def main():
 
     if args.profile_kernels:
         profile_kernels()
+        return
+    if args.legs:
+        import numpy as np
+        import torch
+
+        import workloads as W
+        from paper_2202_07017_amd import qsv
+        dev = torch.device("cuda:0")
+        out = {}
+        if "adjoint" in args.legs:
+            out["adjoint"] = adjoint_leg(qsv, W, torch, np, dev)
+        if "batched" in args.legs:
+            out["batched"] = batched_leg(qsv, W, torch, np, dev)
+        print(json.dumps(out), flush=True)
         return
 
     import numpy as np

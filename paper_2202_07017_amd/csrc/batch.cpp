@@ -99,18 +99,14 @@ qsv_status configure(qsv_batch_plan* P, int m, int threads, int split)
         dops.insert(dops.end(), tp.ops.begin(), tp.ops.end());
         terms.insert(terms.end(), I.terms.begin(), I.terms.end());
     }
-    auto bytes_of = [](const void* p, size_t n) {
-        return std::vector<unsigned char>(static_cast<const unsigned char*>(p),
-                                          static_cast<const unsigned char*>(p) + n);
-    };
-    P->o_inst = P->dev.add(bytes_of(bi.data(), bi.size() * sizeof(BInst)));
-    P->o_order = P->dev.add(bytes_of(small.data(), std::max<size_t>(small.size(), 1) * sizeof(int)));
+    P->o_inst = P->dev.add(table_bytes(bi));
+    P->o_order = P->dev.add(table_bytes(small));
     P->nsmall = (int)small.size();
-    P->o_pass = P->dev.add(bytes_of(passes.data(), passes.size() * sizeof(DPass)));
-    P->o_steps = P->dev.add(bytes_of(steps.data(), std::max<size_t>(steps.size(), 1) * sizeof(DStep)));
-    P->o_pops = P->dev.add(bytes_of(dops.data(), std::max<size_t>(dops.size(), 1) * sizeof(DOp)));
-    P->o_mats = P->dev.add(bytes_of(P->mats.data(), std::max<size_t>(P->mats.size(), 8) * sizeof(double)));
-    P->o_terms = P->dev.add(bytes_of(terms.data(), terms.size() * sizeof(BTerm)));
+    P->o_pass = P->dev.add(table_bytes(passes));
+    P->o_steps = P->dev.add(table_bytes(steps));
+    P->o_pops = P->dev.add(table_bytes(dops));
+    P->o_mats = P->dev.add(table_bytes(P->mats, 8));
+    P->o_terms = P->dev.add(table_bytes(terms));
     qsv_status st = P->dev.commit();
     if (st)
         return st;

@@ -520,15 +520,9 @@ qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum*
         P->tblocks = (int)std::min<uint64_t>(ntiles, (uint64_t)res);
         P->tiled = true;
         P->nslots = (int)P->tp.slot_param.size();
-        auto bytes_of = [](const void* p, size_t nb) {
-            return std::vector<unsigned char>(static_cast<const unsigned char*>(p),
-                                              static_cast<const unsigned char*>(p) + nb);
-        };
-        P->o_steps = P->dev.add(bytes_of(P->tp.steps.data(), std::max<size_t>(P->tp.steps.size(), 1) * sizeof(DStep)));
-        P->o_ops = P->dev.add(bytes_of(P->tp.ops.data(), std::max<size_t>(P->tp.ops.size(), 1) * sizeof(DOp)));
-        if (mats.empty())
-            mats.assign(8, 0.0);
-        P->o_mats = P->dev.add(bytes_of(mats.data(), mats.size() * sizeof(double)));
+        P->o_steps = P->dev.add(table_bytes(P->tp.steps));
+        P->o_ops = P->dev.add(table_bytes(P->tp.ops));
+        P->o_mats = P->dev.add(table_bytes(mats, 8));
         std::vector<std::vector<int>> sl(circ->nparams);
         for (int sidx = 0; sidx < P->nslots; ++sidx)
             sl[P->tp.slot_param[sidx]].push_back(sidx);
@@ -540,7 +534,7 @@ qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum*
                 csr[circ->nparams + 1 + fill++] = v;
         }
         csr[circ->nparams] = fill;
-        P->off_csr = P->dev.add(bytes_of(csr.data(), csr.size() * sizeof(int)));
+        P->off_csr = P->dev.add(table_bytes(csr));
         if ((st = P->dev.commit()))
             return st;
         const size_t sb = amp_bytes(dt) << n;

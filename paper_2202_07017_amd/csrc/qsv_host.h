@@ -115,6 +115,17 @@ qsv_status run_graph(GraphCache& gc, const std::vector<const void*>& key, hipStr
     return QSV_OK;
 }
 
+// Bytes of a host table for upload, at least min_elems elements (zero-filled
+// beyond the table, so empty tables still give a valid device pointer).
+template <typename T>
+std::vector<unsigned char> table_bytes(const std::vector<T>& v, size_t min_elems = 1)
+{
+    std::vector<unsigned char> out((v.size() > min_elems ? v.size() : min_elems) * sizeof(T), 0);
+    if (!v.empty())
+        std::memcpy(out.data(), v.data(), v.size() * sizeof(T));
+    return out;
+}
+
 // Device memory owned by a plan: all uploads packed at 256-byte offsets.
 struct DevPack {
     void* mem = nullptr;

@@ -126,3 +126,21 @@ def test_batch_full_workload_sample(q, orc):
         gj = g[plan.offsets[j]:plan.offsets[j + 1]]
         assert abs(e[j] - E_ref) <= 2e-4 * inst.circuit.n, (j, inst.circuit.n)
         assert np.max(np.abs(gj - g_ref)) <= 2e-4 * inst.circuit.n, (j, inst.circuit.n)
+
+
+def test_batch_edge_cases(q, orc):
+    """A batch whose instances all take the large tier, a circuit with no
+    gates, and a circuit of rotations only (no fixed matrices)."""
+    rng = np.random.default_rng(3)
+    only_big = [W.BatchInstance(W.hea(17, 1), rng.uniform(0, 6.28, 34), W.tfim_chain(17))]
+    say("batch only large tier")
+    check_batch(q, orc, only_big, 1, "12,512,16", 2e-4 * 17, 2e-4 * 17)
+    empty = W.Circuit(5, [], 0)
+    rot = W.Circuit(4, [W.Op("ry", (j,), param=j) for j in range(4)] +
+                    [W.Op("rz", (j,), param=4 + j) for j in range(4)], 8)
+    insts = [W.BatchInstance(empty, np.zeros(0), W.pauli_sum(5, [("Z", (0,), 1.0), ("X", (3,), 2.0)])),
+             W.BatchInstance(rot, rng.uniform(0, 6.28, 8), W.tfim_chain(4))]
+    for code in [1, 2]:
+        say("batch empty/rotations", code)
+        check_batch(q, orc, insts, code, None, 1e-10 if code == 2 else 2e-4,
+                    1e-9 if code == 2 else 2e-4)
