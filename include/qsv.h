@@ -282,7 +282,7 @@ typedef struct qsv_batch_plan qsv_batch_plan;
  * from the autotuner (qsv_batch_tune) or its cache.  Parameters and
  * gradients of instance i live at offsets[i] .. offsets[i+1]-1 of the
  * concatenated vectors (qsv_batch_offsets).  *work_bytes = workspace size. */
-#define QSV_BATCH_MAX_QUBITS 24
+#define QSV_BATCH_MAX_QUBITS 24  /* and at least 3 qubits per instance */
 qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* Hs, int ninst,
                                  qsv_dtype dt, qsv_batch_plan** plan, size_t* work_bytes);
 

@@ -128,6 +128,7 @@ qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* 
     a.order = static_cast<const int*>(P->dev.at(P->o_order));
     a.ninst = P->nsmall;
     a.m = P->m;
+    a.apt = ((1 << P->m) / P->threads) >= 16 ? 16 : 8;
     a.passes = static_cast<const DPass*>(P->dev.at(P->o_pass));
     a.steps = static_cast<const DStep*>(P->dev.at(P->o_steps));
     a.ops = static_cast<const DOp*>(P->dev.at(P->o_pops));
@@ -154,11 +155,12 @@ qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* 
     return QSV_OK;
 }
 
+// (tile qubits, threads) with 8 or 16 amplitudes per thread in a tile step
 std::vector<std::pair<int, int>> candidates(int dt)
 {
     if (dt == QSV_C64)
-        return {{12, 512}, {12, 256}, {11, 256}, {11, 512}, {13, 512}};
-    return {{11, 512}, {11, 256}, {10, 256}, {12, 512}};
+        return {{12, 512}, {12, 256}, {11, 256}, {13, 512}};
+    return {{11, 256}, {12, 512}, {10, 128}};
 }
 
 std::vector<int> split_candidates()
@@ -240,6 +242,8 @@ qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* 
             return fail(st, "instance %d: %s", i, qsv_last_error());
         if ((st = check_hamiltonian(&Hs[i], C->n)))
             return fail(st, "instance %d: %s", i, qsv_last_error());
+        if (C->n < 3)
+            return fail(QSV_ERR_UNSUPPORTED, "instance %d: batch instances need n >= 3", i);
         HInst& I = P->inst[i];
         I.n = C->n;
         I.nparam = C->nparams;
@@ -315,7 +319,8 @@ qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* 
     read_cache(P->key, &m, &threads, &split);
     if (const char* e = getenv("QSV_BATCH_SHAPE")) {  // "m,threads[,split]" (tests of every shape)
         int a = 0, b = 0, c = split;
-        if (sscanf(e, "%d,%d,%d", &a, &b, &c) >= 2 && a >= 3 && a <= 14 && (b == 256 || b == 512)) {
+        if (sscanf(e, "%d,%d,%d", &a, &b, &c) >= 2 && a >= 3 && a <= 14 &&
+            (b == 128 || b == 256 || b == 512) && ((1 << a) / b == 8 || (1 << a) / b == 16)) {
             m = a;
             threads = b;
             split = c;

@@ -105,7 +105,16 @@ __device__ void run_pass(const BatchArgs& a, const BInst& I, const DPass& P, R* 
                 ll[v] = lg[gi];
         }
         __syncthreads();
-        tx::exec_tile<R, REV>(ops, steps, P.nsteps, m, phiL, lamL, sm.ex, parity);
+        // 16 amplitudes per thread need tiles of >= 16 (complex64 shapes only)
+        bool wide = false;
+        if constexpr (sizeof(R) == 4)
+            wide = a.apt == 16 && m >= 4;
+        if constexpr (sizeof(R) == 4) {
+            if (wide)
+                tx::exec_tile<R, REV, 16>(ops, steps, P.nsteps, m, phiL, lamL, sm.ex, parity);
+        }
+        if (!wide)
+            tx::exec_tile<R, REV, 8>(ops, steps, P.nsteps, m, phiL, lamL, sm.ex, parity);
         for (uint32_t v = threadIdx.x; v < nvec; v += blockDim.x) {
             const uint64_t gi = (base | tx::deposit_mask((uint64_t)v * APV, P.bmask)) / APV;
             pg[gi] = pl[v];

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(kTpassThreads) k_tpass(R* __restrict__ psi, R*
                 ll[v] = lg[gi];
         }
         __syncthreads();
-        tx::exec_tile<R, REV>(ops, steps, P.nsteps, m, phiL, lamL, sh, parity);
+        tx::exec_tile<R, REV, 8>(ops, steps, P.nsteps, m, phiL, lamL, sh, parity);
         for (uint32_t v = threadIdx.x; v < nvec; v += blockDim.x) {
             const uint64_t gi = (base | tx::deposit_mask((uint64_t)v * APV, P.bmask)) / APV;
             pg[gi] = pl[v];

@@ -480,7 +480,8 @@ qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum*
     P->hc.assign(H->coeff, H->coeff + H->nterms);
     P->H = qsv_pauli_sum{H->nterms, P->hx.data(), P->hz.data(), P->hc.data()};
 
-    bool tileable = getenv("QSV_NO_TILES") == nullptr || getenv("QSV_NO_TILES")[0] != '1';
+    // tile steps hold 8 amplitudes per thread: the cache-blocked mode needs n >= 3
+    bool tileable = n >= 3 && (getenv("QSV_NO_TILES") == nullptr || getenv("QSV_NO_TILES")[0] != '1');
     for (int o = 0; o < circ->nops && tileable; ++o) {
         const qsv_op& op = circ->ops[o];
         tileable = op.k == 1 && op.c <= 2 && op.kind != QSV_OP_SWAP;

@@ -30,6 +30,7 @@ struct BatchArgs {
     const int* order;
     int ninst;
     int m;
+    int apt;  // amplitudes per thread in a tile step: 2^m / threads (8 or 16)
     const DPass* passes;
     const DStep* steps;
     const DOp* ops;

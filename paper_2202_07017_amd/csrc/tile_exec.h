@@ -3,14 +3,14 @@
 // stage() copies a pass's steps into LDS and turns its gates into 2x2
 // matrices (U for forward passes, U^dagger for reverse passes; rotations
 // exp(-i theta P/2) read theta from the parameter vector).  exec_tile() runs
-// the steps over a tile of 2^mb amplitudes: per step each thread takes groups
-// of the tile (fixed values of the non-step qubits), holds the step's 2^nq
-// amplitudes in registers, applies the step's gates in order (reverse passes:
-// reverse order, and before each rotation's uncompute it adds
-// Im <lambda|P psi> over the group to a per-thread partial), writes them
-// back, and the block meets one barrier per step.  Per-gate partials are
-// reduced in a fixed order (wave shuffle tree, then one thread over the
-// waves) into per-slot FP64 accumulators in LDS.
+// the steps over a tile of 2^mb amplitudes: per step each thread takes a fixed
+// number of groups of the tile (fixed values of the non-step qubits), holds
+// their amplitudes in registers, applies the step's gates in order (reverse
+// passes: reverse order, and before each rotation's uncompute it adds
+// Im <lambda|P psi> over its groups to a partial), writes them back, and the
+// block meets one barrier per step.  Per-gate partials are reduced in a fixed
+// order (wave shuffle tree, then one thread over the waves) into per-slot
+// FP64 accumulators in LDS.
 #pragma once
 
 #include "qsv_internal.h"
@@ -124,113 +124,150 @@ __device__ __forceinline__ void apply2(const R* m, R& ar, R& ai, R& br, R& bi)
     bi = m[4] * xi + m[5] * xr + m[6] * yi + m[7] * yr;
 }
 
-// Run the staged pass over one LDS tile of 2^mb amplitudes (phi; REV: and lam).
-template <typename R, bool REV>
+// Apply one gate (target at step position TQ, controls cm over the step's
+// qubits) to every group a thread holds: GP groups of 2^NQ amplitudes stored
+// at [gi * 2^NQ + u].  All register indices are compile-time constants.
+template <typename R, bool REV, int NQ, int TQ, int GP>
+__device__ __forceinline__ void gate_pairs(const R* m, int cm, int gen, R* pr, R* pi, R* lr, R* li,
+                                           double& acc)
+{
+    constexpr int NA = 1 << NQ;
+    constexpr int TB = 1 << TQ;
+#pragma unroll
+    for (int gi = 0; gi < GP; ++gi)
+#pragma unroll
+        for (int p = 0; p < NA / 2; ++p) {
+            const int u0 = ((p >> TQ) << (TQ + 1)) | (p & (TB - 1));
+            const int u1 = u0 | TB;
+            if ((u0 & cm) != cm)
+                continue;
+            const int a = gi * NA + u0, b = gi * NA + u1;
+            if (REV) {
+                if (gen)
+                    acc += gen_term(gen, (double)lr[a], (double)li[a], (double)lr[b], (double)li[b],
+                                    (double)pr[a], (double)pi[a], (double)pr[b], (double)pi[b]);
+                apply2(m, lr[a], li[a], lr[b], li[b]);
+            }
+            apply2(m, pr[a], pi[a], pr[b], pi[b]);
+        }
+}
+
+// One step on NQ qubits: each active thread holds APT amplitudes (APT / 2^NQ
+// groups), applies the step's gates in order (reverse: in reverse order), and
+// the per-gate gradient partials go straight to LDS after a wave reduction.
+template <typename R, bool REV, int NQ, int APT>
+__device__ void exec_step(const LOp<R>* ops, int o0, int nop, int q0, int q1, int q2, int mb,
+                          R* phi, R* lam, ExecShared& sh, int parity)
+{
+    constexpr int NA = 1 << NQ;
+    constexpr int GP = APT / NA;
+    const uint32_t nthr = (1u << mb) / APT;  // threads holding amplitudes
+    const bool active = threadIdx.x < nthr;
+    const int qp[3] = {q0, q1, q2};
+    uint32_t off[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int x = 0; x < NQ; ++x)
+            o |= ((uint32_t)(j >> x) & 1u) << qp[x];
+        off[j] = o;
+    }
+    R pr[APT], pi[APT], lr[REV ? APT : 1], li[REV ? APT : 1];
+    uint32_t base[GP];
+    if (active) {
+#pragma unroll
+        for (int gi = 0; gi < GP; ++gi) {
+            uint32_t b = gi * nthr + threadIdx.x;
+#pragma unroll
+            for (int x = 0; x < NQ; ++x) {
+                const uint32_t lo = (1u << qp[x]) - 1;
+                b = ((b & ~lo) << 1) | (b & lo);
+            }
+            base[gi] = b;
+#pragma unroll
+            for (int j = 0; j < NA; ++j) {
+                pr[gi * NA + j] = phi[2 * (b + off[j])];
+                pi[gi * NA + j] = phi[2 * (b + off[j]) + 1];
+                if (REV) {
+                    lr[gi * NA + j] = lam[2 * (b + off[j])];
+                    li[gi * NA + j] = lam[2 * (b + off[j]) + 1];
+                }
+            }
+        }
+    }
+    for (int k = 0; k < nop; ++k) {
+        const int kk = REV ? nop - 1 - k : k;
+        const LOp<R>& o = ops[o0 + kk];
+        const int tq = __builtin_amdgcn_readfirstlane(o.tq);
+        const int cm = __builtin_amdgcn_readfirstlane(o.cm);
+        const int gen = REV ? __builtin_amdgcn_readfirstlane(o.gen) : 0;
+        R m[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            m[q] = o.m[q];
+        double acc = 0.0;
+        if (active) {
+            if (tq == 0)
+                gate_pairs<R, REV, NQ, 0, GP>(m, cm, gen, pr, pi, lr, li, acc);
+            else if (NQ > 1 && tq == 1)
+                gate_pairs<R, REV, NQ, (NQ > 1 ? 1 : 0), GP>(m, cm, gen, pr, pi, lr, li, acc);
+            else if (NQ > 2)
+                gate_pairs<R, REV, NQ, (NQ > 2 ? 2 : 0), GP>(m, cm, gen, pr, pi, lr, li, acc);
+        }
+        if (REV && gen) {
+            acc = wave_sum(acc);
+            if ((threadIdx.x & 63) == 0)
+                sh.red[parity][kk][threadIdx.x >> 6] = acc;
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int gi = 0; gi < GP; ++gi)
+#pragma unroll
+            for (int j = 0; j < NA; ++j) {
+                const uint32_t b = base[gi];
+                phi[2 * (b + off[j])] = pr[gi * NA + j];
+                phi[2 * (b + off[j]) + 1] = pi[gi * NA + j];
+                if (REV) {
+                    lam[2 * (b + off[j])] = lr[gi * NA + j];
+                    lam[2 * (b + off[j]) + 1] = li[gi * NA + j];
+                }
+            }
+    }
+}
+
+// Run the staged pass over one LDS tile of 2^mb amplitudes (phi; REV: and
+// lam).  APT amplitudes per thread: the block needs 2^mb / APT threads
+// (mb >= log2(APT)); extra threads only take part in the barriers.
+template <typename R, bool REV, int APT>
 __device__ void exec_tile(const LOp<R>* ops, const DStep* steps, int nsteps, int mb, R* phi, R* lam,
                           ExecShared& sh, int& parity)
 {
     for (int si = 0; si < nsteps; ++si) {
         // Step and gate descriptors are the same for every lane; readfirstlane
-        // keeps them in scalar registers so the guards below are scalar
-        // branches rather than masked execution of every case.
+        // keeps them in scalar registers.
         const DStep st = steps[REV ? nsteps - 1 - si : si];
         const int nq = __builtin_amdgcn_readfirstlane(st.nq);
-        const int na = 1 << nq;
         const int o0 = __builtin_amdgcn_readfirstlane(st.o0);
         const int nop = __builtin_amdgcn_readfirstlane(st.o1) - o0;
-        const int qp[3] = {__builtin_amdgcn_readfirstlane(st.q[0]),
-                           __builtin_amdgcn_readfirstlane(st.q[1]),
-                           __builtin_amdgcn_readfirstlane(st.q[2])};
-        uint32_t off[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            uint32_t o = 0;
-#pragma unroll
-            for (int x = 0; x < 3; ++x)
-                if (x < nq)
-                    o |= ((uint32_t)(j >> x) & 1u) << qp[x];
-            off[j] = o;
-        }
-        double acc[kMaxStepOps];
-#pragma unroll
-        for (int k = 0; k < kMaxStepOps; ++k)
-            acc[k] = 0.0;
-        const uint32_t ngroups = 1u << (mb - nq);
-        for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
-            uint32_t base = g;
-#pragma unroll
-            for (int x = 0; x < 3; ++x)
-                if (x < nq) {
-                    const uint32_t lo = (1u << qp[x]) - 1;
-                    base = ((base & ~lo) << 1) | (base & lo);
-                }
-            R pr[8], pi[8], lr[8], li[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j < na) {
-                    pr[j] = phi[2 * (base + off[j])];
-                    pi[j] = phi[2 * (base + off[j]) + 1];
-                    if (REV) {
-                        lr[j] = lam[2 * (base + off[j])];
-                        li[j] = lam[2 * (base + off[j]) + 1];
-                    }
-                }
-#pragma unroll
-            for (int kk = 0; kk < kMaxStepOps; ++kk) {
-                if (kk >= nop)
-                    break;
-                const int k = REV ? nop - 1 - kk : kk;
-                const LOp<R>& o = ops[o0 + k];
-                const int tb = 1 << __builtin_amdgcn_readfirstlane(o.tq);
-                const int cm = __builtin_amdgcn_readfirstlane(o.cm);
-                const int gen = __builtin_amdgcn_readfirstlane(o.gen);
-#pragma unroll
-                for (int u0 = 0; u0 < 8; ++u0) {
-                    if (u0 >= na || (u0 & tb) || (u0 & cm) != cm)
-                        continue;
-                    const int u1 = u0 | tb;
-                    if (REV) {
-                        if (gen)
-                            acc[kk] += gen_term(gen, (double)lr[u0], (double)li[u0], (double)lr[u1],
-                                               (double)li[u1], (double)pr[u0], (double)pi[u0],
-                                               (double)pr[u1], (double)pi[u1]);
-                        apply2(o.m, lr[u0], li[u0], lr[u1], li[u1]);
-                    }
-                    apply2(o.m, pr[u0], pi[u0], pr[u1], pi[u1]);
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j < na) {
-                    phi[2 * (base + off[j])] = pr[j];
-                    phi[2 * (base + off[j]) + 1] = pi[j];
-                    if (REV) {
-                        lam[2 * (base + off[j])] = lr[j];
-                        lam[2 * (base + off[j]) + 1] = li[j];
-                    }
-                }
-        }
-        // acc[kk] belongs to the gate at position nop - 1 - kk (reverse passes)
-        if (REV) {
-#pragma unroll
-            for (int kk = 0; kk < kMaxStepOps; ++kk) {
-                if (kk >= nop)
-                    break;
-                if (__builtin_amdgcn_readfirstlane(ops[o0 + nop - 1 - kk].gen)) {
-                    const double v = wave_sum(acc[kk]);
-                    if ((threadIdx.x & 63) == 0)
-                        sh.red[parity][kk][threadIdx.x >> 6] = v;
-                }
-            }
-        }
+        const int q0 = __builtin_amdgcn_readfirstlane(st.q[0]);
+        const int q1 = __builtin_amdgcn_readfirstlane(st.q[1]);
+        const int q2 = __builtin_amdgcn_readfirstlane(st.q[2]);
+        if (nq == 1)
+            exec_step<R, REV, 1, APT>(ops, o0, nop, q0, q1, q2, mb, phi, lam, sh, parity);
+        else if (nq == 2)
+            exec_step<R, REV, 2, APT>(ops, o0, nop, q0, q1, q2, mb, phi, lam, sh, parity);
+        else
+            exec_step<R, REV, 3, APT>(ops, o0, nop, q0, q1, q2, mb, phi, lam, sh, parity);
         __syncthreads();
         if (REV) {
             const int kk = threadIdx.x;
-            if (kk < nop && ops[o0 + nop - 1 - kk].gen) {
+            if (kk < nop && ops[o0 + kk].gen) {
                 double s = 0.0;
                 for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
                     s += sh.red[parity][kk][w];
-                sh.pacc[ops[o0 + nop - 1 - kk].slot] += s;
+                sh.pacc[ops[o0 + kk].slot] += s;
             }
             parity ^= 1;
         }

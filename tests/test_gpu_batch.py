@@ -11,8 +11,8 @@ from gpu_util import say
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = {1: ["12,512", "12,256", "11,256", "11,512", "13,512"],
-          2: ["11,512", "11,256", "10,256", "12,512"]}
+SHAPES = {1: ["12,512", "12,256", "11,256", "13,512"],
+          2: ["11,256", "12,512", "10,128"]}
 SPLITS = ["16", "99"]  # large tier from 16 qubits, or every instance in the persistent kernel
 
 
