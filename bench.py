@@ -49,6 +49,27 @@ def step_ops(n, rng, W):
     return W.Circuit(n, ops, 1)
 
 
+def recorded_traffic():
+    """HBM bytes per dispatch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None once the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_dense_sweep_n30_c64_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic-record:"):
+            rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+    if not rec:
+        return None
+    src = open(os.path.join(ROOT, rec["src"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["src_sha256"]:
+        return None
+    return (float(rec["fetch_kib"]) * float(rec["fetch_factor"]) +
+            float(rec["write_kib"]) * float(rec["write_factor"])) * 1024.0
+
+
 def event_time(fn, reps, stream):
     import torch
     a = torch.cuda.Event(enable_timing=True)
@@ -196,7 +217,7 @@ def main():
     avg = event_time(lambda: qsv.qsv_apply_gate(psi, (15,), (), G), reps, stream)
     roof = {"bound": "hbm", "achieved": round(sweep_bytes / avg / 1e9, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(sweep_bytes / avg / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": None, "kernel": "k_dense<float,1,W2> (single-qubit sweep, target 15)",
+            "traffic": recorded_traffic(), "kernel": "k_dense<float,1,W2> (single-qubit sweep, target 15)",
             "avg_launch_ms": round(avg * 1e3, 4)}
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
