@@ -382,3 +382,86 @@ def test_full_size_sampled(q, orc):
         assert abs(norm - 1.0) < (1e-12 if name == "c128" else 1e-5)
         del d
         torch.cuda.empty_cache()
+
+
+def inverse_circuit(circ, params=None):
+    """The circuit's inverse as data: ops reversed, every matrix daggered,
+    rotations bound to -theta (a property check that holds at any size)."""
+    ops = []
+    for op in reversed(circ.ops):
+        if op.kind == "matrix":
+            ops.append(W.Op("matrix", op.targets, op.controls, matrix=op.matrix.conj().T))
+        elif op.kind in ("rx", "ry", "rz"):
+            ops.append(W.Op(op.kind, op.targets, op.controls, param=op.param))
+        else:  # h, x, y, z, swap are their own inverses
+            ops.append(W.Op(op.kind, op.targets, op.controls))
+    inv = W.Circuit(circ.n, ops, circ.nparams)
+    return inv, (None if params is None else -np.asarray(params))
+
+
+@pytest.mark.parametrize("which", ["pairs28", "dense32"])
+def test_full_size_fused_round_trip(q, orc, which):
+    """Full workload sizes: the random-pairs circuit at n = 28 (fused up to 5
+    qubits) and the random 1-3-qubit circuit at n = 32 (fused to 5-qubit MFMA
+    blocks), each followed by its inverse, must return the seeded input; the
+    result is checked amplitude by amplitude against the oracle's values of
+    the seeded state at sampled indices, and the norm is checked too."""
+    import torch
+    if which == "pairs28":
+        circ, params = W.random_u2_pairs(n=28, depth=20, seed=1001)
+    else:
+        circ, params = W.random_dense_123(n=32, depth=12, seed=1002), None
+    inv, iparams = inverse_circuit(circ, params)
+    n, seed = circ.n, 77
+    scale = 1.0 / np.sqrt(orc.random_norm2(n, seed))
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([rng.integers(0, 1 << n, 200), [0, (1 << n) - 1]]).astype(np.uint64)
+    ref = orc.random_amps(seed, scale, idx)
+    rms = 1.0 / np.sqrt(float(1 << n))  # typical |amplitude|
+    for name in DTYPES:
+        for fuse in [5, 3]:
+            say("round trip", which, name, "fuse", fuse)
+            dc = 1 if name == "c64" else 2
+            fwd = q.Plan(circ, dc, fuse, params)
+            bwd = q.Plan(inv, dc, fuse, iparams)
+            d = torch.empty(1 << n, dtype=torch_dtype(name), device="cuda")
+            q.qsv_init_random(d, seed)
+            fwd.run(d)
+            mid = q.qsv_norm2(d).cpu().numpy()[0]
+            bwd.run(d)
+            got = d[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().astype(np.complex128)
+            err = np.max(np.abs(got - ref))
+            # a few hundred gate applications: rounding grows like sqrt(#ops)
+            # times the unit roundoff, relative to the typical amplitude
+            tol = (1e-10 if name == "c128" else 1e-4) * rms
+            assert abs(mid - 1.0) < (1e-12 if name == "c128" else 1e-4), mid
+            assert err <= tol, (which, name, fuse, err)
+            del d, fwd, bwd
+            torch.cuda.empty_cache()
+
+
+def test_n32_sampled(q, orc):
+    """n = 32 (32 GiB complex64, 64 GiB complex128): single gates at low and
+    high targets, a controlled gate and a 5-qubit MFMA block, sampled against
+    the oracle evaluated one output at a time on the same seeded input."""
+    import torch
+    n, seed = 32, 4243
+    scale = 1.0 / np.sqrt(orc.random_norm2(n, seed))
+    rng = np.random.default_rng(78)
+    idx = np.concatenate([rng.integers(0, 1 << n, 60), [0, (1 << n) - 1, 1 << 31, (1 << 31) - 1,
+                                                       (1 << 32) - 2]]).astype(np.uint64)
+    gates = [((0,), ()), ((31,), ()), ((30, 1), ()), ((31,), (0,)), ((0, 1, 2, 3, 4), ()),
+             ((27, 28, 29, 30, 31), ()), ((0, 31, 16, 8, 24), ())]
+    for name in DTYPES:
+        d = torch.empty(1 << n, dtype=torch_dtype(name), device="cuda")
+        for t, c in gates:
+            G = W.haar_unitary(rng, 2 ** len(t))
+            say("n32", name, t, c)
+            q.qsv_init_random(d, seed)
+            q.qsv_apply_gate(d, t, c, G)
+            got = d[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().astype(np.complex128)
+            ref = orc.apply_sampled_random(n, seed, scale, t, c, G, idx)
+            err = np.max(np.abs(got - ref))
+            assert err <= TOL[name] and err / np.max(np.abs(ref)) <= 1e-5, (name, t, c, err)
+        del d
+        torch.cuda.empty_cache()
