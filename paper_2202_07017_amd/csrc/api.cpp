@@ -599,16 +599,15 @@ void plan_tiles(const qsv_pauli_sum* H, int n, std::vector<TileExpK>& out,
             x.z = t.z;
             x.c = t.c;
             x.zloc = compress(t.z);
-            x.ylo = (int16_t)t.ylo;
+            x.ylo = t.ylo;
             if (t.x == 0) {
                 x.kind = 0;
                 const bool lo = (x.zloc & 63) != 0, hi = (x.zloc >> 6) != 0;
-                x.dpart = (int8_t)(lo && hi ? 3 : (hi ? 2 : 1));
+                x.dpart = (lo && hi ? 3 : (hi ? 2 : 1));
                 (x.dpart == 3 ? str : tab).push_back(x);
             } else {
                 x.xloc = compress(t.x);
-                x.hloc = 1u << (31 - __builtin_clz(x.xloc));
-                x.kind = (int8_t)((t.z == 0 && t.ylo == 0) ? 2 : 1);
+                x.kind = (t.z == 0 && t.ylo == 0) ? 2 : 1;
                 pairs.push_back(x);
             }
         }
@@ -646,6 +645,11 @@ void plan_tiles(const qsv_pauli_sum* H, int n, std::vector<TileExpK>& out,
             while (pi < pairs.size() && nt < kMaxTileTerms)
                 k.t[nt++] = pairs[pi++];
             k.nt = nt;
+            // pure X strings first (their loop needs no phase)
+            std::stable_partition(k.t + k.pstart, k.t + k.nt, [](const XTerm& x) { return x.kind == 2; });
+            k.pxend = k.pstart;
+            while (k.pxend < k.nt && k.t[k.pxend].kind == 2)
+                ++k.pxend;
             out.push_back(k);
         }
     }

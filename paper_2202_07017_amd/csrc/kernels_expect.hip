@@ -7,6 +7,9 @@
 // read of the state serves all of them; the terms of a Hamiltonian are split
 // into passes by their x masks on the host.
 //
+// A tile is held in LDS in FP64 (both state precisions), so each term costs
+// one 16-byte LDS read and two FMAs per amplitude.
+//
 // Phases i^(y + 2 popcount(i & z)) are split into a per-tile part
 // (popcount(base & z)) and a local part (popcount(l & zloc), zloc = z
 // compressed onto B).  Diagonal terms are folded per tile into two tables
@@ -20,18 +23,24 @@ namespace {
 
 constexpr int kM = kTileQubits;   // 12
 constexpr int kTA = 1 << kM;      // amplitudes per tile
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
+constexpr int kAPT = kTA / kThreads;  // amplitudes per thread (8)
+
+// native vector types (not HIP's float4 / double2 classes): a loop-carried
+// array of them stays in registers
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <typename R>
 struct EV;
 template <>
 struct EV<float> {
-    using V = float4;
+    using V = f32x4;  // two amplitudes
     static constexpr int APV = 2;
 };
 template <>
 struct EV<double> {
-    using V = double2;
+    using V = f64x2;  // one amplitude
     static constexpr int APV = 1;
 };
 
@@ -48,49 +57,22 @@ __device__ __forceinline__ uint64_t insert_bits(uint64_t g, const InsertSpec& s)
     return g;
 }
 
-// i^e for e in 0..3
-__device__ __forceinline__ C2 ipow(int e)
+__device__ __forceinline__ C2 lds_amp(const f64x2* t, uint32_t l)
 {
-    e &= 3;
-    return C2{e == 0 ? 1.0 : (e == 2 ? -1.0 : 0.0), e == 1 ? 1.0 : (e == 3 ? -1.0 : 0.0)};
-}
-
-__device__ __forceinline__ float vcomp(const float4& v, int c)
-{
-    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
-}
-__device__ __forceinline__ double vcomp(const double2& v, int c)
-{
-    return c == 0 ? v.x : v.y;
-}
-__device__ __forceinline__ float4 mkv(const float* o)
-{
-    return make_float4(o[0], o[1], o[2], o[3]);
-}
-__device__ __forceinline__ double2 mkv(const double* o)
-{
-    return make_double2(o[0], o[1]);
-}
-
-template <typename R>
-__device__ __forceinline__ C2 lds_amp(const R* t, uint32_t l)
-{
-    return C2{(double)t[2 * l], (double)t[2 * l + 1]};
+    const f64x2 v = t[l];
+    return C2{v.x, v.y};
 }
 
 // Shared state of a tile pass.
 struct TileShared {
     double wa[64];
     double wb[kTA / 64];
-    int tphase[kMaxTileTerms];  // per-term tile phase offset: y + 2 popcount(base & z)
     double red[2][kThreads / 64];
 };
 
-// Per tile: tile phase offsets for every term and the diagonal tables.
+// Per tile: the diagonal tables.
 __device__ void tile_prologue(const TileExpK& a, uint64_t base, TileShared& sh)
 {
-    for (int t = threadIdx.x; t < a.nt; t += blockDim.x)
-        sh.tphase[t] = a.t[t].ylo + 2 * __popcll(base & a.t[t].z);
     if (a.ndiag == 0)
         return;
     for (int e = threadIdx.x; e < 64 + kTA / 64; e += blockDim.x) {
@@ -111,119 +93,202 @@ __device__ void tile_prologue(const TileExpK& a, uint64_t base, TileShared& sh)
     }
 }
 
-// Diagonal weight of local amplitude l (tables + straddling terms).
-__device__ __forceinline__ double diag_weight(const TileExpK& a, const TileShared& sh, uint32_t l)
+// Adds c * i^e * psi_j to h for the amplitudes of a thread, for a pair term
+// with uniform swap (e odd) and per-amplitude sign (bit 1 of e).
+template <bool SWP>
+__device__ __forceinline__ void pair_term(const f64x2* tile, uint32_t A, double c, uint32_t sl,
+                                          const uint32_t (&sk)[kAPT], C2 (&hs)[kAPT])
 {
-    double w = sh.wa[l & 63] + sh.wb[l >> 6];
-    for (int t = 0; t < a.nstr; ++t) {
-        const XTerm& T = a.t[t];
-        w += ((sh.tphase[t] >> 1) + __popc(l & T.zloc)) & 1 ? -T.c : T.c;
+#pragma unroll
+    for (int j = 0; j < kAPT; ++j) {
+        const C2 q = lds_amp(tile, A ^ (uint32_t)(kThreads * j));
+        const double cs = ((sl ^ sk[j]) & 1) ? -c : c;
+        hs[j].re += cs * (SWP ? -q.im : q.re);
+        hs[j].im += cs * (SWP ? q.re : q.im);
     }
-    return w;
 }
 
+// One kernel for both products: every amplitude i of a tile gets
+// h_i = w_i psi_i + sum_t c_t i^e_t(j) psi_j (j = i xor x_t, the terms of the
+// pass), i.e. (H psi)_i restricted to the pass.  HPSI stores (or adds) h;
+// otherwise the block sums conj(psi_i) h_i, whose total over all passes is
+// <psi|H|psi>.  Terms are the outer loop over the 8 amplitudes of a thread,
+// so each term's scalar data is read once and its 8 LDS partner reads are in
+// flight together.
+//
+// Indexing: amplitude j of a thread has local index lt | K_j with lt =
+// threadIdx.x and K_j = kThreads * j (consecutive lanes read consecutive LDS
+// words: no bank conflicts).  Global offsets, partner indices and phase
+// parities are linear in the local bits, so the K_j parts are uniform
+// (scalar) and a lane keeps only lt.  The grid is one block per resident
+// slot.
 template <typename R, bool HPSI>
-__global__ void __launch_bounds__(kThreads) k_tile_pass(const R* __restrict__ psi, R* __restrict__ lam,
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_tile_pass(const R* __restrict__ psi, R* __restrict__ lam,
                                                         const TileExpK a, double* partials,
-                                                        int accumulate)
+                                                        int pstride, int accumulate)
 {
     using V = typename EV<R>::V;
     constexpr int APV = EV<R>::APV;
-    constexpr int VPT = kTA / APV / kThreads;
-    __shared__ R tile[2 * kTA];
+    constexpr int VPT = kTA / APV / kThreads;  // loaded vectors per thread
+    __shared__ f64x2 tile[kTA];
     __shared__ TileShared sh;
 
-    uint64_t goff[VPT];
-    uint32_t loc[VPT];
+    const uint32_t lmask = (1u << a.L) - 1;
+    auto goff = [&](uint32_t l) { return a.choff[l >> a.L] + (l & lmask); };
+    const uint64_t gv = goff(threadIdx.x * APV);  // lane part of the load offsets
+    const uint64_t gt = goff(threadIdx.x);        // lane part of the compute offsets
+    double er = 0.0, ei = 0.0;
+    // complex64 prefetches the next tile into registers; complex128 (twice
+    // the registers per amplitude) loads each tile at the top of its iteration
+    constexpr bool PF = APV == 2;
+    V nxt[VPT];
+    if (PF && blockIdx.x < a.ntiles) {
+        const uint64_t b = insert_bits(blockIdx.x, a.ins);
 #pragma unroll
-    for (int r = 0; r < VPT; ++r) {
-        const uint32_t l = (uint32_t)(threadIdx.x + kThreads * r) * APV;
-        loc[r] = l;
-        goff[r] = a.choff[l >> a.L] + (l & ((1u << a.L) - 1));
+        for (int r = 0; r < VPT; ++r)
+            nxt[r] = *reinterpret_cast<const V*>(psi + 2 * (b + goff(APV * kThreads * r) + gv));
     }
-    double sr = 0.0, si = 0.0;
     for (uint64_t tl = blockIdx.x; tl < a.ntiles; tl += gridDim.x) {
         const uint64_t base = insert_bits(tl, a.ins);
-        V own[VPT];
+        if (!PF) {
+            uint64_t gvl = gv;
+            asm volatile("" : "+v"(gvl));
+#pragma unroll
+            for (int r = 0; r < VPT; ++r)
+                nxt[r] = *reinterpret_cast<const V*>(psi + 2 * (base + goff(APV * kThreads * r) + gvl));
+        }
 #pragma unroll
         for (int r = 0; r < VPT; ++r) {
-            own[r] = *reinterpret_cast<const V*>(psi + 2 * (base + goff[r]));
-            *reinterpret_cast<V*>(tile + 2 * loc[r]) = own[r];
+            const uint32_t l = APV * (threadIdx.x + kThreads * r);
+            if (APV == 2) {
+                tile[l] = f64x2{(double)nxt[r][0], (double)nxt[r][1]};
+                tile[l + 1] = f64x2{(double)nxt[r][2], (double)nxt[r][3]};
+            } else {
+                tile[l] = f64x2{(double)nxt[r][0], (double)nxt[r][1]};
+            }
         }
         tile_prologue(a, base, sh);
         __syncthreads();
+        if (PF) {
+            // next tile (the last one reloads itself: no branch around the
+            // loads); the opaque lane offset keeps the VPT sums with the
+            // uniform parts from being hoisted into registers
+            const uint64_t tn = tl + gridDim.x < a.ntiles ? tl + gridDim.x : tl;
+            const uint64_t b = insert_bits(tn, a.ins);
+            uint64_t gvl = gv;
+            asm volatile("" : "+v"(gvl));
 #pragma unroll
-        for (int r = 0; r < VPT; ++r) {
-            R outv[2 * APV];
+            for (int r = 0; r < VPT; ++r)
+                nxt[r] = *reinterpret_cast<const V*>(psi + 2 * (b + goff(APV * kThreads * r) + gvl));
+        }
+        // opaque copy of the lane index: keeps the compiler from hoisting the
+        // per-amplitude LDS addresses out of the tile loop into registers
+        uint32_t lt = threadIdx.x;
+        asm volatile("" : "+v"(lt));
+        C2 hs[kAPT];
+        {
+            double w[kAPT];
 #pragma unroll
-            for (int h = 0; h < APV; ++h) {
-                const uint32_t l = loc[r] + h;
-                const C2 p{(double)vcomp(own[r], 2 * h), (double)vcomp(own[r], 2 * h + 1)};
-                C2 lsum{0.0, 0.0};
-                if (a.ndiag) {
-                    const double w = diag_weight(a, sh, l);
-                    if (HPSI) {
-                        lsum.re += w * p.re;
-                        lsum.im += w * p.im;
-                    } else {
-                        sr += w * (p.re * p.re + p.im * p.im);
-                    }
+            for (int j = 0; j < kAPT; ++j) {
+                const uint32_t l = lt | (uint32_t)(kThreads * j);
+                w[j] = a.ndiag ? sh.wa[l & 63] + sh.wb[l >> 6] : 0.0;
+            }
+#pragma unroll 1
+            for (int t = 0; t < a.nstr; ++t) {  // diagonal terms straddling both table halves
+                const XTerm& T = a.t[t];
+                const uint32_t zl = T.zloc;
+                const uint32_t sl = (uint32_t)__popcll(base & T.z) ^ (uint32_t)__popc(lt & zl);
+                const double c = T.c;
+#pragma unroll
+                for (int j = 0; j < kAPT; ++j)
+                    w[j] += ((sl ^ (uint32_t)__popc((uint32_t)(kThreads * j) & zl)) & 1) ? -c : c;
+            }
+            if (a.ndiag) {
+#pragma unroll
+                for (int j = 0; j < kAPT; ++j) {  // psi_i is re-read at the end: not live across the terms
+                    const C2 p = lds_amp(tile, lt | (uint32_t)(kThreads * j));
+                    hs[j] = C2{w[j] * p.re, w[j] * p.im};
                 }
-                for (int t = a.pstart; t < a.nt; ++t) {
-                    const XTerm& T = a.t[t];
-                    const uint32_t lj = l ^ T.xloc;
-                    if (HPSI) {
-                        // (P psi)[i] = i^(phase of j) psi[j], j = i xor x
-                        const C2 q = lds_amp(tile, lj);
-                        if (T.kind == 2) {
-                            lsum.re += T.c * q.re;
-                            lsum.im += T.c * q.im;
-                        } else {
-                            const C2 f = ipow(sh.tphase[t] + 2 * __popc(lj & T.zloc));
-                            lsum.re += T.c * (f.re * q.re - f.im * q.im);
-                            lsum.im += T.c * (f.re * q.im + f.im * q.re);
-                        }
-                    } else {
-                        if (l & T.hloc)
-                            continue;  // the pair is counted by its lower member
-                        const C2 q = lds_amp(tile, lj);
-                        const double wr = q.re * p.re + q.im * p.im;  // conj(q) p
-                        const double wi = q.re * p.im - q.im * p.re;
-                        if (T.kind == 2) {
-                            sr += 2.0 * T.c * wr;
-                        } else {
-                            const C2 fi = ipow(sh.tphase[t] + 2 * __popc(l & T.zloc));
-                            const C2 fj = ipow(sh.tphase[t] + 2 * __popc(lj & T.zloc));
-                            const double pr = fi.re + fj.re, pi = fi.im - fj.im;
-                            const double qr = fi.re - fj.re, qi = fi.im + fj.im;
-                            sr += T.c * (wr * pr - wi * pi);
-                            si += T.c * (wr * qi + wi * qr);
-                        }
-                    }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kAPT; ++j)
+                    hs[j] = C2{0.0, 0.0};
+            }
+        }
+#pragma unroll 1
+        for (int t = a.pstart; t < a.pxend; ++t) {  // pure X strings
+            const XTerm& T = a.t[t];
+            const double c = T.c;
+            const uint32_t A = lt ^ T.xloc;  // partner of lt | K_j is A ^ K_j
+            if ((T.xloc & ~(uint32_t)(kThreads - 1)) == 0) {
+                // x only in lane bits: A ^ K_j = A + K_j, immediate LDS offsets
+                const f64x2* tp = tile + A;
+#pragma unroll
+                for (int j = 0; j < kAPT; ++j) {
+                    const f64x2 q = tp[kThreads * j];
+                    hs[j].re += c * q.x;
+                    hs[j].im += c * q.y;
                 }
-                if (HPSI) {
-                    if (accumulate) {
-                        const R* lv = lam + 2 * (base + goff[r] + h);
-                        lsum.re += (double)lv[0];
-                        lsum.im += (double)lv[1];
-                    }
-                    outv[2 * h] = (R)lsum.re;
-                    outv[2 * h + 1] = (R)lsum.im;
+            } else {
+#pragma unroll
+                for (int j = 0; j < kAPT; ++j) {
+                    const C2 q = lds_amp(tile, A ^ (uint32_t)(kThreads * j));
+                    hs[j].re += c * q.re;
+                    hs[j].im += c * q.im;
                 }
             }
-            if (HPSI)
-                *reinterpret_cast<V*>(lam + 2 * (base + goff[r])) = mkv(outv);
+        }
+#pragma unroll 1
+        for (int t = a.pxend; t < a.nt; ++t) {
+            // (P psi)_i = i^e psi_j, e = y + 2 popcount(j & z): bit 0 of e is
+            // uniform, bit 1 is the parity of the tile and local parts
+            const XTerm& T = a.t[t];
+            const double c = T.c;
+            const uint32_t A = lt ^ T.xloc;
+            const uint32_t zl = T.zloc;
+            const int tph = T.ylo + 2 * __popcll(base & T.z);
+            const uint32_t sl = (uint32_t)(tph >> 1) ^ (uint32_t)__popc(A & zl);
+            uint32_t sk[kAPT];
+#pragma unroll
+            for (int j = 0; j < kAPT; ++j)
+                sk[j] = (uint32_t)__popc((uint32_t)(kThreads * j) & zl);
+            if (tph & 1)
+                pair_term<true>(tile, A, c, sl, sk, hs);
+            else
+                pair_term<false>(tile, A, c, sl, sk, hs);
+        }
+        if (HPSI) {
+#pragma unroll
+            for (int j = 0; j < kAPT; ++j) {
+                R* dst = lam + 2 * (base + gt + goff((uint32_t)(kThreads * j)));
+                C2 o = hs[j];
+                if (accumulate) {
+                    o.re += (double)dst[0];
+                    o.im += (double)dst[1];
+                }
+                dst[0] = (R)o.re;
+                dst[1] = (R)o.im;
+            }
+        } else {
+            uint32_t lt2 = lt;  // opaque: a fresh read, not values kept from the start
+            asm volatile("" : "+v"(lt2));
+#pragma unroll
+            for (int j = 0; j < kAPT; ++j) {
+                const C2 p = lds_amp(tile, lt2 | (uint32_t)(kThreads * j));
+                er += p.re * hs[j].re + p.im * hs[j].im;  // conj(psi_i) h_i
+                ei += p.re * hs[j].im - p.im * hs[j].re;
+            }
         }
         __syncthreads();
     }
     if (!HPSI) {
         for (int off = 32; off > 0; off >>= 1) {
-            sr += __shfl_xor(sr, off, 64);
-            si += __shfl_xor(si, off, 64);
+            er += __shfl_xor(er, off, 64);
+            ei += __shfl_xor(ei, off, 64);
         }
         if ((threadIdx.x & 63) == 0) {
-            sh.red[0][threadIdx.x >> 6] = sr;
-            sh.red[1][threadIdx.x >> 6] = si;
+            sh.red[0][threadIdx.x >> 6] = er;
+            sh.red[1][threadIdx.x >> 6] = ei;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -233,43 +298,73 @@ __global__ void __launch_bounds__(kThreads) k_tile_pass(const R* __restrict__ ps
                 a1 += sh.red[1][w];
             }
             double* p = partials + blockIdx.x;
-            double* q = partials + gridDim.x + blockIdx.x;
+            double* q = partials + pstride + blockIdx.x;
             *p = accumulate ? *p + a0 : a0;
             *q = accumulate ? *q + a1 : a1;
         }
+        if (!accumulate)  // slots beyond the grid start at zero for later passes
+            for (int b = gridDim.x + blockIdx.x * kThreads + threadIdx.x; b < pstride;
+                 b += gridDim.x * kThreads) {
+                partials[b] = 0.0;
+                partials[pstride + b] = 0.0;
+            }
     }
 }
 
 }  // namespace
 
+// Blocks of the tile pass resident on the whole device (the grid: one block
+// per resident slot, each streaming tiles with the next tile's loads in
+// flight).  Cached per device and kernel variant.
+template <typename R, bool HPSI>
+int resident_grid()
+{
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 1024;
+    if (cache[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pass<R, HPSI>, kThreads, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            per_cu < 1 || cus < 1)
+            return 1024;
+        cache[dev] = per_cu * cus;
+    }
+    return cache[dev];
+}
+
 hipError_t launch_tile_pass(const TileExpK& a, const void* psi, void* lam, int dt, bool hpsi,
-                            double* partials, int nblocks, int accumulate, hipStream_t s)
+                            double* partials, int nslots, int accumulate, hipStream_t s)
 {
     if (a.ntiles == 0)
         return hipSuccess;
-    unsigned blocks = (unsigned)nblocks;
-    if (hpsi) {
-        const uint64_t b = a.ntiles < 4096 ? a.ntiles : 4096;
-        blocks = (unsigned)b;
-    }
+    int g = dt == C64 ? (hpsi ? resident_grid<float, true>() : resident_grid<float, false>())
+                      : (hpsi ? resident_grid<double, true>() : resident_grid<double, false>());
+    if (!hpsi && g > nslots)
+        g = nslots;  // partial slots: block b writes slot b, the first pass zeroes the rest
+    if ((uint64_t)g > a.ntiles)
+        g = (int)a.ntiles;
+    const dim3 grid((unsigned)g);
     if (dt == C64) {
         if (hpsi)
-            hipLaunchKernelGGL((k_tile_pass<float, true>), dim3(blocks), dim3(kThreads), 0, s,
+            hipLaunchKernelGGL((k_tile_pass<float, true>), grid, dim3(kThreads), 0, s,
                                static_cast<const float*>(psi), static_cast<float*>(lam), a, partials,
-                               accumulate);
+                               nslots, accumulate);
         else
-            hipLaunchKernelGGL((k_tile_pass<float, false>), dim3(blocks), dim3(kThreads), 0, s,
+            hipLaunchKernelGGL((k_tile_pass<float, false>), grid, dim3(kThreads), 0, s,
                                static_cast<const float*>(psi), static_cast<float*>(lam), a, partials,
-                               accumulate);
+                               nslots, accumulate);
     } else {
         if (hpsi)
-            hipLaunchKernelGGL((k_tile_pass<double, true>), dim3(blocks), dim3(kThreads), 0, s,
+            hipLaunchKernelGGL((k_tile_pass<double, true>), grid, dim3(kThreads), 0, s,
                                static_cast<const double*>(psi), static_cast<double*>(lam), a, partials,
-                               accumulate);
+                               nslots, accumulate);
         else
-            hipLaunchKernelGGL((k_tile_pass<double, false>), dim3(blocks), dim3(kThreads), 0, s,
+            hipLaunchKernelGGL((k_tile_pass<double, false>), grid, dim3(kThreads), 0, s,
                                static_cast<const double*>(psi), static_cast<double*>(lam), a, partials,
-                               accumulate);
+                               nslots, accumulate);
     }
     return hipGetLastError();
 }

@@ -10,6 +10,13 @@
 // For complex64 states two adjacent amplitudes are moved as one 16-byte
 // float4 (modes W2 / INTRA), which keeps 16-byte accesses for every target
 // position including qubit 0.
+//
+// Launch shape (measured on MI355X at n = 30): one group per thread, blocks
+// visited in XCD-contiguous order (the hardware deals blocks round-robin to
+// the 8 XCDs; remapping block b to (b mod 8) * G/8 + b / 8 hands each XCD one
+// contiguous eighth of the state), nontemporal loads and stores once the
+// contiguous runs are >= 128 bytes, and a lane-exchange kernel for
+// uncontrolled single-qubit gates whose partner sits within 64 units.
 #include <cstdlib>
 
 #include "qsv_internal.h"
@@ -37,6 +44,13 @@ __device__ __forceinline__ uint64_t insert_bits(uint64_t g, const InsertSpec& s)
         g = ((g & ~lo) << 1) | (g & lo);
     }
     return g | s.setmask;
+}
+
+// Block index in XCD-contiguous order (a bijection on [0, gridDim.x)).
+__device__ __forceinline__ uint64_t xcd_block()
+{
+    const uint32_t G = gridDim.x, b = blockIdx.x, per = G >> 3;
+    return b < (per << 3) ? (uint64_t)(b & 7u) * per + (b >> 3) : (uint64_t)b;
 }
 
 template <typename R>
@@ -98,6 +112,50 @@ template <bool NT>
 __device__ __forceinline__ void stv(float2* p, float2 v)
 {
     *p = v;
+}
+
+// Raw 8- and 16-byte units (permutations), optionally nontemporal.
+typedef unsigned int nv2u __attribute__((ext_vector_type(2)));
+typedef unsigned int nv4u __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ uint4 ldu(const uint4* p)
+{
+    if constexpr (NT) {
+        const nv4u v = __builtin_nontemporal_load(reinterpret_cast<const nv4u*>(p));
+        return make_uint4(v[0], v[1], v[2], v[3]);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ uint2 ldu(const uint2* p)
+{
+    if constexpr (NT) {
+        const nv2u v = __builtin_nontemporal_load(reinterpret_cast<const nv2u*>(p));
+        return make_uint2(v[0], v[1]);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void stu(uint4* p, uint4 v)
+{
+    if constexpr (NT) {
+        nv4u w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<nv4u*>(p));
+    } else {
+        *p = v;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void stu(uint2* p, uint2 v)
+{
+    if constexpr (NT) {
+        nv2u w = {v.x, v.y};
+        __builtin_nontemporal_store(w, reinterpret_cast<nv2u*>(p));
+    } else {
+        *p = v;
+    }
 }
 
 template <typename R>
@@ -175,7 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(R* __restrict__ psi0, R* __res
     };
 
     const uint64_t step = (uint64_t)gridDim.x * kBlock * UNR;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * kBlock * UNR + threadIdx.x; g0 < a.ngroups; g0 += step) {
+    for (uint64_t g0 = xcd_block() * kBlock * UNR + threadIdx.x; g0 < a.ngroups; g0 += step) {
         uint64_t base[UNR];
         bool ok[UNR];
 #pragma unroll
@@ -258,6 +316,64 @@ __global__ void __launch_bounds__(kBlock) k_dense(R* __restrict__ psi0, R* __res
     }
 }
 
+// Uncontrolled single-qubit gate whose target is unit bit tb < 6 (complex64:
+// qubit tb + 1, the two amplitudes of a float4 share the target bit;
+// complex128: qubit tb).  One 16-byte unit per thread: the partner unit
+// (target bit flipped) sits in lane xor 2^tb of the same wavefront, so every
+// load and store of a wavefront is one contiguous 1 KB run and the pair is
+// exchanged across lanes.  nunits is a multiple of kBlock, so every lane of
+// a block runs the same iterations.
+template <typename R, bool ROT>
+__global__ void __launch_bounds__(kBlock) k_dense_lane(R* __restrict__ psi0, R* __restrict__ psi1,
+                                                       const DenseK<R, 1> a, uint64_t nunits, int tb)
+{
+    R* psi = blockIdx.y ? psi1 : psi0;
+    R m[8];
+    if constexpr (ROT) {
+        const double th = a.params[a.pidx];
+        rotation_matrix<R>(a.rot, a.dag ? -th : th, m);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            m[j] = a.g[j];
+    }
+    const int mask = 1 << tb;
+    const uint64_t step = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = xcd_block() * kBlock + threadIdx.x; i < nunits; i += step) {
+        const bool hi = ((i >> tb) & 1u) != 0;
+        // row `hi` of the gate: out = g[hi][0] * (bit-0 unit) + g[hi][1] * (bit-1 unit)
+        const R ar = hi ? m[4] : m[0], ai = hi ? m[5] : m[1];
+        const R br = hi ? m[6] : m[2], bi = hi ? m[7] : m[3];
+        if constexpr (sizeof(R) == 4) {
+            float4* p = reinterpret_cast<float4*>(psi);
+            const float4 x = p[i];
+            float4 y;
+            y.x = __shfl_xor(x.x, mask, 64);
+            y.y = __shfl_xor(x.y, mask, 64);
+            y.z = __shfl_xor(x.z, mask, 64);
+            y.w = __shfl_xor(x.w, mask, 64);
+            const float4 u0 = hi ? y : x, u1 = hi ? x : y;
+            float4 o;
+            o.x = ar * u0.x - ai * u0.y + br * u1.x - bi * u1.y;
+            o.y = ar * u0.y + ai * u0.x + br * u1.y + bi * u1.x;
+            o.z = ar * u0.z - ai * u0.w + br * u1.z - bi * u1.w;
+            o.w = ar * u0.w + ai * u0.z + br * u1.w + bi * u1.z;
+            p[i] = o;
+        } else {
+            double2* p = reinterpret_cast<double2*>(psi);
+            const double2 x = p[i];
+            double2 y;
+            y.x = __shfl_xor(x.x, mask, 64);
+            y.y = __shfl_xor(x.y, mask, 64);
+            const double2 u0 = hi ? y : x, u1 = hi ? x : y;
+            double2 o;
+            o.x = ar * u0.x - ai * u0.y + br * u1.x - bi * u1.y;
+            o.y = ar * u0.y + ai * u0.x + br * u1.y + bi * u1.x;
+            p[i] = o;
+        }
+    }
+}
+
 // --------------------------------------------------------------- diagonal
 
 template <typename R>
@@ -272,7 +388,7 @@ struct DiagK {
     int dag;
 };
 
-template <typename R, int MODE, bool ROT, int UNR>
+template <typename R, int MODE, bool ROT, int UNR, bool NT>
 __global__ void __launch_bounds__(kBlock) k_diag(R* __restrict__ psi0, R* __restrict__ psi1,
                                                  const DiagK<R> a)
 {
@@ -300,7 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(R* __restrict__ psi0, R* __rest
         return t;
     };
     const uint64_t step = (uint64_t)gridDim.x * kBlock * UNR;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * kBlock * UNR + threadIdx.x; g0 < a.ngroups; g0 += step) {
+    for (uint64_t g0 = xcd_block() * kBlock * UNR + threadIdx.x; g0 < a.ngroups; g0 += step) {
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             const uint64_t g = g0 + (uint64_t)u * kBlock;
@@ -309,21 +425,21 @@ __global__ void __launch_bounds__(kBlock) k_diag(R* __restrict__ psi0, R* __rest
             const uint64_t idx = insert_bits(g, a.ins);
             if constexpr (MODE == W1) {
                 A* p = reinterpret_cast<A*>(psi);
-                A x = p[idx];
+                A x = ldv<NT>(&p[idx]);
                 const int t = tau_of(idx);
                 const R dr = dl[2 * t], di = dl[2 * t + 1];
                 A o;
                 o.x = dr * x.x - di * x.y;
                 o.y = dr * x.y + di * x.x;
-                p[idx] = o;
+                stv<NT>(&p[idx], o);
             } else {
                 float4* p = reinterpret_cast<float4*>(psi);
-                float4 x = p[idx];
+                float4 x = ldv<NT>(&p[idx]);
                 const int t0 = tau_of(idx << 1), t1 = tau_of((idx << 1) | 1u);
                 const float d0r = dl[2 * t0], d0i = dl[2 * t0 + 1];
                 const float d1r = dl[2 * t1], d1i = dl[2 * t1 + 1];
-                p[idx] = make_float4(d0r * x.x - d0i * x.y, d0r * x.y + d0i * x.x,
-                                     d1r * x.z - d1i * x.w, d1r * x.w + d1i * x.z);
+                stv<NT>(&p[idx], make_float4(d0r * x.x - d0i * x.y, d0r * x.y + d0i * x.x,
+                                             d1r * x.z - d1i * x.w, d1r * x.w + d1i * x.z));
             }
         }
     }
@@ -342,13 +458,13 @@ struct PermK {
 // Pure moves of raw bits (no arithmetic, so signed zeros and NaN payloads
 // survive).  UT is the raw unit type (uint2 = one c64 amplitude, uint4 = one
 // c128 amplitude or two adjacent c64 amplitudes).
-template <typename UT, int NM, int UNR>
+template <typename UT, int NM, int UNR, bool NT>
 __global__ void __launch_bounds__(kBlock) k_perm(UT* __restrict__ psi0, UT* __restrict__ psi1,
                                                  const PermK a)
 {
     UT* p = blockIdx.y ? psi1 : psi0;
     const uint64_t step = (uint64_t)gridDim.x * kBlock * UNR;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * kBlock * UNR + threadIdx.x; g0 < a.ngroups; g0 += step) {
+    for (uint64_t g0 = xcd_block() * kBlock * UNR + threadIdx.x; g0 < a.ngroups; g0 += step) {
         UT x[UNR][NM];
         uint64_t base[UNR];
         bool ok[UNR];
@@ -360,14 +476,14 @@ __global__ void __launch_bounds__(kBlock) k_perm(UT* __restrict__ psi0, UT* __re
 #pragma unroll
             for (int j = 0; j < NM; ++j)
                 if (ok[u] && j < a.nmoved)
-                    x[u][j] = p[base[u] + a.src[j]];
+                    x[u][j] = ldu<NT>(&p[base[u] + a.src[j]]);
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
 #pragma unroll
             for (int j = 0; j < NM; ++j)
                 if (ok[u] && j < a.nmoved)
-                    p[base[u] + a.dst[j]] = x[u][j];
+                    stu<NT>(&p[base[u] + a.dst[j]], x[u][j]);
     }
 }
 
@@ -489,32 +605,22 @@ DenseK<R, K> dense_args(const GateLaunch& L)
     return a;
 }
 
-// Groups per thread (UNR) and the nontemporal hint of the sweeps.  Measured
-// on MI355X at n = 30: one group per thread is fastest, and the nontemporal
-// hint gains up to 10% once the lowest touched qubit is >= 2 (the two halves
-// of a pair then sit in different 32-byte sectors) but not below.
-// QSV_SWEEP_UNROLL / QSV_SWEEP_NT (0/1) override the choice.
-struct SweepTune {
-    int unr = 1;
-    bool nt = false;
-};
-
-SweepTune sweep_tune(int lowest_qubit)
+// Nontemporal hint: on once the contiguous runs of a launch (2^p units, p the
+// lowest inserted unit bit) are >= 128 bytes; below that it loses on MI355X.
+// QSV_SWEEP_NT (0/1) overrides the choice.
+bool use_nt(const InsertSpec& ins, int unit_bytes)
 {
-    SweepTune t;
-    t.nt = lowest_qubit >= 2;
-    if (const char* e = getenv("QSV_SWEEP_UNROLL"))
-        t.unr = atoi(e) <= 1 ? 1 : (atoi(e) >= 4 ? 4 : 2);
     if (const char* e = getenv("QSV_SWEEP_NT"))
-        t.nt = e[0] == '1';
-    return t;
+        return e[0] == '1';
+    const int p = ins.nins ? __builtin_ctzll(ins.low[0] + 1) : 63;
+    return p >= 16 || ((uint64_t)unit_bytes << p) >= 128;
 }
 
-template <typename R, int K, int MODE, bool ROT, int UNR, bool NT>
+template <typename R, int K, int MODE, bool ROT, bool NT>
 hipError_t dense_launch(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
 {
-    dim3 grid(grid_for(L.ngroups, UNR), p1 ? 2 : 1);
-    hipLaunchKernelGGL((k_dense<R, K, MODE, ROT, UNR, NT>), grid, dim3(kBlock), 0, s,
+    dim3 grid(grid_for(L.ngroups, 1), p1 ? 2 : 1);
+    hipLaunchKernelGGL((k_dense<R, K, MODE, ROT, 1, NT>), grid, dim3(kBlock), 0, s,
                        static_cast<R*>(p0), static_cast<R*>(p1 ? p1 : p0), dense_args<R, K>(L));
     return hipGetLastError();
 }
@@ -522,25 +628,47 @@ hipError_t dense_launch(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
 template <typename R, int K, int MODE, bool ROT>
 hipError_t dense_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
 {
-    const SweepTune t = sweep_tune(L.lowq);
-    if constexpr (K <= 3) {
-        if (t.unr == 2)
-            return t.nt ? dense_launch<R, K, MODE, ROT, 2, true>(L, p0, p1, s)
-                        : dense_launch<R, K, MODE, ROT, 2, false>(L, p0, p1, s);
-        if (t.unr == 4 && K == 1)
-            return t.nt ? dense_launch<R, K, MODE, ROT, 4, true>(L, p0, p1, s)
-                        : dense_launch<R, K, MODE, ROT, 4, false>(L, p0, p1, s);
-        return t.nt ? dense_launch<R, K, MODE, ROT, 1, true>(L, p0, p1, s)
-                    : dense_launch<R, K, MODE, ROT, 1, false>(L, p0, p1, s);
-    } else {
-        return dense_launch<R, K, MODE, ROT, 1, false>(L, p0, p1, s);
-    }
+    const int unit = (MODE == W1) ? (int)(2 * sizeof(R)) : 16;
+    return use_nt(L.ins, unit) ? dense_launch<R, K, MODE, ROT, true>(L, p0, p1, s)
+                               : dense_launch<R, K, MODE, ROT, false>(L, p0, p1, s);
+}
+
+// Uncontrolled single-qubit gate on unit bit < 6 with at least one block of
+// units: the lane-exchange kernel.  Returns false when it does not apply.
+template <typename R>
+bool lane_launch(const GateLaunch& L, void* p0, void* p1, hipStream_t s, hipError_t& err)
+{
+    if (L.K != 1 || L.ins.nins != 1 || L.ins.setmask != 0)
+        return false;
+    if (!(sizeof(R) == 4 ? L.mode == W2 : L.mode == W1))
+        return false;
+    const int tb = L.lowq - (L.mode == W2 ? 1 : 0);  // target as a unit bit
+    const uint64_t nunits = L.ngroups * 2;
+    if (tb < 0 || tb >= 6 || nunits < (uint64_t)kBlock || nunits % kBlock)
+        return false;
+    if (const char* e = getenv("QSV_NO_LANE_SWEEP"))
+        if (e[0] == '1')
+            return false;
+    dim3 grid(grid_for(nunits, 1), p1 ? 2 : 1);
+    R* q0 = static_cast<R*>(p0);
+    R* q1 = static_cast<R*>(p1 ? p1 : p0);
+    if (L.rot != ROT_NONE)
+        hipLaunchKernelGGL((k_dense_lane<R, true>), grid, dim3(kBlock), 0, s, q0, q1, dense_args<R, 1>(L),
+                           nunits, tb);
+    else
+        hipLaunchKernelGGL((k_dense_lane<R, false>), grid, dim3(kBlock), 0, s, q0, q1, dense_args<R, 1>(L),
+                           nunits, tb);
+    err = hipGetLastError();
+    return true;
 }
 
 template <typename R, int K>
 hipError_t dense_mode(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
 {
     if constexpr (K == 1) {
+        hipError_t e = hipSuccess;
+        if (lane_launch<R>(L, p0, p1, s, e))
+            return e;
         if (L.rot != ROT_NONE) {
             if constexpr (sizeof(R) == 4) {
                 if (L.mode == W2)
@@ -573,6 +701,15 @@ hipError_t dense_k(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
     }
 }
 
+template <typename R, int MODE, bool ROT, bool NT>
+hipError_t diag_launch(const DiagK<R>& a, const GateLaunch& L, void* p0, void* p1, hipStream_t s)
+{
+    dim3 grid(grid_for(L.ngroups, 1), p1 ? 2 : 1);
+    hipLaunchKernelGGL((k_diag<R, MODE, ROT, 1, NT>), grid, dim3(kBlock), 0, s, static_cast<R*>(p0),
+                       static_cast<R*>(p1 ? p1 : p0), a);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t diag_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
 {
@@ -588,32 +725,26 @@ hipError_t diag_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
     a.params = L.params;
     a.pidx = L.pidx;
     a.dag = L.dag;
-    constexpr int UNR = 2;
-    dim3 grid(grid_for(L.ngroups, UNR), p1 ? 2 : 1);
-    R* q0 = static_cast<R*>(p0);
-    R* q1 = static_cast<R*>(p1 ? p1 : p0);
+    const bool w2 = sizeof(R) == 4 && L.mode == W2;
+    const bool nt = use_nt(L.ins, w2 ? 16 : (int)(2 * sizeof(R)));
     const bool rot = L.rot != ROT_NONE;
-    if (sizeof(R) == 4 && L.mode == W2) {
-        if (rot)
-            hipLaunchKernelGGL((k_diag<R, W2, true, UNR>), grid, dim3(kBlock), 0, s, q0, q1, a);
-        else
-            hipLaunchKernelGGL((k_diag<R, W2, false, UNR>), grid, dim3(kBlock), 0, s, q0, q1, a);
-    } else {
-        if (rot)
-            hipLaunchKernelGGL((k_diag<R, W1, true, UNR>), grid, dim3(kBlock), 0, s, q0, q1, a);
-        else
-            hipLaunchKernelGGL((k_diag<R, W1, false, UNR>), grid, dim3(kBlock), 0, s, q0, q1, a);
-    }
-    return hipGetLastError();
+    if (w2)
+        return rot ? (nt ? diag_launch<R, W2, true, true>(a, L, p0, p1, s) : diag_launch<R, W2, true, false>(a, L, p0, p1, s))
+                   : (nt ? diag_launch<R, W2, false, true>(a, L, p0, p1, s) : diag_launch<R, W2, false, false>(a, L, p0, p1, s));
+    return rot ? (nt ? diag_launch<R, W1, true, true>(a, L, p0, p1, s) : diag_launch<R, W1, true, false>(a, L, p0, p1, s))
+               : (nt ? diag_launch<R, W1, false, true>(a, L, p0, p1, s) : diag_launch<R, W1, false, false>(a, L, p0, p1, s));
 }
 
 template <typename UT, int NM>
 hipError_t perm_go2(const GateLaunch& L, const PermK& a, void* p0, void* p1, hipStream_t s)
 {
-    constexpr int UNR = NM <= 4 ? 2 : 1;
-    dim3 grid(grid_for(L.ngroups, UNR), p1 ? 2 : 1);
-    hipLaunchKernelGGL((k_perm<UT, NM, UNR>), grid, dim3(kBlock), 0, s, static_cast<UT*>(p0),
-                       static_cast<UT*>(p1 ? p1 : p0), a);
+    dim3 grid(grid_for(L.ngroups, 1), p1 ? 2 : 1);
+    if (use_nt(L.ins, (int)sizeof(UT)))
+        hipLaunchKernelGGL((k_perm<UT, NM, 1, true>), grid, dim3(kBlock), 0, s, static_cast<UT*>(p0),
+                           static_cast<UT*>(p1 ? p1 : p0), a);
+    else
+        hipLaunchKernelGGL((k_perm<UT, NM, 1, false>), grid, dim3(kBlock), 0, s, static_cast<UT*>(p0),
+                           static_cast<UT*>(p1 ? p1 : p0), a);
     return hipGetLastError();
 }
 

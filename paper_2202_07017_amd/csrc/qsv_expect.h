@@ -16,10 +16,9 @@ struct XTerm {
     double c;
     uint32_t zloc;  // z restricted to the tile, compressed to local bits
     uint32_t xloc;  // x compressed to local bits (x lies inside the tile)
-    uint32_t hloc;  // highest bit of xloc (pair ownership)
-    int8_t kind;
-    int8_t dpart;
-    int16_t ylo;    // number of Y factors mod 4
+    int32_t kind;
+    int32_t dpart;
+    int32_t ylo;    // number of Y factors mod 4 (32-bit fields: scalar loads)
 };
 
 struct TileExpK {
@@ -27,14 +26,18 @@ struct TileExpK {
     InsertSpec ins;  // tile qubits, ascending (zeros inserted into the tile index)
     int L;           // contiguous low run of tile qubits
     int nt;          // terms [0, nstr): straddling diagonal; [nstr, pstart): table diagonal;
-    int nstr;        //       [pstart, nt): pair terms
+    int nstr;        //       [pstart, pxend): pure X strings; [pxend, nt): other pair terms
     int pstart;
+    int pxend;
     int ndiag;       // number of diagonal terms (0: no diagonal part in this pass)
     uint64_t choff[64];
     XTerm t[kMaxTileTerms];
 };
 
+// hpsi: lam (+)= the pass's part of H psi.  Otherwise the block partials of
+// <psi|H_pass|psi> go to partials[b] (real) and partials[nslots + b] (imaginary),
+// b < nslots, added to the slots' contents when accumulate is set.
 hipError_t launch_tile_pass(const TileExpK& a, const void* psi, void* lam, int dt, bool hpsi,
-                            double* partials, int nblocks, int accumulate, hipStream_t s);
+                            double* partials, int nslots, int accumulate, hipStream_t s);
 
 }  // namespace qsv

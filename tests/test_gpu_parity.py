@@ -71,6 +71,36 @@ def test_init_random(q, orc):
             assert rel <= (1e-14 if name == "c128" else 1e-7), rel
 
 
+@pytest.mark.parametrize("n", [8, 9, 11])
+def test_single_qubit_every_target(q, orc, n):
+    """Uncontrolled single-qubit gates on every target at sizes with at least
+    one block of 16-byte units (the lane-exchange sweep for low targets, the
+    strided sweeps above), fixed matrices and device-side rotation angles, on
+    one state and through the two-state path of a plan's rotations."""
+    import torch
+    rng = np.random.default_rng(40 + n)
+    for name in DTYPES:
+        psi = rand_state(n, rng, name)
+        for t in range(n):
+            G = W.haar_unitary(rng, 2)
+            say("1q every target", name, n, t)
+            gate_case(q, orc, psi, name, (t,), (), G)
+        # rotations with device parameters: one RX, RY, RZ per qubit
+        ops, npar = [], 0
+        for t in range(n):
+            for kind in ("rx", "ry", "rz"):
+                ops.append(W.Op(kind, (t,), (), param=npar))
+                npar += 1
+        circ = W.Circuit(n, ops, npar)
+        params = W.random_params(npar, 7)
+        ref = orc.run(circ, params, psi0=psi)
+        say("1q rotations every target", name, n)
+        plan = q.Plan(circ, 1 if name == "c64" else 2, 1)
+        d = to_gpu(psi, name)
+        plan.run(d, torch.from_numpy(params).cuda())
+        check_close(to_np(d), ref, name, "rotations")
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7])
 def test_dense_gates_all_placements(q, orc, n):
     """Every (sampled) ordered placement of k <= 3 targets and c <= 2 controls."""
