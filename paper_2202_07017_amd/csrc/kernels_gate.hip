@@ -308,6 +308,8 @@ __global__ void __launch_bounds__(kBlock) k_dense(R* __restrict__ psi0, R* __res
                                      x[u][cv].w);
                             }
                         }
+                        if constexpr (NU == 1)  // keeps -O3 from dropping the store's nontemporal hint
+                            asm volatile("" ::: "memory");
                         stv<NT>(&p[base[u] + a.off[rv]], make_float4(o[0].re, o[0].im, o[1].re, o[1].im));
                     }
                 }

@@ -12,15 +12,18 @@
 // returns rows 4 (lane / 16) + r, the f64 form rows lane / 16 + 4 r (column
 // lane % 16, register r), as measured on gfx950.
 //
-// A workgroup handles tiles of 2^(k+6) amplitudes: all targets plus the six
-// lowest non-target qubits (64 groups).  Because those six bits and every
+// A workgroup handles one tile of 2^(k+6) amplitudes: all targets plus the
+// six lowest non-target qubits (64 groups).  Because those six bits and every
 // target below them form a contiguous run of low bits, a tile is a few
-// contiguous chunks of >= 64 amplitudes, loaded with 16-byte accesses.  The
-// tile is transposed through LDS into [tau'][group] rows (padded by one
-// amplitude against bank conflicts), each of the 4 wavefronts multiplies 16
-// groups, writes its results back in place and the tile is stored.  The grid
-// is persistent over tiles and the next tile's loads are issued before the
-// current tile's matrix products.
+// contiguous chunks of >= 64 amplitudes, loaded with 16-byte nontemporal
+// accesses.  The tile is transposed through LDS into [tau'][group] rows
+// (padded by one amplitude against bank conflicts).  Work is split by output
+// rows: wavefront w computes the real rows of 16-row block(s) w mod RB for
+// its share of the 64 group columns, so it keeps only its own A fragments in
+// registers (16 per lane for k = 5).  Results go back to LDS and the tile is
+// stored in place.  One tile per workgroup, blocks in XCD-contiguous order:
+// on MI355X this streams faster than persistent tile loops (measured), and
+// the small register footprint keeps several workgroups per CU.
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -28,6 +31,7 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 template <int K>
 struct MfmaK {
@@ -53,7 +57,7 @@ struct MfmaT;
 template <>
 struct MfmaT<float> {
     using Acc = v4f;
-    using Vec = float4;                 // 16-byte global vector
+    using NV = v4f;                     // 16-byte global vector (two amplitudes)
     static constexpr int APV = 2;       // amplitudes per vector
     __device__ static Acc mfma(float a, float b, Acc c)
     {
@@ -65,7 +69,7 @@ struct MfmaT<float> {
 template <>
 struct MfmaT<double> {
     using Acc = v4d;
-    using Vec = double2;
+    using NV = v2d;                     // one amplitude
     static constexpr int APV = 1;
     __device__ static Acc mfma(double a, double b, Acc c)
     {
@@ -77,42 +81,77 @@ struct MfmaT<double> {
 
 constexpr int kRow = 65;  // LDS row length in amplitudes (64 groups + 1 pad)
 
+// Complex amplitude as one LDS access (8 bytes for float, 16 for double).
+template <typename R>
+struct Pair2;
+template <>
+struct Pair2<float> {
+    using T = float2;
+};
+template <>
+struct Pair2<double> {
+    using T = double2;
+};
+
+// Block index in XCD-contiguous order (a bijection on [0, gridDim.x)).
+__device__ __forceinline__ uint64_t xcd_block()
+{
+    const uint32_t G = gridDim.x, b = blockIdx.x, per = G >> 3;
+    return b < (per << 3) ? (uint64_t)(b & 7u) * per + (b >> 3) : (uint64_t)b;
+}
+
 template <typename R, int K>
 __global__ void __launch_bounds__(256) k_mfma(R* __restrict__ psi0, R* __restrict__ psi1,
                                               const MfmaK<K> a, const R* __restrict__ frag)
 {
     using T = MfmaT<R>;
-    using Vec = typename T::Vec;
+    using NV = typename T::NV;
+    using P2 = typename Pair2<R>::T;
     constexpr int D = 1 << K;           // amplitudes per group
     constexpr int TA = D * 64;          // amplitudes per tile
     constexpr int APV = T::APV;
     constexpr int VPT = TA / APV / 256; // vectors per thread
     constexpr int KS = (2 * D) / 4;     // k-steps of 4 real rows
-    constexpr int RB = (2 * D) / 16;    // 16-row output blocks
+    constexpr int RB = (2 * D) / 16;    // 16-row output blocks (4 for k = 5, 2 for k = 4)
+    // Wave w takes row block w % RB and CBW = RB of the 4 16-column blocks,
+    // starting at (w / RB) * RB: for k = 5 every wave covers all 64 groups of
+    // its row block; for k = 4 waves 0, 1 take groups 0..31, waves 2, 3 the rest.
+    constexpr int CBW = RB;
+    static_assert(RB == 2 || RB == 4, "tile split");
 
-    __shared__ R lds[D * kRow * 2];
+    __shared__ __align__(16) R lds[D * kRow * 2];
 
     R* psi = blockIdx.y ? psi1 : psi0;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int grp = wave * 16 + (lane & 15);
+    const int rb = wave % RB;
+    const int cb0 = (wave / RB) * CBW;
 
-    // A operand: R(G) fragments, lane-major, kept in registers.
-    R afr[RB][KS];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk)
-            afr[rb][kk] = frag[(rb * KS + kk) * 64 + lane];
+    const uint64_t tile = xcd_block();
+    if (tile >= a.ntiles)
+        return;
+    const uint64_t base = insert_bits(tile, a.ins);
 
-    // Per-thread tile geometry (same for every tile).
+    // Tile loads first (their latency covers the set-up below).
     uint64_t goff[VPT];
-    int pos[VPT][APV];
+    NV in[VPT];
 #pragma unroll
     for (int r = 0; r < VPT; ++r) {
         const int loc = (tid + 256 * r) * APV;
         goff[r] = a.choff[loc >> a.L] + (uint64_t)(loc & ((1 << a.L) - 1));
+        in[r] = __builtin_nontemporal_load(reinterpret_cast<const NV*>(psi + 2 * (base + goff[r])));
+    }
+    // A operand: this wave's row block of R(G), KS values per lane,
+    // contiguous in the fragment table ([rb][lane][kk]).
+    R afr[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+        afr[kk] = frag[((size_t)rb * 64 + lane) * KS + kk];
+    int pos[VPT][APV];
+#pragma unroll
+    for (int r = 0; r < VPT; ++r) {
+        const int loc = (tid + 256 * r) * APV;
 #pragma unroll
         for (int h = 0; h < APV; ++h) {
             const int l = loc + h;
@@ -126,77 +165,73 @@ __global__ void __launch_bounds__(256) k_mfma(R* __restrict__ psi0, R* __restric
             pos[r][h] = (tau * kRow + j) * 2;
         }
     }
+    // registers -> LDS [tau'][group]
+#pragma unroll
+    for (int r = 0; r < VPT; ++r)
+#pragma unroll
+        for (int h = 0; h < APV; ++h)
+            *reinterpret_cast<P2*>(&lds[pos[r][h]]) = P2{in[r][2 * h], in[r][2 * h + 1]};
+    __syncthreads();
 
-    uint64_t tile = blockIdx.x;
-    if (tile >= a.ntiles)
-        return;
-    Vec in[VPT];
-    {
-        const uint64_t base = insert_bits(tile, a.ins);
+    // B operand: lane holds real row 4kk + lane/16 of group (cb0 + c) * 16 +
+    // lane % 16.  k-steps outermost: the CBW accumulators are independent
+    // chains that the matrix core overlaps.
+    typename T::Acc acc[CBW];
 #pragma unroll
-        for (int r = 0; r < VPT; ++r)
-            in[r] = *reinterpret_cast<const Vec*>(psi + 2 * (base + goff[r]));
+    for (int c = 0; c < CBW; ++c)
+        acc[c] = typename T::Acc{0, 0, 0, 0};
+    const int bofs = ((lane >> 5) * kRow + cb0 * 16 + (lane & 15)) * 2 + ((lane >> 4) & 1);
+    // B reads in groups of KG k-steps, one group ahead of its products
+    // (the scheduling barriers keep the reads of group g + 1 issued before
+    // the products of group g).
+    constexpr int KG = 4;
+    R bfr[KS][CBW];
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+        for (int c = 0; c < CBW; ++c)
+            bfr[kk][c] = lds[bofs + (2 * kk * kRow + 16 * c) * 2];
+#pragma unroll
+    for (int g = 0; g < KS / KG; ++g) {
+        if (g + 1 < KS / KG) {
+#pragma unroll
+            for (int kk = (g + 1) * KG; kk < (g + 2) * KG; ++kk)
+#pragma unroll
+                for (int c = 0; c < CBW; ++c)
+                    bfr[kk][c] = lds[bofs + (2 * kk * kRow + 16 * c) * 2];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int kk = g * KG; kk < (g + 1) * KG; ++kk)
+#pragma unroll
+            for (int c = 0; c < CBW; ++c)
+                acc[c] = T::mfma(afr[kk], bfr[kk][c], acc[c]);
+        __builtin_amdgcn_sched_barrier(0);
     }
-    for (; tile < a.ntiles; tile += gridDim.x) {
-        const uint64_t base = insert_bits(tile, a.ins);
-        // registers -> LDS [tau'][group]
+    __syncthreads();  // every wave has read its B operands (all rows)
+    // D: register r of each lane holds real row 16 rb + T::row(lane, r) of
+    // group (cb0 + c) * 16 + lane % 16; real row 2 tau + c' is component c'
+    // of amplitude tau.
 #pragma unroll
-        for (int r = 0; r < VPT; ++r) {
-            const R* v = reinterpret_cast<const R*>(&in[r]);
+    for (int c = 0; c < CBW; ++c) {
+        const int grp = (cb0 + c) * 16 + (lane & 15);
 #pragma unroll
-            for (int h = 0; h < APV; ++h) {
-                lds[pos[r][h]] = v[2 * h];
-                lds[pos[r][h] + 1] = v[2 * h + 1];
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int rr = 16 * rb + T::row(lane, r);
+            lds[((rr >> 1) * kRow + grp) * 2 + (rr & 1)] = acc[c][r];
         }
-        __syncthreads();
-        const uint64_t next = tile + gridDim.x;
-        if (next < a.ntiles) {
-            const uint64_t nb = insert_bits(next, a.ins);
+    }
+    __syncthreads();
 #pragma unroll
-            for (int r = 0; r < VPT; ++r)
-                in[r] = *reinterpret_cast<const Vec*>(psi + 2 * (nb + goff[r]));
+    for (int r = 0; r < VPT; ++r) {
+        NV o;
+#pragma unroll
+        for (int h = 0; h < APV; ++h) {
+            const P2 w = *reinterpret_cast<const P2*>(&lds[pos[r][h]]);
+            o[2 * h] = w.x;
+            o[2 * h + 1] = w.y;
         }
-        // B operand: lane holds real row 4kk + lane/16 of group `grp`.
-        R bfr[KS];
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk) {
-            const int tp = 2 * kk + (lane >> 5);
-            bfr[kk] = lds[(tp * kRow + grp) * 2 + ((lane >> 4) & 1)];
-        }
-        typename T::Acc acc[RB];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-            acc[rb] = typename T::Acc{0, 0, 0, 0};
-        // k-steps outermost: the RB accumulators are independent chains that
-        // the matrix core can overlap.
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk)
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-                acc[rb] = T::mfma(afr[rb][kk], bfr[kk], acc[rb]);
-        // D: register r of each lane holds real row 16 rb + T::row(lane, r) of
-        // group `grp`; real row 2 tau + c is component c of amplitude tau.
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int rr = 16 * rb + T::row(lane, r);
-                lds[((rr >> 1) * kRow + grp) * 2 + (rr & 1)] = acc[rb][r];
-            }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < VPT; ++r) {
-            Vec o;
-            R* v = reinterpret_cast<R*>(&o);
-#pragma unroll
-            for (int h = 0; h < APV; ++h) {
-                v[2 * h] = lds[pos[r][h]];
-                v[2 * h + 1] = lds[pos[r][h] + 1];
-            }
-            *reinterpret_cast<Vec*>(psi + 2 * (base + goff[r])) = o;
-        }
-        __syncthreads();
+        __builtin_nontemporal_store(o, reinterpret_cast<NV*>(psi + 2 * (base + goff[r])));
     }
 }
 
@@ -213,8 +248,9 @@ hipError_t mfma_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
         a.tloc[j] = L.tloc[j];
     for (int j = 0; j < 6; ++j)
         a.floc[j] = L.floc[j];
-    uint64_t blocks = L.ntiles < 2048 ? L.ntiles : 2048;
-    dim3 grid((unsigned)blocks, p1 ? 2 : 1);
+    if (L.ntiles > (1ull << 31))
+        return hipErrorInvalidValue;
+    dim3 grid((unsigned)L.ntiles, p1 ? 2 : 1);
     hipLaunchKernelGGL((k_mfma<R, K>), grid, dim3(256), 0, s, static_cast<R*>(p0),
                        static_cast<R*>(p1 ? p1 : p0), a, static_cast<const R*>(L.gdev));
     return hipGetLastError();
@@ -244,7 +280,7 @@ void mfma_fragments(const double* Gc, int K, int dt, std::vector<unsigned char>&
                 const double gre = Gc[((size_t)tau * D + tp) * 2];
                 const double gim = Gc[((size_t)tau * D + tp) * 2 + 1];
                 const double v = (ra == cb) ? gre : (ra == 0 ? -gim : gim);
-                const size_t idx = ((size_t)rb * KS + kk) * 64 + lane;
+                const size_t idx = ((size_t)rb * 64 + lane) * KS + kk;
                 if (dt == C64)
                     reinterpret_cast<float*>(out.data())[idx] = (float)v;
                 else
