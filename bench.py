@@ -143,7 +143,7 @@ def main():
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only the dominant kernel and a copy of known size (counter runs)")
     ap.add_argument("--legs", default="",
-                    help="comma list of side legs to run alone (adjoint, batched): profiling runs")
+                    help="comma list of side legs to run alone (adjoint, adjoint26, batched): profiling runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X and this build has no "
@@ -161,9 +161,12 @@ def main():
         from paper_2202_07017_amd import qsv
         dev = torch.device("cuda:0")
         out = {}
-        if "adjoint" in args.legs:
+        legs = set(args.legs.split(","))
+        if "adjoint" in legs:
             out["adjoint"] = adjoint_leg(qsv, W, torch, np, dev)
-        if "batched" in args.legs:
+        if "adjoint26" in legs:
+            out["adjoint_n26"] = adjoint_leg_large(qsv, W, torch, np, dev)
+        if "batched" in legs:
             out["batched"] = batched_leg(qsv, W, torch, np, dev)
         print(json.dumps(out), flush=True)
         return
@@ -246,6 +249,7 @@ def main():
         del psi
         torch.cuda.empty_cache()
         out["adjoint"] = adjoint_leg(qsv, W, torch, np, dev)
+        out["adjoint_n26"] = adjoint_leg_large(qsv, W, torch, np, dev)
         out["batched"] = batched_leg(qsv, W, torch, np, dev)
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
@@ -314,6 +318,65 @@ def adjoint_leg(qsv, W, torch, np, dev):
             res["param_shift_grads_per_s"] = round(1.0 / tps, 3)
             res["adjoint_over_param_shift"] = round(tps / ta, 1)
             res["max_abs_adjoint_minus_shift"] = float((gps - g).abs().max().cpu())
+    return res
+
+
+def adjoint_leg_large(qsv, W, torch, np, dev, n=26, L=8, nsub=8):
+    """HEA at n = 26, L = 8 (416 parameters): full adjoint gradients/s in
+    complex64 and complex128; plain parameter shift timed on a seeded subset
+    of nsub parameters (2 nsub energies) and extrapolated to all of them;
+    complex128 central finite differences (h = 1e-6) on the same subset as
+    the accuracy check."""
+    circ, H = W.hea(n, L), W.tfim_chain(n)
+    P = circ.nparams
+    p = torch.from_numpy(W.random_params(P, 1003)).to(dev)
+    sub = np.sort(np.random.default_rng(26).choice(P, size=nsub, replace=False))
+    res = {"workload": "HEA n=%d L=%d, TFIM" % (n, L), "nparams": P, "subset": [int(j) for j in sub]}
+    for name, code in [("c64", qsv.C64), ("c128", qsv.C128)]:
+        plan = qsv.AdjointPlan(circ, H, code, 5, device=dev)
+        e, g = plan.run(p)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.run(p, e, g)
+        torch.cuda.synchronize()
+        ta = (time.perf_counter() - t0) / reps
+        res[name + "_grads_per_s"] = round(1.0 / ta, 3)
+        res[name + "_ms_per_gradient"] = round(ta * 1e3, 2)
+        pe = p.clone()
+        en = torch.empty(1, dtype=torch.float64, device=dev)
+        plan.energy(pe, en)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        shift = []
+        for j in sub:
+            vals = []
+            for sign in (1.0, -1.0):
+                pe.copy_(p)
+                pe[int(j)] += sign * np.pi / 2
+                plan.energy(pe, en)
+                vals.append(float(en.cpu()[0]))
+            shift.append(0.5 * (vals[0] - vals[1]))
+        tsub = time.perf_counter() - t0
+        gsub = g.cpu().numpy()[sub]
+        res[name + "_param_shift_grads_per_s_extrapolated"] = round(nsub / (tsub * P), 4)
+        res[name + "_adjoint_over_param_shift"] = round(tsub * P / nsub / ta, 1)
+        res[name + "_max_abs_adjoint_minus_shift"] = float(np.max(np.abs(np.array(shift) - gsub)))
+        if name == "c128":
+            h = 1e-6
+            fd = []
+            for j in sub:
+                vals = []
+                for sign in (1.0, -1.0):
+                    pe.copy_(p)
+                    pe[int(j)] += sign * h
+                    plan.energy(pe, en)
+                    vals.append(float(en.cpu()[0]))
+                fd.append((vals[0] - vals[1]) / (2 * h))
+            res["c128_max_abs_adjoint_minus_fd"] = float(np.max(np.abs(np.array(fd) - gsub)))
+        del plan
+        torch.cuda.empty_cache()
     return res
 
 
