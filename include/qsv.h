@@ -217,7 +217,8 @@ qsv_status qsv_plan_create(const qsv_circuit* circ, qsv_dtype dt, int fuse_k,
  * read only by unbound rotations (may be NULL if there are none).  The first
  * run for a given (psi, params_dev, stream) records the launches into a HIP
  * graph that later runs replay (disable with the environment variable
- * QSV_NO_GRAPH=1). */
+ * QSV_NO_GRAPH=1).  A plan without launches (empty or all-identity circuit)
+ * enqueues nothing. */
 qsv_status qsv_plan_run(qsv_plan* plan, void* psi, const double* params_dev, void* stream);
 
 /* Launch count, algorithmic HBM bytes (each touched amplitude read and

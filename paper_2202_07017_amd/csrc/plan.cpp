@@ -425,6 +425,8 @@ qsv_status qsv_plan_run(qsv_plan* plan, void* psi, const double* params_dev, voi
         return st;
     if (has_rotation(plan->launches) && !params_dev)
         return fail(QSV_ERR_ARG, "plan has unbound rotations but params_dev is NULL");
+    if (plan->launches.empty())
+        return ok();  // nothing to enqueue (empty or all-identity circuit)
     hipStream_t s = (hipStream_t)stream;
     std::vector<const void*> key = {psi, params_dev};
     if ((st = run_graph(plan->graph, key, s, [&](hipStream_t cs) {

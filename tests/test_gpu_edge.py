@@ -1,0 +1,143 @@
+"""Degenerate and boundary cases of the GPU path, through the C ABI, against
+the CPU oracle: gates that span every qubit (k + c = n), identity gates (a
+no-op that must leave the state bit-exact), non-unitary matrices on the VALU
+and MFMA paths, MFMA launches of exactly one tile, empty plans, and Pauli
+sums with identity and duplicated terms at one and two tiles."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import TOL, rand_state, raw_bits, say, to_gpu, to_np, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = ["c64", "c128"]
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2202_07017_amd import qsv
+    qsv.lib()
+    return qsv
+
+
+def close(got, ref, name, what):
+    err = np.max(np.abs(got - ref)) if got.size else 0.0
+    assert err <= TOL[name], "%s %s: max|d| = %.3e" % (what, name, err)
+
+
+def random_matrix(rng, d):
+    return (rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))) / np.sqrt(2 * d)
+
+
+def test_gates_spanning_every_qubit(q, orc):
+    """k + c = n: the whole state is one group (or one controlled group)."""
+    rng = np.random.default_rng(71)
+    cases = [(1, (0,), ()), (2, (1, 0), ()), (3, (2, 0, 1), ()), (4, (3,), (0, 1, 2)),
+             (4, (0, 2), (3, 1)), (5, (4, 2, 0, 1, 3), ()), (5, (1, 3, 0, 4), (2,)),
+             (6, (5, 0), (1, 2, 3, 4))]
+    for name in DTYPES:
+        for n, t, c in cases:
+            psi = rand_state(n, rng, name)
+            G = W.haar_unitary(rng, 2 ** len(t))
+            say("span", name, n, t, c)
+            d = to_gpu(psi, name)
+            q.qsv_apply_gate(d, t, c, G)
+            close(to_np(d), orc.apply(psi, t, c, G), name, "span %s %s" % (t, c))
+
+
+def test_identity_gates_are_bitexact_noops(q):
+    rng = np.random.default_rng(72)
+    for name in DTYPES:
+        for n, t, c in [(1, (0,), ()), (7, (2, 5), ()), (7, (0,), (6,)), (12, (1, 4, 7, 9), ()),
+                        (12, (0, 3, 5, 8, 11), ())]:
+            psi = rand_state(n, rng, name)
+            d = to_gpu(psi, name)
+            before = raw_bits(d.cpu().numpy()).copy()
+            say("identity", name, n, t, c)
+            q.qsv_apply_gate(d, t, c, np.eye(2 ** len(t), dtype=np.complex128))
+            assert np.array_equal(raw_bits(d.cpu().numpy()), before)
+
+
+def test_non_unitary_matrices(q, orc):
+    """eq. (1) is linear for any G: random complex and singular matrices on
+    every kernel family (dense k <= 3, VALU k = 4, 5 and the matrix cores)."""
+    import os
+    rng = np.random.default_rng(73)
+    proj = np.zeros((2, 2), np.complex128)
+    proj[0, 0] = 1.0
+    for name in DTYPES:
+        n = 11
+        psi = rand_state(n, rng, name)
+        cases = [((3,), (), proj), ((0,), (), random_matrix(rng, 2)), ((9,), (2,), random_matrix(rng, 2)),
+                 ((1, 8), (), random_matrix(rng, 4)), ((0, 5, 10), (), random_matrix(rng, 8)),
+                 ((0, 1, 2, 3), (), random_matrix(rng, 16)), ((10, 2, 6, 4, 0), (), random_matrix(rng, 32))]
+        for t, c, G in cases:
+            for mfma in ["1", "0"]:
+                os.environ["QSV_NO_MFMA"] = "0" if mfma == "1" else "1"
+                say("non-unitary", name, t, c, mfma)
+                d = to_gpu(psi, name)
+                q.qsv_apply_gate(d, t, c, G)
+                ref = orc.apply(psi, t, c, G)
+                close(to_np(d), ref, name, "non-unitary %s" % (t,))
+    os.environ.pop("QSV_NO_MFMA", None)
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_mfma_single_tile(q, orc, k):
+    """n = k + 6: the matrix-core launch has exactly one tile; n = k + 7: two."""
+    rng = np.random.default_rng(74 + k)
+    for name in DTYPES:
+        for n in [k + 6, k + 7]:
+            psi = rand_state(n, rng, name)
+            for t in [tuple(range(k)), tuple(range(n - k, n)), tuple(int(v) for v in rng.choice(n, k, replace=False))]:
+                G = W.haar_unitary(rng, 2 ** k)
+                say("mfma tiles", name, n, t)
+                d = to_gpu(psi, name)
+                q.qsv_apply_gate(d, t, (), G)
+                close(to_np(d), orc.apply(psi, t, (), G), name, "mfma n=%d %s" % (n, t))
+
+
+def test_empty_and_noop_plans(q):
+    import torch
+    rng = np.random.default_rng(75)
+    for name in DTYPES:
+        dc = 1 if name == "c64" else 2
+        n = 9
+        psi = rand_state(n, rng, name)
+        for circ in [W.Circuit(n, []),
+                     W.Circuit(n, [W.Op("matrix", (3,), matrix=np.eye(2, dtype=np.complex128)),
+                                   W.Op("matrix", (1, 7), matrix=np.eye(4, dtype=np.complex128))])]:
+            for fuse in [1, 5]:
+                say("empty plan", name, len(circ.ops), fuse)
+                plan = q.Plan(circ, dc, fuse)
+                d = to_gpu(psi, name)
+                before = raw_bits(d.cpu().numpy()).copy()
+                plan.run(d)
+                torch.cuda.synchronize()
+                assert np.array_equal(raw_bits(d.cpu().numpy()), before)
+
+
+@pytest.mark.parametrize("n", [12, 13])
+def test_pauli_identity_and_duplicate_terms(q, orc, n):
+    """An identity term contributes c ||psi||^2, duplicated strings add, Y
+    strings carry their phases; n = 12 is exactly one tile, n = 13 two."""
+    rng = np.random.default_rng(76 + n)
+    x = np.array([0, 0b101, 0b101, (1 << (n - 1)) | 1, 0b110, 0, 1 << 7], np.uint64)
+    z = np.array([0, 0, 0, 1 << (n - 1), 0b110, 0b11, 1 << 3], np.uint64)
+    c = np.array([0.7, -0.4, 0.25, 1.1, -0.6, 0.9, 0.3])
+    H = W.PauliSum(n, x, z, c)
+    scale = np.sum(np.abs(c))
+    for name in DTYPES:
+        psi = rand_state(n, rng, name)
+        say("pauli edge", name, n)
+        d = to_gpu(psi, name)
+        e = q.qsv_expectation(d, H).cpu().numpy()
+        ref = orc.expect(psi, H)
+        assert abs(e[0] - ref.real) <= 1e-10 * scale, (e, ref)
+        assert abs(e[1]) <= 1e-10 * scale
+        out = to_gpu(np.zeros_like(psi), name)
+        q.qsv_apply_pauli_sum(d, out, H)
+        close(to_np(out) / scale, orc.apply_hamiltonian(psi, H) / scale, name, "H psi")

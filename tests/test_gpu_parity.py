@@ -373,6 +373,42 @@ def test_adjoint_autograd(q, orc):
     assert np.max(np.abs(theta.grad.cpu().numpy() - 2.0 * g_ref)) < 1e-10
 
 
+def test_adjoint_large_vs_finite_differences(q):
+    """HEA n = 22, L = 8 (352 parameters, TFIM): the complex128 adjoint
+    gradient against complex128 central finite differences (h = 1e-6) on a
+    seeded sample of parameters, within 1e-6; the complex64 adjoint (complex64
+    sweeps, FP64 accumulation) against the complex128 one within 1e-4 of the
+    largest gradient entry."""
+    import torch
+    n, L = 22, 8
+    circ, H = W.hea(n, L), W.tfim_chain(n)
+    p = torch.from_numpy(W.random_params(circ.nparams, 22)).cuda()
+    sub = np.sort(np.random.default_rng(22).choice(circ.nparams, size=6, replace=False))
+    say("adjoint n22 c128")
+    plan = q.AdjointPlan(circ, H, 2, 5)
+    e, g = plan.run(p)
+    g = g.cpu().numpy().copy()
+    pe = p.clone()
+    en = torch.empty(1, dtype=torch.float64, device="cuda")
+    h = 1e-6
+    for j in sub:
+        vals = []
+        for sign in (1.0, -1.0):
+            pe.copy_(p)
+            pe[int(j)] += sign * h
+            plan.energy(pe, en)
+            vals.append(float(en.cpu()[0]))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-6, (int(j), fd, g[j])
+    del plan
+    say("adjoint n22 c64")
+    plan64 = q.AdjointPlan(circ, H, 1, 5)
+    e64, g64 = plan64.run(p)
+    g64 = g64.cpu().numpy()
+    assert np.max(np.abs(g64 - g)) <= 1e-4 * np.max(np.abs(g)), np.max(np.abs(g64 - g))
+    assert abs(float(e64.cpu()[0]) - float(e.cpu()[0])) <= 1e-4 * n
+
+
 def test_full_size_sampled(q, orc):
     """n = 30 (8 GiB complex64, 16 GiB complex128): each gate applied to the
     seeded random state, 96 output amplitudes compared with the oracle
