@@ -3,8 +3,9 @@
 //
 // Every block stages the pass (matrices, steps) in LDS once, then takes tiles
 // tile = blockIdx.x, + gridDim.x, ...: loads the tile (psi; reverse passes
-// also lambda) into LDS in contiguous chunks of 16-byte vectors, runs the
-// pass's steps on it (tile_exec.h) and stores it back.  Reverse passes end by
+// also lambda) into LDS in contiguous chunks of 16-byte vectors (all of a
+// thread's vectors in flight together, the next tile's while this one is
+// processed), runs the pass's steps on it (tile_exec.h) and stores it back.  Reverse passes end by
 // writing the block's per-rotation FP64 sums to
 // partials[(slot_base + slot) * nb + block], which a finalize kernel adds in
 // block order.
@@ -17,25 +18,42 @@ namespace {
 using tx::ExecShared;
 using tx::LOp;
 
+typedef float tv4f __attribute__((ext_vector_type(4)));
+typedef double tv2d __attribute__((ext_vector_type(2)));
+
 template <typename R>
 struct TV;
 template <>
 struct TV<float> {
-    using V = float4;
+    using V = tv4f;  // two amplitudes
     static constexpr int APV = 2;
 };
 template <>
 struct TV<double> {
-    using V = double2;
+    using V = tv2d;  // one amplitude
     static constexpr int APV = 1;
 };
 
+// 16-byte vectors per thread per state: a tile has at most 2^12 complex64 or
+// 2^11 complex128 amplitudes, i.e. 2048 vectors over kTpassThreads threads.
+constexpr int kVPT = 2048 / kTpassThreads;
+
+// Waves per SIMD to keep two blocks resident (both tiles of a complex64
+// reverse pass fit twice in LDS); 1 = no constraint.
 template <typename R, bool REV>
-__global__ void __launch_bounds__(kTpassThreads) k_tpass(R* __restrict__ psi, R* __restrict__ lam,
+constexpr int tpass_wpe()
+{
+    return (sizeof(R) == 4 && REV) ? 4 : 1;
+}
+
+template <typename R, bool REV>
+__global__ void __launch_bounds__(kTpassThreads) __attribute__((amdgpu_waves_per_eu(tpass_wpe<R, REV>())))
+k_tpass(R* __restrict__ psi, R* __restrict__ lam,
                                                          const TPassArgs a)
 {
     using V = typename TV<R>::V;
     constexpr int APV = TV<R>::APV;
+    constexpr int NS = REV ? 2 : 1;  // states moved per tile
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ ExecShared sh;
     const int m = a.m;
@@ -47,31 +65,76 @@ __global__ void __launch_bounds__(kTpassThreads) k_tpass(R* __restrict__ psi, R*
                                             sizeof(LOp<R>) * kMaxPassOps);
     const DPass P = a.pass;
     tx::stage<R>(P, a.steps, a.ops, a.mats, a.params, REV, ops, steps, sh);
-    __syncthreads();
     const uint32_t nvec = (1u << m) / APV;
     const uint64_t ntiles = 1ull << (a.n - m);
-    V* pg = reinterpret_cast<V*>(psi);
-    V* lg = reinterpret_cast<V*>(lam);
-    V* pl = reinterpret_cast<V*>(phiL);
-    V* ll = reinterpret_cast<V*>(lamL);
-    int parity = 0;
-    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    V* const gs[2] = {reinterpret_cast<V*>(psi), reinterpret_cast<V*>(lam)};
+    V* const ls[2] = {reinterpret_cast<V*>(phiL), reinterpret_cast<V*>(lamL)};
+    // Vector v = threadIdx.x + kTpassThreads * r holds local amplitudes v * APV
+    // (+ 1); its global index is base | deposit(v * APV).  The tile bits are
+    // disjoint, so the deposit splits into a lane part and a uniform part.
+    const uint64_t glane = tx::deposit_mask((uint64_t)threadIdx.x * APV, P.bmask);
+    uint64_t greg[kVPT];
+#pragma unroll
+    for (int r = 0; r < kVPT; ++r)
+        greg[r] = tx::deposit_mask((uint64_t)kTpassThreads * APV * r, P.bmask);
+    V x[NS][kVPT];
+    // (opaque copies of the lane offset keep the compiler from holding every
+    // vector's global address in registers across the steps)
+    auto load = [&](uint64_t t) {
         const uint64_t base = tx::insert_mask(t, P.bmask);
-        for (uint32_t v = threadIdx.x; v < nvec; v += blockDim.x) {
-            const uint64_t gi = (base | tx::deposit_mask((uint64_t)v * APV, P.bmask)) / APV;
-            pl[v] = pg[gi];
-            if (REV)
-                ll[v] = lg[gi];
+        uint64_t gl = glane;
+        asm volatile("" : "+v"(gl));
+#pragma unroll
+        for (int r = 0; r < kVPT; ++r)
+            if (threadIdx.x + kTpassThreads * r < nvec)
+#pragma unroll
+                for (int sidx = 0; sidx < NS; ++sidx)
+                    x[sidx][r] = __builtin_nontemporal_load(gs[sidx] + (base | gl | greg[r]) / APV);
+    };
+    auto to_lds = [&]() {
+#pragma unroll
+        for (int r = 0; r < kVPT; ++r)
+            if (threadIdx.x + kTpassThreads * r < nvec)
+#pragma unroll
+                for (int sidx = 0; sidx < NS; ++sidx)
+                    ls[sidx][threadIdx.x + kTpassThreads * r] = x[sidx][r];
+    };
+    int parity = 0;
+    uint64_t t = blockIdx.x;
+    // Forward passes prefetch: the next tile's loads are issued before this
+    // tile's steps, and its LDS copy is written at the end of the iteration,
+    // after this tile's stores (vector memory counters retire in order, so
+    // the wait for the loads then need not cover the stores); past the last
+    // tile a block reloads its own tile, a copy that is never used.  Reverse
+    // passes (two states: the prefetch registers would halve the resident
+    // blocks) load each tile at the top of its iteration.
+    constexpr bool PF = !REV;
+    if (PF && t < ntiles) {
+        load(t);
+        to_lds();
+    }
+    for (; t < ntiles; t += gridDim.x) {
+        const uint64_t base = tx::insert_mask(t, P.bmask);
+        if (!PF) {
+            load(t);
+            to_lds();
         }
         __syncthreads();
+        if (PF)
+            load(t + gridDim.x < ntiles ? t + gridDim.x : t);
         tx::exec_tile<R, REV, 8>(ops, steps, P.nsteps, m, phiL, lamL, sh, parity);
-        for (uint32_t v = threadIdx.x; v < nvec; v += blockDim.x) {
-            const uint64_t gi = (base | tx::deposit_mask((uint64_t)v * APV, P.bmask)) / APV;
-            pg[gi] = pl[v];
-            if (REV)
-                lg[gi] = ll[v];
-        }
+        uint64_t gl = glane;
+        asm volatile("" : "+v"(gl));
+#pragma unroll
+        for (int r = 0; r < kVPT; ++r)
+            if (threadIdx.x + kTpassThreads * r < nvec)
+#pragma unroll
+                for (int sidx = 0; sidx < NS; ++sidx)
+                    __builtin_nontemporal_store(ls[sidx][threadIdx.x + kTpassThreads * r],
+                                                gs[sidx] + (base | gl | greg[r]) / APV);
         __syncthreads();
+        if (PF)
+            to_lds();
     }
     if (REV)
         for (int j = threadIdx.x; j < P.nrot; j += blockDim.x)
