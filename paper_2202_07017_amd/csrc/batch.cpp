@@ -1,6 +1,7 @@
 // Host side of the batched mode: validation, the cache-blocking pass
 // scheduler, device tables, graph replay and the autotuner.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <fstream>
 #include <map>
@@ -36,15 +37,26 @@ struct qsv_batch_plan {
     std::vector<int> order;
     long long work_bytes = 0;
     std::vector<long long> work_off;
-    // large instances (n >= split) run one at a time across the whole GPU
+    // large instances (n >= split) run as single-instance adjoint plans, on
+    // kLargeStreams side streams at once (each stream with its own workspace
+    // region of big_bytes, starting at big_off)
     std::vector<qsv_adjoint_plan*> sub;  // per instance with n >= kSplitMin, else nullptr
-    long long big_off = 0;               // shared workspace region of the large tier
+    long long big_off = 0;
+    long long big_bytes = 0;
     int split = 99;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;  // fork, then one join per side stream
     ~qsv_batch_plan()
     {
         for (qsv_adjoint_plan* p : sub)
             if (p)
                 qsv_adjoint_plan_destroy(p);
+        for (hipEvent_t e : ev)
+            if (e)
+                hipEventDestroy(e);
+        for (hipStream_t q : side)
+            if (q)
+                hipStreamDestroy(q);
     }
     // configuration
     int m = 0, threads = 0, blocks = 0;
@@ -60,6 +72,10 @@ namespace {
 
 constexpr int kWorkMinQubits = 11;  // instances with n >= this get a workspace region
 constexpr int kSplitMin = 16;       // smallest size the large tier may take
+// Side streams of the large tier.  One suffices: it lets the large tier run
+// beside the persistent kernel (whose tail leaves the GPU half idle), while
+// its own launches already fill the GPU, so that more streams only share it.
+constexpr int kLargeStreams = 1;
 
 qsv_status configure(qsv_batch_plan* P, int m, int threads, int split)
 {
@@ -80,7 +96,7 @@ qsv_status configure(qsv_batch_plan* P, int m, int threads, int split)
     for (int i = 0; i < P->ninst; ++i) {
         const HInst& I = P->inst[i];
         TileProgram tp;
-        compile_tile_program(I.ops, I.n, m, tp);
+        compile_tile_program(I.ops, I.n, m, kMaxPassOps, tp);
         BInst& b = bi[i];
         b.n = I.n;
         b.npass = (int)tp.passes.size();
@@ -139,20 +155,48 @@ qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* 
     a.energies = energies;
     a.work = static_cast<char*>(work);
     a.counter = static_cast<int*>(work);
-    if (P->nsmall > 0) {
-        hipError_t e = launch_batch(a, P->dt, P->threads, P->blocks, s);
-        if (e != hipSuccess)
-            return fail(QSV_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
-    }
+    // Large tier: on side streams forked from s (and joined back into s),
+    // instances assigned largest first to the least loaded stream, each stream
+    // with its own workspace region.  The persistent kernel runs on s
+    // meanwhile.
+    std::vector<int> large;
     for (int i : P->order)
-        if (P->inst[i].n >= P->split && P->sub[i]) {
-            qsv_status st = adjoint_enqueue_direct(P->sub[i], params + P->param_off[i],
-                                                   static_cast<char*>(work) + P->big_off,
-                                                   energies + i, grads + P->param_off[i], s);
-            if (st)
-                return st;
-        }
-    return QSV_OK;
+        if (P->inst[i].n >= P->split && P->sub[i])
+            large.push_back(i);
+    const int ns = std::min((int)P->side.size(), (int)large.size());
+    hipError_t e = hipSuccess;
+    if (ns > 0) {
+        e = hipEventRecord(P->ev[0], s);
+        for (int k = 0; k < ns && e == hipSuccess; ++k)
+            e = hipStreamWaitEvent(P->side[k], P->ev[0], 0);
+        if (e != hipSuccess)
+            return fail(QSV_ERR_HIP, "large-tier fork: %s", hipGetErrorString(e));
+    }
+    qsv_status st = QSV_OK;
+    if (P->nsmall > 0) {
+        e = launch_batch(a, P->dt, P->threads, P->blocks, s);
+        if (e != hipSuccess)
+            st = fail(QSV_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+    }
+    std::vector<double> load(ns > 0 ? ns : 1, 0.0);
+    for (int i : large) {
+        if (st)
+            break;
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += std::ldexp((double)P->inst[i].ops.size() + 1, P->inst[i].n);
+        st = adjoint_enqueue_direct(P->sub[i], params + P->param_off[i],
+                                    static_cast<char*>(work) + P->big_off + k * P->big_bytes,
+                                    energies + i, grads + P->param_off[i], P->side[k]);
+    }
+    // join every forked stream, also after an error (a capture needs it)
+    for (int k = 0; k < ns; ++k) {
+        hipError_t j = hipEventRecord(P->ev[1 + k], P->side[k]);
+        if (j == hipSuccess)
+            j = hipStreamWaitEvent(s, P->ev[1 + k], 0);
+        if (j != hipSuccess && !st)
+            st = fail(QSV_ERR_HIP, "large-tier join: %s", hipGetErrorString(j));
+    }
+    return st;
 }
 
 // (tile qubits, threads) with 8 or 16 amplitudes per thread in a tile step
@@ -289,10 +333,12 @@ qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* 
     }
     sig << "/" << std::hex << h;
     P->key = sig.str();
-    // the large tier: an adjoint plan per instance of >= kSplitMin qubits, all
-    // sharing one workspace region (they run one after another)
+    // the large tier: an adjoint plan per instance of >= kSplitMin qubits; up
+    // to kLargeStreams of them run at once, each in a workspace region of its
+    // stream
     P->sub.assign(ninst, nullptr);
     size_t big = 0;
+    int nlarge = 0;
     for (int i = 0; i < ninst; ++i) {
         if (P->inst[i].n < kSplitMin)
             continue;
@@ -302,9 +348,22 @@ qsv_status qsv_batch_plan_create(const qsv_circuit* circs, const qsv_pauli_sum* 
             return fail(st, "instance %d: %s", i, qsv_last_error());
         P->sub[i] = ap;
         big = std::max(big, wb);
+        ++nlarge;
     }
     P->big_off = woff;
-    woff += (long long)((big + 255) & ~size_t(255));
+    P->big_bytes = (long long)((big + 255) & ~size_t(255));
+    if (nlarge > 0) {
+        const int ns = std::min(nlarge, kLargeStreams);
+        woff += ns * P->big_bytes;
+        P->side.assign(ns, nullptr);
+        P->ev.assign(1 + ns, nullptr);
+        for (hipStream_t& q : P->side)
+            if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess)
+                return fail(QSV_ERR_HIP, "large-tier stream creation failed");
+        for (hipEvent_t& q : P->ev)
+            if (hipEventCreateWithFlags(&q, hipEventDisableTiming) != hipSuccess)
+                return fail(QSV_ERR_HIP, "large-tier event creation failed");
+    }
     P->work_bytes = woff;
     // largest estimated work first
     P->order.resize(ninst);

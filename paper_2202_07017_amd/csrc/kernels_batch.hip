@@ -34,16 +34,20 @@ namespace {
 using tx::ExecShared;
 using tx::LOp;
 
+// native 16-byte vector types (arrays of them stay in registers)
+typedef float bv4f __attribute__((ext_vector_type(4)));
+typedef double bv2d __attribute__((ext_vector_type(2)));
+
 template <typename R>
 struct BVec;
 template <>
 struct BVec<float> {
-    using V = float4;
+    using V = bv4f;  // two amplitudes
     static constexpr int APV = 2;
 };
 template <>
 struct BVec<double> {
-    using V = double2;
+    using V = bv2d;  // one amplitude
     static constexpr int APV = 1;
 };
 
@@ -75,6 +79,7 @@ struct BShared {
     int item;
     int pad;
     ExecShared ex;
+    double pacc[kMaxPassOps];  // per-slot sums of a reverse pass
 };
 
 template <typename R, bool REV>
@@ -84,7 +89,7 @@ __device__ void run_pass(const BatchArgs& a, const BInst& I, const DPass& P, R* 
 {
     using V = typename BVec<R>::V;
     constexpr int APV = BVec<R>::APV;
-    tx::stage<R>(P, a.steps, a.ops, a.mats, a.params + I.param_off, REV, ops, steps, sm.ex);
+    tx::stage<R>(P, a.steps, a.ops, a.mats, a.params + I.param_off, REV, ops, steps, sm.pacc);
     __syncthreads();
     // One loop for both tiers (a single inlined copy of the executor): the
     // LDS tier is one tile of n qubits that never leaves LDS.
@@ -96,13 +101,33 @@ __device__ void run_pass(const BatchArgs& a, const BInst& I, const DPass& P, R* 
     V* lg = reinterpret_cast<V*>(lamG);
     V* pl = reinterpret_cast<V*>(phiL);
     V* ll = reinterpret_cast<V*>(lamL);
+    // Vector v = threadIdx.x + blockDim.x * r sits at base | deposit(v * APV);
+    // the tile bits are disjoint, so the deposit splits into a lane part and a
+    // uniform part, and a thread moves its vectors in groups of kMove with
+    // every load of a group in flight together.
+    constexpr int kMove = 4;
+    const uint32_t vpt = nvec / blockDim.x;  // nvec is a multiple of blockDim.x
+    const uint64_t glane = lds_tier ? 0 : tx::deposit_mask((uint64_t)threadIdx.x * APV, P.bmask);
     for (uint64_t tile = 0; tile < ntiles; ++tile) {
         const uint64_t base = tx::insert_mask(tile, P.bmask);
-        for (uint32_t v = threadIdx.x; v < nvec; v += blockDim.x) {
-            const uint64_t gi = (base | tx::deposit_mask((uint64_t)v * APV, P.bmask)) / APV;
-            pl[v] = pg[gi];
-            if (REV)
-                ll[v] = lg[gi];
+        for (uint32_t r0 = 0; r0 < vpt; r0 += kMove) {
+            V xp[kMove], xl[kMove];
+#pragma unroll
+            for (int u = 0; u < kMove; ++u)
+                if (r0 + u < vpt) {
+                    const uint64_t gi =
+                        (base | glane | tx::deposit_mask((uint64_t)blockDim.x * APV * (r0 + u), P.bmask)) / APV;
+                    xp[u] = pg[gi];
+                    if (REV)
+                        xl[u] = lg[gi];
+                }
+#pragma unroll
+            for (int u = 0; u < kMove; ++u)
+                if (r0 + u < vpt) {
+                    pl[threadIdx.x + blockDim.x * (r0 + u)] = xp[u];
+                    if (REV)
+                        ll[threadIdx.x + blockDim.x * (r0 + u)] = xl[u];
+                }
         }
         __syncthreads();
         // 16 amplitudes per thread need tiles of >= 16 (complex64 shapes only)
@@ -111,12 +136,14 @@ __device__ void run_pass(const BatchArgs& a, const BInst& I, const DPass& P, R* 
             wide = a.apt == 16 && m >= 4;
         if constexpr (sizeof(R) == 4) {
             if (wide)
-                tx::exec_tile<R, REV, 16>(ops, steps, P.nsteps, m, phiL, lamL, sm.ex, parity);
+                tx::exec_tile<R, REV, 16>(ops, steps, P.nsteps, m, phiL, lamL, sm.ex, sm.pacc, parity);
         }
         if (!wide)
-            tx::exec_tile<R, REV, 8>(ops, steps, P.nsteps, m, phiL, lamL, sm.ex, parity);
-        for (uint32_t v = threadIdx.x; v < nvec; v += blockDim.x) {
-            const uint64_t gi = (base | tx::deposit_mask((uint64_t)v * APV, P.bmask)) / APV;
+            tx::exec_tile<R, REV, 8>(ops, steps, P.nsteps, m, phiL, lamL, sm.ex, sm.pacc, parity);
+        for (uint32_t r = 0; r < vpt; ++r) {
+            const uint32_t v = threadIdx.x + blockDim.x * r;
+            const uint64_t gi =
+                (base | glane | tx::deposit_mask((uint64_t)blockDim.x * APV * r, P.bmask)) / APV;
             pg[gi] = pl[v];
             if (REV)
                 lg[gi] = ll[v];
@@ -131,13 +158,13 @@ __device__ void run_pass(const BatchArgs& a, const BInst& I, const DPass& P, R* 
                 for (int j = 0; j < P.nops; ++j) {
                     const DOp d = a.ops[P.op_off + j];
                     if (d.kind != 0)
-                        grads[d.param] += sm.ex.pacc[d.slot];
+                        grads[d.param] += sm.pacc[d.slot];
                 }
         } else {
             for (int j = threadIdx.x; j < P.nops; j += blockDim.x) {
                 const DOp d = a.ops[P.op_off + j];
                 if (d.kind != 0)
-                    grads[d.param] += sm.ex.pacc[d.slot];
+                    grads[d.param] += sm.pacc[d.slot];
             }
         }
         __syncthreads();

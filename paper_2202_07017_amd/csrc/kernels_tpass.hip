@@ -1,14 +1,16 @@
 // One cache-blocked pass of a tile program over a whole state (one launch per
 // pass, tiles spread over the grid).
 //
-// Every block stages the pass (matrices, steps) in LDS once, then takes tiles
-// tile = blockIdx.x, + gridDim.x, ...: loads the tile (psi; reverse passes
-// also lambda) into LDS in contiguous chunks of 16-byte vectors (all of a
-// thread's vectors in flight together, the next tile's while this one is
-// processed), runs the pass's steps on it (tile_exec.h) and stores it back.  Reverse passes end by
-// writing the block's per-rotation FP64 sums to
-// partials[(slot_base + slot) * nb + block], which a finalize kernel adds in
-// block order.
+// k_tstage turns every gate of the program into its executor descriptor
+// (matrix and form; forward U, then reverse U^dagger) once per run; the pass
+// kernels read a pass's descriptors and steps from there through scalar
+// loads.  Every block takes tiles tile = blockIdx.x, + gridDim.x, ...: loads
+// the tile (psi; reverse passes also lambda) into LDS in contiguous chunks of
+// 16-byte vectors (all of a thread's vectors in flight together, the next
+// tile's while this one is processed), runs the pass's steps on it
+// (tile_exec.h) and stores it back.  Reverse passes end by writing the
+// block's per-rotation FP64 sums to partials[(slot_base + slot) * nb + block],
+// which a finalize kernel adds in block order.
 #include "qsv_tpass.h"
 #include "tile_exec.h"
 
@@ -34,9 +36,20 @@ struct TV<double> {
     static constexpr int APV = 1;
 };
 
-// 16-byte vectors per thread per state: a tile has at most 2^12 complex64 or
-// 2^11 complex128 amplitudes, i.e. 2048 vectors over kTpassThreads threads.
-constexpr int kVPT = 2048 / kTpassThreads;
+// Threads per block: 8 amplitudes each over a full tile (2^12 complex64 or
+// 2^11 complex128 amplitudes).
+template <typename R>
+constexpr int tpass_threads()
+{
+    return sizeof(R) == 4 ? 512 : 256;
+}
+
+// 16-byte vectors per thread per state (a tile is 2048 vectors).
+template <typename R>
+constexpr int tpass_vpt()
+{
+    return 2048 / tpass_threads<R>();
+}
 
 // Waves per SIMD to keep two blocks resident (both tiles of a complex64
 // reverse pass fit twice in LDS); 1 = no constraint.
@@ -46,25 +59,39 @@ constexpr int tpass_wpe()
     return (sizeof(R) == 4 && REV) ? 4 : 1;
 }
 
+template <typename R>
+__global__ void __launch_bounds__(256) k_tstage(const DOp* __restrict__ ops, int nops,
+                                                const double* __restrict__ mats,
+                                                const double* __restrict__ params,
+                                                LOp<R>* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2 * nops)
+        out[i] = tx::make_lop<R>(ops[i < nops ? i : i - nops], mats, params, i >= nops);
+}
+
 template <typename R, bool REV>
-__global__ void __launch_bounds__(kTpassThreads) __attribute__((amdgpu_waves_per_eu(tpass_wpe<R, REV>())))
-k_tpass(R* __restrict__ psi, R* __restrict__ lam,
-                                                         const TPassArgs a)
+__global__ void __launch_bounds__(tpass_threads<R>())
+    __attribute__((amdgpu_waves_per_eu(tpass_wpe<R, REV>())))
+    k_tpass(R* __restrict__ psi, R* __restrict__ lam, const LOp<R>* __restrict__ ops,
+            const DStep* __restrict__ steps, const TPassArgs a)
 {
     using V = typename TV<R>::V;
     constexpr int APV = TV<R>::APV;
     constexpr int NS = REV ? 2 : 1;  // states moved per tile
+    constexpr int kTpassThreads = tpass_threads<R>();
+    constexpr int kVPT = tpass_vpt<R>();
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ ExecShared sh;
     const int m = a.m;
     const size_t tile = (size_t)2 * sizeof(R) << m;
     R* phiL = reinterpret_cast<R*>(smem);
     R* lamL = reinterpret_cast<R*>(smem + tile);
-    LOp<R>* ops = reinterpret_cast<LOp<R>*>(smem + (REV ? 2 : 1) * tile);
-    DStep* steps = reinterpret_cast<DStep*>(reinterpret_cast<unsigned char*>(ops) +
-                                            sizeof(LOp<R>) * kMaxPassOps);
+    double* pacc = reinterpret_cast<double*>(smem + 2 * tile);  // reverse passes
     const DPass P = a.pass;
-    tx::stage<R>(P, a.steps, a.ops, a.mats, a.params, REV, ops, steps, sh);
+    if (REV)
+        for (int j = threadIdx.x; j < P.nrot; j += kTpassThreads)
+            pacc[j] = 0.0;
     const uint32_t nvec = (1u << m) / APV;
     const uint64_t ntiles = 1ull << (a.n - m);
     V* const gs[2] = {reinterpret_cast<V*>(psi), reinterpret_cast<V*>(lam)};
@@ -122,7 +149,7 @@ k_tpass(R* __restrict__ psi, R* __restrict__ lam,
         __syncthreads();
         if (PF)
             load(t + gridDim.x < ntiles ? t + gridDim.x : t);
-        tx::exec_tile<R, REV, 8>(ops, steps, P.nsteps, m, phiL, lamL, sh, parity);
+        tx::exec_tile<R, REV, 8>(ops, steps, P.nsteps, m, phiL, lamL, sh, pacc, parity);
         uint64_t gl = glane;
         asm volatile("" : "+v"(gl));
 #pragma unroll
@@ -138,7 +165,7 @@ k_tpass(R* __restrict__ psi, R* __restrict__ lam,
     }
     if (REV)
         for (int j = threadIdx.x; j < P.nrot; j += blockDim.x)
-            a.partials[(size_t)(P.slot_base + j) * gridDim.x + blockIdx.x] = sh.pacc[j];
+            a.partials[(size_t)(P.slot_base + j) * gridDim.x + blockIdx.x] = pacc[j];
 }
 
 template <typename R, bool REV>
@@ -149,8 +176,10 @@ hipError_t go(const TPassArgs& a, void* psi, void* lam, int blocks, hipStream_t 
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_tpass<R, REV>), dim3(blocks), dim3(kTpassThreads), lds, s,
-                       static_cast<R*>(psi), static_cast<R*>(lam ? lam : psi), a);
+    const LOp<R>* ops = static_cast<const LOp<R>*>(a.lops) + (REV ? a.nops_total : 0) + a.pass.op_off;
+    hipLaunchKernelGGL((k_tpass<R, REV>), dim3(blocks), dim3(tpass_threads<R>()), lds, s,
+                       static_cast<R*>(psi), static_cast<R*>(lam ? lam : psi), ops,
+                       a.steps + a.pass.step_off, a);
     return hipGetLastError();
 }
 
@@ -159,8 +188,27 @@ hipError_t go(const TPassArgs& a, void* psi, void* lam, int blocks, hipStream_t 
 size_t tpass_lds_bytes(int dt, int m, bool rev)
 {
     const size_t R = dt == C64 ? 4 : 8;
-    const size_t op = dt == C64 ? sizeof(LOp<float>) : sizeof(LOp<double>);
-    return (rev ? 2 : 1) * (2 * R << m) + (op + sizeof(DStep)) * kMaxPassOps;
+    return rev ? 2 * (2 * R << m) + sizeof(double) * kMaxTpassOps : (2 * R << m);
+}
+
+size_t tpass_lop_bytes(int dt, int nops)
+{
+    return 2 * (size_t)nops * (dt == C64 ? sizeof(LOp<float>) : sizeof(LOp<double>));
+}
+
+hipError_t launch_tstage(const TPassArgs& a, int dt, hipStream_t s)
+{
+    const int n2 = 2 * a.nops_total;
+    if (n2 == 0)
+        return hipSuccess;
+    const int blocks = (n2 + 255) / 256;
+    if (dt == C64)
+        hipLaunchKernelGGL(k_tstage<float>, dim3(blocks), dim3(256), 0, s, a.ops, a.nops_total, a.mats,
+                           a.params, static_cast<LOp<float>*>(a.lops));
+    else
+        hipLaunchKernelGGL(k_tstage<double>, dim3(blocks), dim3(256), 0, s, a.ops, a.nops_total, a.mats,
+                           a.params, static_cast<LOp<double>*>(a.lops));
+    return hipGetLastError();
 }
 
 int tpass_resident_blocks(int dt, int m, bool rev)
@@ -179,7 +227,8 @@ int tpass_resident_blocks(int dt, int m, bool rev)
                                       : reinterpret_cast<const void*>(k_tpass<double, false>));
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kTpassThreads, lds) != hipSuccess)
+    const int threads = dt == C64 ? tpass_threads<float>() : tpass_threads<double>();
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, lds) != hipSuccess)
         return 0;
     return per * cus;
 }

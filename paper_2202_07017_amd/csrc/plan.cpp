@@ -327,6 +327,7 @@ struct qsv_adjoint_plan {
     int tm = 0;       // tile qubits
     int tblocks = 0;  // blocks per pass launch (= partial columns)
     size_t o_steps = 0, o_ops = 0, o_mats = 0;
+    size_t off_lops = 0;  // workspace: staged gate descriptors (forward, reverse)
 };
 
 namespace {
@@ -515,7 +516,7 @@ qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum*
             gates.push_back(g);
         }
         P->tm = std::min(n, dt == QSV_C64 ? 12 : 11);
-        compile_tile_program(gates, n, P->tm, P->tp);
+        compile_tile_program(gates, n, P->tm, kMaxTpassOps, P->tp);
         const int res = tpass_resident_blocks(dt, P->tm, true);
         if (res <= 0)
             return fail(QSV_ERR_UNSUPPORTED, "tile pass kernel does not fit this device");
@@ -546,7 +547,8 @@ qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum*
         P->off_part = P->off_lam + up(sb);
         P->off_red = P->off_part +
                      up(sizeof(double) * (size_t)std::max(P->nslots, 1) * (size_t)P->tblocks);
-        P->work_bytes = P->off_red + kReduceWorkBytes;
+        P->off_lops = P->off_red + up(kReduceWorkBytes);
+        P->work_bytes = P->off_lops + tpass_lop_bytes(dt, (int)P->tp.ops.size());
         *work_bytes = P->work_bytes;
         *plan = P.release();
         return ok();
@@ -623,9 +625,14 @@ static qsv_status adjoint_enqueue_tiled(qsv_adjoint_plan* P, const double* param
     a.ops = static_cast<const DOp*>(P->dev.at(P->o_ops));
     a.mats = static_cast<const double*>(P->dev.at(P->o_mats));
     a.params = params;
+    a.lops = static_cast<char*>(psi) + P->off_lops;
     a.partials = part;
+    a.nops_total = (int)P->tp.ops.size();
     a.n = P->n;
     a.m = P->tm;
+    hipError_t es = launch_tstage(a, P->dt, s);
+    if (es != hipSuccess)
+        return fail(QSV_ERR_HIP, "tile program staging launch: %s", hipGetErrorString(es));
     for (const DPass& pass : P->tp.passes) {
         a.pass = pass;
         hipError_t e = launch_tpass(a, P->dt, false, psi, nullptr, P->tblocks, s);

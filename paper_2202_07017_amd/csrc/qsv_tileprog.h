@@ -17,7 +17,8 @@
 
 namespace qsv {
 
-constexpr int kMaxPassOps = 128;  // gates per pass
+constexpr int kMaxPassOps = 128;   // gates per pass, batched mode (staged in LDS)
+constexpr int kMaxTpassOps = 512;  // gates per pass, single-state passes
 constexpr int kMaxStepOps = 8;    // gates per step
 constexpr int kStepQubits = 3;
 
@@ -31,8 +32,8 @@ struct DOp {         // a gate of a pass, step-local coordinates
     int32_t slot;    // rotations: pass-local slot (0..nrot-1); -1 otherwise
 };
 
-struct DStep {
-    uint8_t nq;      // qubits of the step (1..3)
+struct alignas(8) DStep {
+    uint8_t nq;      // qubits of the step (always 3)
     uint8_t q[3];    // their tile-local positions, ascending
     int16_t o0, o1;  // gate range [o0, o1) inside the pass
 };
@@ -62,9 +63,10 @@ struct TileProgram {
     std::vector<int> slot_param;  // global slot -> parameter (rotations, in pass order)
 };
 
-// Compile `gates` (circuit order) on n qubits into passes with tiles of m
-// qubits (m >= n: passes over the whole state, split every kMaxPassOps gates).
-// Rotations get consecutive global slots in forward pass order.
-void compile_tile_program(const std::vector<HGate>& gates, int n, int m, TileProgram& out);
+// Compile `gates` (circuit order) on n >= 3 qubits into passes of at most cap
+// gates with tiles of m >= 3 qubits (m >= n: passes over the whole state).
+// Every step spans exactly three qubits.  Rotations get consecutive global
+// slots in forward pass order.
+void compile_tile_program(const std::vector<HGate>& gates, int n, int m, int cap, TileProgram& out);
 
 }  // namespace qsv

@@ -26,19 +26,40 @@ int local_bit(uint64_t B, int q)
     return popc(B & ((1ull << q) - 1));
 }
 
-// Passes: each takes, in circuit order, every remaining gate whose qubits are
-// tile qubits and that no earlier unscheduled gate blocks (an unscheduled
-// gate blocks its qubits for every later gate).  Tile qubits: 0, 1, 2 (so a
-// tile is made of >= 64-byte contiguous chunks), then the qubits of the
-// remaining gates in order of first appearance, then the lowest unused ones.
-std::vector<std::pair<uint64_t, std::vector<int>>> schedule(const std::vector<HGate>& g, int n, int m)
+// Gates (indices into `rest`, circuit order) that a pass with tile qubits B
+// takes: every gate whose qubits are tile qubits and that no earlier gate
+// left behind blocks (a gate left behind blocks its qubits for every later
+// gate, so the taken gates commute with all of them), at most cap gates.
+int take(const std::vector<uint64_t>& rest, uint64_t B, int cap, std::vector<int>* out)
+{
+    uint64_t blocked = 0;
+    int c = 0;
+    for (int o = 0; o < (int)rest.size(); ++o) {
+        const uint64_t q = rest[o];
+        if ((q & ~B) == 0 && (q & blocked) == 0 && c < cap) {
+            ++c;
+            if (out)
+                out->push_back(o);
+        } else {
+            blocked |= q;
+        }
+    }
+    return c;
+}
+
+// Passes.  Tile qubits: 0, 1, 2 (so a tile is made of >= 64-byte contiguous
+// chunks), then one qubit at a time the one that lets the pass take the most
+// gates; where no single qubit adds a gate, the first qubit outside the tile
+// of the first remaining gate.
+std::vector<std::pair<uint64_t, std::vector<int>>> schedule(const std::vector<HGate>& g, int n, int m,
+                                                            int cap)
 {
     std::vector<std::pair<uint64_t, std::vector<int>>> out;
     const int N = (int)g.size();
     if (n <= m) {
-        for (int s = 0; s < N || (s == 0 && N == 0); s += kMaxPassOps) {
+        for (int s = 0; s < N || (s == 0 && N == 0); s += cap) {
             std::vector<int> ops;
-            for (int o = s; o < N && o < s + kMaxPassOps; ++o)
+            for (int o = s; o < N && o < s + cap; ++o)
                 ops.push_back(o);
             out.push_back({(n >= 64 ? ~0ull : ((1ull << n) - 1)), ops});
             if (N == 0)
@@ -46,35 +67,51 @@ std::vector<std::pair<uint64_t, std::vector<int>>> schedule(const std::vector<HG
         }
         return out;
     }
-    std::vector<bool> done(N, false);
-    int left = N;
-    while (left > 0) {
+    std::vector<int> idx(N);
+    std::vector<uint64_t> rest(N);
+    for (int o = 0; o < N; ++o) {
+        idx[o] = o;
+        rest[o] = gate_qubits(g[o]);
+    }
+    while (!rest.empty()) {
         uint64_t B = 0x7;
-        for (int o = 0; o < N && popc(B) < m; ++o) {
-            if (done[o])
-                continue;
-            uint64_t q = gate_qubits(g[o]) & ~B;
-            while (q && popc(B) < m) {
-                B |= q & (~q + 1);
-                q &= q - 1;
+        while (popc(B) < m) {
+            const int base = take(rest, B, cap, nullptr);
+            int best = -1, gain = base;
+            for (int q = 0; q < n; ++q) {
+                if ((B >> q) & 1)
+                    continue;
+                const int c = take(rest, B | (1ull << q), cap, nullptr);
+                if (c > gain) {
+                    gain = c;
+                    best = q;
+                }
             }
+            for (size_t o = 0; o < rest.size() && best < 0; ++o)
+                if (rest[o] & ~B)
+                    best = __builtin_ctzll(rest[o] & ~B);
+            for (int q = 0; q < n && best < 0; ++q)
+                if (!((B >> q) & 1))
+                    best = q;
+            B |= 1ull << best;
         }
-        for (int b = 0; b < n && popc(B) < m; ++b)
-            B |= 1ull << b;
+        std::vector<int> sel;
+        take(rest, B, cap, &sel);
         std::vector<int> ops;
-        uint64_t blocked = 0;
-        for (int o = 0; o < N; ++o) {
-            if (done[o])
-                continue;
-            const uint64_t q = gate_qubits(g[o]);
-            if ((q & ~B) == 0 && (q & blocked) == 0 && (int)ops.size() < kMaxPassOps) {
-                ops.push_back(o);
-                done[o] = true;
-                --left;
-            } else {
-                blocked |= q;
-            }
+        std::vector<bool> taken(rest.size(), false);
+        for (int o : sel) {
+            ops.push_back(idx[o]);
+            taken[o] = true;
         }
+        size_t w = 0;
+        for (size_t o = 0; o < rest.size(); ++o)
+            if (!taken[o]) {
+                rest[w] = rest[o];
+                idx[w] = idx[o];
+                ++w;
+            }
+        rest.resize(w);
+        idx.resize(w);
         out.push_back({B, ops});
     }
     return out;
@@ -82,10 +119,10 @@ std::vector<std::pair<uint64_t, std::vector<int>>> schedule(const std::vector<HG
 
 }  // namespace
 
-void compile_tile_program(const std::vector<HGate>& gates, int n, int m, TileProgram& out)
+void compile_tile_program(const std::vector<HGate>& gates, int n, int m, int cap, TileProgram& out)
 {
     out = TileProgram{};
-    for (const auto& pr : schedule(gates, n, m)) {
+    for (const auto& pr : schedule(gates, n, m, cap)) {
         const uint64_t B = pr.first;
         DPass P{};
         P.bmask = B;
@@ -93,24 +130,37 @@ void compile_tile_program(const std::vector<HGate>& gates, int n, int m, TilePro
         P.op_off = (int)out.ops.size();
         P.nops = (int)pr.second.size();
         P.slot_base = (int)out.slot_param.size();
-        // steps: consecutive gates whose (tile-local) qubits fit 3 qubits
-        size_t i = 0;
-        const std::vector<int>& ops = pr.second;
-        while (i < ops.size()) {
-            uint32_t S = 0;
-            size_t j = i;
-            while (j < ops.size() && (int)(j - i) < kMaxStepOps) {
-                const HGate& h = gates[ops[j]];
-                uint32_t q = 1u << local_bit(B, h.t);
-                if (h.nc > 0)
-                    q |= 1u << local_bit(B, h.c0);
-                if (h.nc > 1)
-                    q |= 1u << local_bit(B, h.c1);
-                if (popc(S | q) > kStepQubits)
-                    break;
-                S |= q;
-                ++j;
+        auto local = [&](const HGate& h) {
+            uint32_t q = 1u << local_bit(B, h.t);
+            if (h.nc > 0)
+                q |= 1u << local_bit(B, h.c0);
+            if (h.nc > 1)
+                q |= 1u << local_bit(B, h.c1);
+            return q;
+        };
+        // Steps: the first remaining gate, then every later one whose qubits
+        // fit the step's three and that commutes with the gates passed over
+        // (no shared qubit), at most kMaxStepOps; gates keep circuit order.
+        std::vector<int> rest = pr.second;
+        while (!rest.empty()) {
+            uint32_t S = 0, blocked = 0;
+            std::vector<int> step;
+            std::vector<int> left;
+            for (int o : rest) {
+                const uint32_t q = local(gates[o]);
+                if ((int)step.size() < kMaxStepOps && (q & blocked) == 0 && popc(S | q) <= kStepQubits) {
+                    S |= q;
+                    step.push_back(o);
+                } else {
+                    blocked |= q;
+                    left.push_back(o);
+                }
             }
+            rest.swap(left);
+            // pad to three qubits with the highest free tile positions: the
+            // executor always works on groups of 8 amplitudes
+            for (int b = popc(B) - 1; b >= 0 && popc(S) < kStepQubits; --b)
+                S |= 1u << b;
             DStep st{};
             st.nq = (uint8_t)popc(S);
             int k = 0;
@@ -125,8 +175,8 @@ void compile_tile_program(const std::vector<HGate>& gates, int n, int m, TilePro
                         return x;
                 return -1;
             };
-            for (size_t o = i; o < j; ++o) {
-                const HGate& h = gates[ops[o]];
+            for (int o : step) {
+                const HGate& h = gates[o];
                 DOp d{};
                 d.kind = (uint8_t)h.kind;
                 d.tq = (uint8_t)stepbit(h.t);
@@ -142,7 +192,6 @@ void compile_tile_program(const std::vector<HGate>& gates, int n, int m, TilePro
             }
             st.o1 = (int16_t)(out.ops.size() - P.op_off);
             out.steps.push_back(st);
-            i = j;
         }
         P.nsteps = (int)out.steps.size() - P.step_off;
         std::vector<int> ps(out.slot_param.begin() + P.slot_base, out.slot_param.end());
