@@ -330,7 +330,15 @@ __device__ __forceinline__ void exec_step(const LOp<R>* ops, int o0, int nop, in
     for (int j = 0; j < kNA; ++j)
         off[j] = ((uint32_t)(j & 1) << q0) | ((uint32_t)((j >> 1) & 1) << q1) |
                  ((uint32_t)((j >> 2) & 1) << q2);
+    // (threads without amplitudes run the gates on zeros: no predicate per
+    // gate, and their generator terms are zero)
     R pr[APT], pi[APT], lr[REV ? APT : 1], li[REV ? APT : 1];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        pr[j] = pi[j] = R(0);
+        if (REV)
+            lr[j] = li[j] = R(0);
+    }
     uint32_t base[GP];
     if (active) {
 #pragma unroll
@@ -363,9 +371,8 @@ __device__ __forceinline__ void exec_step(const LOp<R>* ops, int o0, int nop, in
         for (int q = 0; q < 8; ++q)
             m[q] = o.m[q];
         double acc = 0.0;
-        if (active)
-            apply_gate<R, REV, GP>(lop_tq(info), lop_cm(info), lop_form(info), gen, m, pr, pi, lr,
-                                   li, acc);
+        apply_gate<R, REV, GP>(lop_tq(info), lop_cm(info), lop_form(info), gen, m, pr, pi, lr, li,
+                               acc);
         if (REV && gen) {
             acc = wave_sum(acc);
             if ((threadIdx.x & 63) == 0)

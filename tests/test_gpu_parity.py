@@ -336,6 +336,51 @@ def test_adjoint_gradient(q, orc):
                 assert abs(en - E_ref) < (1e-11 if name == "c128" else 1e-4)
 
 
+def every_form_circuit(n, ngates, seed):
+    """Single-target gates of every matrix form the tile executor specialises
+    (real: H, RY; swap: X; imaginary off-diagonal: Y, RX; real diagonal: Z;
+    complex diagonal: S, T, RZ; general: Haar U(2)), each with 0, 1 or 2
+    controls on random qubits, rotations sharing some parameters."""
+    rng = np.random.default_rng(seed)
+    s = np.diag([1, 1j]).astype(complex)
+    t = np.diag([1, np.exp(0.25j * np.pi)]).astype(complex)
+    ops, npar = [], 0
+    for _ in range(ngates):
+        kind = ["h", "x", "y", "z", "s", "t", "u", "rx", "ry", "rz"][rng.integers(10)]
+        q = [int(v) for v in rng.choice(n, 1 + int(rng.integers(3)), replace=False)]
+        tq, cs = (q[0],), tuple(q[1:])
+        if kind in ("rx", "ry", "rz"):
+            share = npar > 0 and rng.random() < 0.2
+            ops.append(W.Op(kind, tq, controls=cs, param=int(rng.integers(npar)) if share else npar))
+            npar += 0 if share else 1
+        elif kind in ("s", "t", "u"):
+            m = {"s": s, "t": t}.get(kind)
+            ops.append(W.Op("matrix", tq, controls=cs, matrix=m if m is not None else W.haar_unitary(rng, 2)))
+        else:
+            ops.append(W.Op(kind, tq, controls=cs))
+    return W.Circuit(n, ops, npar)
+
+
+@pytest.mark.parametrize("n", [13, 15])
+def test_adjoint_tiled_every_form(q, orc, n):
+    """Cache-blocked adjoint over several tiles with gates of every form and
+    control count, against the oracle's adjoint."""
+    import torch
+    circ = every_form_circuit(n, 160, 300 + n)
+    H = W.random_pauli_sum(n, 12, seed=n)
+    p = W.random_params(circ.nparams, 31 + n)
+    E_ref, g_ref = orc.adjoint(circ, p, H)
+    for name in DTYPES:
+        say("adjoint every form", name, n, len(circ.ops), circ.nparams)
+        plan = q.AdjointPlan(circ, H, 1 if name == "c64" else 2, 5)
+        e, g = plan.run(torch.from_numpy(p).cuda())
+        e, g = e.cpu().numpy()[0], g.cpu().numpy()
+        scale = float(np.sum(np.abs(H.coeff)))
+        tol = (1e-10 * scale, 1e-9 * scale) if name == "c128" else (2e-6 * n * scale, 2e-6 * n * scale)
+        assert abs(e - E_ref) < tol[0], (e, E_ref)
+        assert np.max(np.abs(g - g_ref)) < tol[1], np.max(np.abs(g - g_ref))
+
+
 @pytest.mark.parametrize("n", [14, 16])
 def test_adjoint_tiled_multi_tile(q, orc, n):
     """Cache-blocked adjoint (several tiles per pass, staircase passes) and the
