@@ -133,6 +133,32 @@ def profile_kernels():
     print("profile run done: 2 x 4 GiB copy, 10 x single-qubit sweep n=30 c64 t=15", flush=True)
 
 
+def profile_mfma():
+    """Short run for the matrix-core counters: fused dense blocks of k = 4 and
+    k = 5 qubits (Haar unitaries) on a 30-qubit state, complex64 then
+    complex128, five launches each on low and on spread targets."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_07017_amd import qsv
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(1005)
+    n = 30
+    for dt in (torch.complex64, torch.complex128):
+        psi = torch.empty(1 << n, dtype=dt, device=dev)
+        qsv.qsv_init_random(psi, 5)
+        for t in [(0, 1, 2, 3), (0, 1, 2, 3, 4), (3, 11, 19, 27), (2, 9, 15, 22, 29)]:
+            G = W.haar_unitary(rng, 2 ** len(t))
+            for _ in range(5):
+                qsv.qsv_apply_gate(psi, t, (), G)
+        torch.cuda.synchronize()
+        del psi
+        torch.cuda.empty_cache()
+    print("profile run done: k = 4, 5 fused blocks, n=30, c64 and c128, 5 launches per target set",
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +168,8 @@ def main():
     ap.add_argument("--skip-side", action="store_true", help="only the timed step")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only the dominant kernel and a copy of known size (counter runs)")
+    ap.add_argument("--profile-mfma", action="store_true",
+                    help="only fused k = 4, 5 blocks (matrix-core counter runs)")
     ap.add_argument("--legs", default="",
                     help="comma list of side legs to run alone (adjoint, adjoint26, batched): profiling runs")
     args = ap.parse_args()
@@ -152,6 +180,9 @@ def main():
 
     if args.profile_kernels:
         profile_kernels()
+        return
+    if args.profile_mfma:
+        profile_mfma()
         return
     if args.legs:
         import numpy as np
