@@ -171,7 +171,7 @@ def main():
     ap.add_argument("--profile-mfma", action="store_true",
                     help="only fused k = 4, 5 blocks (matrix-core counter runs)")
     ap.add_argument("--legs", default="",
-                    help="comma list of side legs to run alone (adjoint, adjoint26, batched): profiling runs")
+                    help="comma list of side legs to run alone (adjoint, adjoint26, batched, configs): profiling runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X and this build has no "
@@ -199,6 +199,8 @@ def main():
             out["adjoint_n26"] = adjoint_leg_large(qsv, W, torch, np, dev)
         if "batched" in legs:
             out["batched"] = batched_leg(qsv, W, torch, np, dev)
+        if "configs" in legs:
+            out["configs"] = configs_leg(qsv, W, torch, np, dev, torch.cuda.current_stream())
         print(json.dumps(out), flush=True)
         return
 
@@ -282,8 +284,41 @@ def main():
         out["adjoint"] = adjoint_leg(qsv, W, torch, np, dev)
         out["adjoint_n26"] = adjoint_leg_large(qsv, W, torch, np, dev)
         out["batched"] = batched_leg(qsv, W, torch, np, dev)
+        out["configs"] = configs_leg(qsv, W, torch, np, dev, stream)
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+
+
+def configs_leg(qsv, W, torch, np, dev, stream):
+    """The seeded random circuits of the workload list, timed as whole plans
+    (graph replay, state resident): n = 20 complex128 U(2) + CZ layers
+    (depth 10); n = 28 random pairs (depth 20) unfused and fused to
+    k = 2..5 in complex64 and complex128; n = 32 random 1-3-qubit unitaries
+    (depth 12) fused to k = 5 in complex64 and complex128.  GB/s counts the
+    plan's algorithmic bytes, TFLOP/s its algorithmic flops."""
+    cases = [("n20_u2cz_depth10", W.random_u2_cz(n=20, depth=10, seed=1000), None, ["c128"], [1, 5])]
+    c2, p2 = W.random_u2_pairs(n=28, depth=20, seed=1001)
+    cases.append(("n28_pairs_depth20", c2, p2, ["c64", "c128"], [1, 2, 3, 4, 5]))
+    cases.append(("n32_dense123_depth12", W.random_dense_123(n=32, depth=12, seed=1002), None,
+                  ["c64", "c128"], [5]))
+    out = {}
+    for name, circ, params, dts, fuses in cases:
+        for dt in dts:
+            tdt = torch.complex64 if dt == "c64" else torch.complex128
+            psi = torch.empty(1 << circ.n, dtype=tdt, device=dev)
+            qsv.qsv_init_random(psi, 7)
+            for k in fuses:
+                plan = qsv.Plan(circ, qsv.C64 if dt == "c64" else qsv.C128, k, params_host=params)
+                nl, b, f = plan.info()
+                plan.run(psi)
+                t = event_time(lambda: plan.run(psi), 3, stream)
+                out["%s_%s_fuse%d" % (name, dt, k)] = {
+                    "ms": round(t * 1e3, 3), "launches": nl, "gbs": round(b / t / 1e9, 1),
+                    "hbm_frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4), "tflops": round(f / t / 1e12, 2)}
+                del plan
+            del psi
+            torch.cuda.empty_cache()
+    return out
 
 
 def batched_leg(qsv, W, torch, np, dev):
