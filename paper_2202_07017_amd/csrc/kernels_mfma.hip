@@ -100,8 +100,19 @@ __device__ __forceinline__ uint64_t xcd_block()
     return b < (per << 3) ? (uint64_t)(b & 7u) * per + (b >> 3) : (uint64_t)b;
 }
 
+// Waves per SIMD the register allocation must allow (1 = no constraint):
+// 8 for complex64 k = 4 (fits in 64 VGPRs), 4 for complex128 k = 5 (with the
+// B reads two k-steps ahead it fits in 128); measured 3-5% faster each.
+// complex64 k = 5 keeps its 72 VGPRs: capping it spills, and 8-wave
+// workgroups with half the columns per wave ran slower.
 template <typename R, int K>
-__global__ void __launch_bounds__(256) k_mfma(R* __restrict__ psi0, R* __restrict__ psi1,
+constexpr int mfma_wpe()
+{
+    return (sizeof(R) == 4 && K == 4) ? 8 : ((sizeof(R) == 8 && K == 5) ? 4 : 1);
+}
+
+template <typename R, int K>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma_wpe<R, K>()))) k_mfma(R* __restrict__ psi0, R* __restrict__ psi1,
                                               const MfmaK<K> a, const R* __restrict__ frag)
 {
     using T = MfmaT<R>;
@@ -184,7 +195,7 @@ __global__ void __launch_bounds__(256) k_mfma(R* __restrict__ psi0, R* __restric
     // B reads in groups of KG k-steps, one group ahead of its products
     // (the scheduling barriers keep the reads of group g + 1 issued before
     // the products of group g).
-    constexpr int KG = 4;
+    constexpr int KG = (sizeof(R) == 8 && K == 5) ? 2 : 4;
     R bfr[KS][CBW];
 #pragma unroll
     for (int kk = 0; kk < KG; ++kk)
