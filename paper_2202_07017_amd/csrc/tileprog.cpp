@@ -96,7 +96,14 @@ std::vector<std::pair<uint64_t, std::vector<int>>> schedule(const std::vector<HG
             B |= 1ull << best;
         }
         std::vector<int> sel;
-        take(rest, B, cap, &sel);
+        if (take(rest, B, cap, &sel) == 0) {
+            // (only when the first remaining gate's qubits do not fit beside
+            // 0, 1, 2, i.e. m < 6) its qubits first, then the lowest others
+            B = rest[0];
+            for (int b = 0; b < n && popc(B) < m; ++b)
+                B |= 1ull << b;
+            take(rest, B, cap, &sel);
+        }
         std::vector<int> ops;
         std::vector<bool> taken(rest.size(), false);
         for (int o : sel) {
