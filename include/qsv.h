@@ -239,8 +239,10 @@ typedef struct qsv_adjoint_plan qsv_adjoint_plan;
  * control-on subspace).  No per-gate checkpoints are kept.  Ops must be
  * unitary; parameters may be shared between ops (their terms add).
  * *work_bytes = size of the device workspace qsv_adjoint_run needs (two
- * states plus FP64 partial sums).  fuse_k as in qsv_plan_create (applies to
- * runs of non-rotation gates). */
+ * states, FP64 partial sums and, for cache-blocked plans, the gate
+ * descriptors each run stages from params_dev).  Runs that share one
+ * workspace must not overlap in time.  fuse_k as in qsv_plan_create (applies
+ * to runs of non-rotation gates). */
 qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum* H, qsv_dtype dt,
                                    int fuse_k, qsv_adjoint_plan** plan, size_t* work_bytes);
 
@@ -278,8 +280,12 @@ typedef struct qsv_batch_plan qsv_batch_plan;
  * largest first: those whose two state vectors fit the workgroup's LDS tile
  * stay there for the whole evaluation, the others stream cache-blocked tiles
  * of their own workspace region.  Instances at or above the split size (16 or
- * more qubits) run after it, one at a time across the whole GPU, with the
- * cache-blocked adjoint.  The tile size, workgroup size and split size come
+ * more qubits) run one at a time across the whole GPU with the cache-blocked
+ * adjoint, on a side stream that the plan owns (created on the device current
+ * at plan creation, default priority): qsv_batch_run forks it from `stream`
+ * with an event before the persistent launch and joins it back after, so the
+ * two tiers overlap and every result is ready when `stream` reaches the end
+ * of the call's work.  The tile size, workgroup size and split size come
  * from the autotuner (qsv_batch_tune) or its cache.  Parameters and
  * gradients of instance i live at offsets[i] .. offsets[i+1]-1 of the
  * concatenated vectors (qsv_batch_offsets).  *work_bytes = workspace size. */
