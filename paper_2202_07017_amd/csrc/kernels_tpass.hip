@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(tpass_threads<R>())
         __syncthreads();
         if (PF)
             load(t + gridDim.x < ntiles ? t + gridDim.x : t);
-        tx::exec_tile<R, REV, 8>(ops, steps, P.nsteps, m, phiL, lamL, sh, pacc, parity);
+        tx::exec_tile<R, REV, 8, true>(ops, steps, P.nsteps, m, phiL, lamL, sh, pacc, parity);
         uint64_t gl = glane;
         asm volatile("" : "+v"(gl));
 #pragma unroll

@@ -316,7 +316,7 @@ __device__ __forceinline__ void apply_gate(int tq, int cm, int form, int gen, co
 // in reverse order), and the per-gate gradient partials go to LDS after a
 // wave reduction.  `ops` may point to LDS or to global memory; the gate
 // descriptors are the same for every lane.
-template <typename R, bool REV, int APT>
+template <typename R, bool REV, int APT, bool PAIR2>
 __device__ __forceinline__ void exec_step(const LOp<R>* ops, int o0, int nop, int q0, int q1,
                                           int q2, int mb, R* phi, R* lam, ExecShared& sh,
                                           int parity)
@@ -361,7 +361,7 @@ __device__ __forceinline__ void exec_step(const LOp<R>* ops, int o0, int nop, in
             }
         }
     }
-    auto one = [&](int k) {
+    auto one = [&](int k) __attribute__((always_inline)) {
         const int kk = REV ? nop - 1 - k : k;
         const LOp<R>& o = ops[o0 + kk];
         const uint32_t info = __builtin_amdgcn_readfirstlane(o.info);
@@ -379,12 +379,13 @@ __device__ __forceinline__ void exec_step(const LOp<R>* ops, int o0, int nop, in
                 sh.red[parity][kk][threadIdx.x >> 6] = acc;
         }
     };
-    // Forward passes take two gates per iteration: the register allocator
-    // then alternates between two sets of amplitude registers instead of
-    // copying the results back after every gate (measured 12-14% faster
-    // passes).  Reverse passes hold two states; a second set would not fit
-    // the registers of two resident blocks.
-    if (REV) {
+    // Two gates per iteration: the register allocator then alternates
+    // between two sets of amplitude registers instead of copying the results
+    // back after every gate (forward passes 12-14% faster, reverse passes of
+    // the single-state kernel 3-4%).  PAIR2 = false keeps one gate per
+    // iteration for reverse passes where registers are short (the batched
+    // kernel would spill).
+    if (REV && !PAIR2) {
         for (int k = 0; k < nop; ++k)
             one(k);
     } else {
@@ -415,7 +416,7 @@ __device__ __forceinline__ void exec_step(const LOp<R>* ops, int o0, int nop, in
 // 2^mb >= APT); extra threads only take part in the barriers.  `ops` and
 // `steps` point to the pass's first gate and step (LDS or global memory);
 // reverse passes add each rotation's sum to pacc[slot] (LDS).
-template <typename R, bool REV, int APT>
+template <typename R, bool REV, int APT, bool PAIR2 = false>
 __device__ __forceinline__ void exec_tile(const LOp<R>* ops, const DStep* steps, int nsteps, int mb,
                                           R* phi, R* lam, ExecShared& sh, double* pacc, int& parity)
 {
@@ -429,7 +430,7 @@ __device__ __forceinline__ void exec_tile(const LOp<R>* ops, const DStep* steps,
         const int q0 = (w0 >> 8) & 0xff, q1 = (w0 >> 16) & 0xff, q2 = w0 >> 24;
         const int o0 = (int16_t)(w1 & 0xffff);
         const int nop = (int16_t)(w1 >> 16) - o0;
-        exec_step<R, REV, APT>(ops, o0, nop, q0, q1, q2, mb, phi, lam, sh, parity);
+        exec_step<R, REV, APT, PAIR2>(ops, o0, nop, q0, q1, q2, mb, phi, lam, sh, parity);
         __syncthreads();
         if (REV) {
             const int kk = threadIdx.x;
