@@ -136,8 +136,10 @@ qsv_status configure(qsv_batch_plan* P, int m, int threads, int split)
     return QSV_OK;
 }
 
+// with_large = false leaves out the large tier (the autotuner times the
+// persistent kernel's shapes on their own).
 qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* energies,
-                   double* grads, hipStream_t s)
+                   double* grads, hipStream_t s, bool with_large = true)
 {
     BatchArgs a{};
     a.inst = static_cast<const BInst*>(P->dev.at(P->o_inst));
@@ -161,7 +163,7 @@ qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* 
     // meanwhile.
     std::vector<int> large;
     for (int i : P->order)
-        if (P->inst[i].n >= P->split && P->sub[i])
+        if (with_large && P->inst[i].n >= P->split && P->sub[i])
             large.push_back(i);
     const int ns = std::min((int)P->side.size(), (int)large.size());
     hipError_t e = hipSuccess;
@@ -437,16 +439,18 @@ qsv_status qsv_batch_tune(qsv_batch_plan* plan, const double* params_dev, void* 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(QSV_ERR_HIP, "event creation failed");
-    // time one configuration: a warm-up run, then the mean of two
-    auto measure = [&](int m, int t, int split, double* ms) -> bool {
+    // time one configuration: a warm-up run, then the mean of two (the
+    // large tier left out while tile shapes are compared: it does not depend
+    // on them, and its time would only add noise)
+    auto measure = [&](int m, int t, int split, bool with_large, double* ms) -> bool {
         hipStreamSynchronize(s);
         if (configure(plan, m, t, split) != QSV_OK)
             return false;
-        if (enqueue(plan, params_dev, work, energies_dev, grads_dev, s) != QSV_OK)
+        if (enqueue(plan, params_dev, work, energies_dev, grads_dev, s, with_large) != QSV_OK)
             return false;
         hipEventRecord(e0, s);
         for (int r = 0; r < 2; ++r)
-            if (enqueue(plan, params_dev, work, energies_dev, grads_dev, s) != QSV_OK)
+            if (enqueue(plan, params_dev, work, energies_dev, grads_dev, s, with_large) != QSV_OK)
                 return false;
         hipEventRecord(e1, s);
         hipEventSynchronize(e1);
@@ -457,18 +461,20 @@ qsv_status qsv_batch_tune(qsv_batch_plan* plan, const double* params_dev, void* 
     };
     double best = 1e300;
     int bm = plan->m, bt = plan->threads, bs = plan->split;
-    // 1) tile shape at the current split, 2) split at the best shape
+    // 1) tile shape at the current split (persistent kernel alone), 2) split
+    // at the best shape (whole batch)
     for (auto c : candidates(plan->dt)) {
         double ms;
-        if (measure(c.first, c.second, bs, &ms) && ms < best) {
+        if (measure(c.first, c.second, bs, false, &ms) && ms < best) {
             best = ms;
             bm = c.first;
             bt = c.second;
         }
     }
+    best = 1e300;
     for (int sp : split_candidates()) {
         double ms;
-        if (sp != bs && measure(bm, bt, sp, &ms) && ms < best) {
+        if (measure(bm, bt, sp, true, &ms) && ms < best) {
             best = ms;
             bs = sp;
         }

@@ -36,23 +36,33 @@ struct TV<double> {
     static constexpr int APV = 1;
 };
 
-// Threads per block: 8 amplitudes each over a full tile (2^12 complex64 or
-// 2^11 complex128 amplitudes).
+// Threads per block NT: 8 amplitudes each, so a block holds a tile of
+// 8 NT amplitudes (NT = 512, 256, 128 for complex64 tiles of 12, 11, 10
+// qubits; 256, 128 for complex128 tiles of 11, 10).  Smaller tiles serve
+// states too small to give every CU a tile of the full size.
 template <typename R>
-constexpr int tpass_threads()
+constexpr int tpass_max_threads()
 {
     return sizeof(R) == 4 ? 512 : 256;
 }
 
-// 16-byte vectors per thread per state (a tile is 2048 vectors).
+int tpass_threads_for(int dt, int m)
+{
+    const int hi = dt == C64 ? 512 : 256;
+    const int nt = m >= 3 ? (1 << (m - 3)) : 1;
+    return nt >= hi ? hi : (nt <= 128 ? 128 : nt);
+}
+
+// 16-byte vectors per thread per state: 8 amplitudes.
 template <typename R>
 constexpr int tpass_vpt()
 {
-    return 2048 / tpass_threads<R>();
+    return sizeof(R) == 4 ? 4 : 8;
 }
 
-// Waves per SIMD to keep two blocks resident (both tiles of a complex64
-// reverse pass fit twice in LDS); 1 = no constraint.
+// Waves per SIMD to keep the resident blocks' waves within the register
+// file: complex64 reverse passes fit two full-size tiles (or more smaller
+// ones) in LDS, i.e. 16 waves per CU; 1 = no constraint.
 template <typename R, bool REV>
 constexpr int tpass_wpe()
 {
@@ -70,16 +80,15 @@ __global__ void __launch_bounds__(256) k_tstage(const DOp* __restrict__ ops, int
         out[i] = tx::make_lop<R>(ops[i < nops ? i : i - nops], mats, params, i >= nops);
 }
 
-template <typename R, bool REV>
-__global__ void __launch_bounds__(tpass_threads<R>())
-    __attribute__((amdgpu_waves_per_eu(tpass_wpe<R, REV>())))
+template <typename R, bool REV, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(tpass_wpe<R, REV>())))
     k_tpass(R* __restrict__ psi, R* __restrict__ lam, const LOp<R>* __restrict__ ops,
             const DStep* __restrict__ steps, const TPassArgs a)
 {
     using V = typename TV<R>::V;
     constexpr int APV = TV<R>::APV;
     constexpr int NS = REV ? 2 : 1;  // states moved per tile
-    constexpr int kTpassThreads = tpass_threads<R>();
+    constexpr int kTpassThreads = NT;
     constexpr int kVPT = tpass_vpt<R>();
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ ExecShared sh;
@@ -169,18 +178,39 @@ __global__ void __launch_bounds__(tpass_threads<R>())
 }
 
 template <typename R, bool REV>
+const void* tpass_fn(int nt)
+{
+    if (nt == 512)
+        return reinterpret_cast<const void*>(k_tpass<R, REV, (sizeof(R) == 4 ? 512 : 256)>);
+    if (nt == 256)
+        return reinterpret_cast<const void*>(k_tpass<R, REV, 256>);
+    return reinterpret_cast<const void*>(k_tpass<R, REV, 128>);
+}
+
+template <typename R, bool REV, int NT>
+hipError_t go_nt(const TPassArgs& a, void* psi, void* lam, int blocks, size_t lds, hipStream_t s)
+{
+    const LOp<R>* ops = static_cast<const LOp<R>*>(a.lops) + (REV ? a.nops_total : 0) + a.pass.op_off;
+    hipLaunchKernelGGL((k_tpass<R, REV, NT>), dim3(blocks), dim3(NT), lds, s, static_cast<R*>(psi),
+                       static_cast<R*>(lam ? lam : psi), ops, a.steps + a.pass.step_off, a);
+    return hipGetLastError();
+}
+
+template <typename R, bool REV>
 hipError_t go(const TPassArgs& a, void* psi, void* lam, int blocks, hipStream_t s)
 {
-    const size_t lds = tpass_lds_bytes(sizeof(R) == 4 ? C64 : C128, a.m, REV);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_tpass<R, REV>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int dt = sizeof(R) == 4 ? C64 : C128;
+    const size_t lds = tpass_lds_bytes(dt, a.m, REV);
+    const int nt = tpass_threads_for(dt, a.m);
+    hipError_t e = hipFuncSetAttribute(tpass_fn<R, REV>(nt), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
     if (e != hipSuccess)
         return e;
-    const LOp<R>* ops = static_cast<const LOp<R>*>(a.lops) + (REV ? a.nops_total : 0) + a.pass.op_off;
-    hipLaunchKernelGGL((k_tpass<R, REV>), dim3(blocks), dim3(tpass_threads<R>()), lds, s,
-                       static_cast<R*>(psi), static_cast<R*>(lam ? lam : psi), ops,
-                       a.steps + a.pass.step_off, a);
-    return hipGetLastError();
+    if (nt == tpass_max_threads<R>())
+        return go_nt<R, REV, tpass_max_threads<R>()>(a, psi, lam, blocks, lds, s);
+    if (nt == 256)
+        return go_nt<R, REV, 256>(a, psi, lam, blocks, lds, s);
+    return go_nt<R, REV, 128>(a, psi, lam, blocks, lds, s);
 }
 
 }  // namespace
@@ -221,13 +251,11 @@ int tpass_resident_blocks(int dt, int m, bool rev)
     const size_t lds = tpass_lds_bytes(dt, m, rev);
     if (lds + sizeof(ExecShared) > (size_t)maxlds)
         return 0;
-    const void* fn = dt == C64 ? (rev ? reinterpret_cast<const void*>(k_tpass<float, true>)
-                                      : reinterpret_cast<const void*>(k_tpass<float, false>))
-                               : (rev ? reinterpret_cast<const void*>(k_tpass<double, true>)
-                                      : reinterpret_cast<const void*>(k_tpass<double, false>));
+    const int threads = tpass_threads_for(dt, m);
+    const void* fn = dt == C64 ? (rev ? tpass_fn<float, true>(threads) : tpass_fn<float, false>(threads))
+                               : (rev ? tpass_fn<double, true>(threads) : tpass_fn<double, false>(threads));
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
-    const int threads = dt == C64 ? tpass_threads<float>() : tpass_threads<double>();
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, lds) != hipSuccess)
         return 0;
     return per * cus;

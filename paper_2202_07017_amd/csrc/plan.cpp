@@ -515,7 +515,18 @@ qsv_status qsv_adjoint_plan_create(const qsv_circuit* circ, const qsv_pauli_sum*
             }
             gates.push_back(g);
         }
+        // Full-size tiles (2^12 complex64, 2^11 complex128 amplitudes), down
+        // to 2^10 while the state would give fewer tiles than there are CUs
+        // (small states: more, smaller blocks spread the steps over the
+        // whole GPU).
         P->tm = std::min(n, dt == QSV_C64 ? 12 : 11);
+        {
+            int dev = 0, cus = 256;
+            if (hipGetDevice(&dev) == hipSuccess)
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            while (P->tm > 10 && (1ll << (n - P->tm)) < (long long)cus)
+                --P->tm;
+        }
         compile_tile_program(gates, n, P->tm, kMaxTpassOps, P->tp);
         const int res = tpass_resident_blocks(dt, P->tm, true);
         if (res <= 0)
