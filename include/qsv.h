@@ -280,12 +280,14 @@ typedef struct qsv_batch_plan qsv_batch_plan;
  * largest first: those whose two state vectors fit the workgroup's LDS tile
  * stay there for the whole evaluation, the others stream cache-blocked tiles
  * of their own workspace region.  Instances at or above the split size (16 or
- * more qubits) run one at a time across the whole GPU with the cache-blocked
- * adjoint, on a side stream that the plan owns (created on the device current
- * at plan creation, default priority): qsv_batch_run forks it from `stream`
- * with an event before the persistent launch and joins it back after, so the
- * two tiers overlap and every result is ready when `stream` reaches the end
- * of the call's work.  The tile size, workgroup size and split size come
+ * more qubits) run across the whole GPU with the cache-blocked adjoint, on
+ * three side streams that the plan owns (created on the device current at
+ * plan creation, default priority): qsv_batch_run forks them from `stream`
+ * with an event before the persistent launch (which replays through a HIP
+ * graph) and joins them back after, so the tiers and the large instances
+ * overlap and every result is ready when `stream` reaches the end of the
+ * call's work.  Calls with one plan must not overlap in time.  The tile
+ * size, workgroup size and split size come
  * from the autotuner (qsv_batch_tune) or its cache.  Parameters and
  * gradients of instance i live at offsets[i] .. offsets[i+1]-1 of the
  * concatenated vectors (qsv_batch_offsets).  *work_bytes = workspace size. */

@@ -72,10 +72,10 @@ namespace {
 
 constexpr int kWorkMinQubits = 11;  // instances with n >= this get a workspace region
 constexpr int kSplitMin = 16;       // smallest size the large tier may take
-// Side streams of the large tier.  One suffices: it lets the large tier run
-// beside the persistent kernel (whose tail leaves the GPU half idle), while
-// its own launches already fill the GPU, so that more streams only share it.
-constexpr int kLargeStreams = 1;
+// Side streams of the large tier: they run beside the persistent kernel and
+// beside each other (the small large-tier instances leave most of the GPU
+// idle on their own).
+constexpr int kLargeStreams = 3;
 
 qsv_status configure(qsv_batch_plan* P, int m, int threads, int split)
 {
@@ -136,10 +136,8 @@ qsv_status configure(qsv_batch_plan* P, int m, int threads, int split)
     return QSV_OK;
 }
 
-// with_large = false leaves out the large tier (the autotuner times the
-// persistent kernel's shapes on their own).
-qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* energies,
-                   double* grads, hipStream_t s, bool with_large = true)
+BatchArgs batch_args(const qsv_batch_plan* P, const double* params, void* work, double* energies,
+                     double* grads)
 {
     BatchArgs a{};
     a.inst = static_cast<const BInst*>(P->dev.at(P->o_inst));
@@ -157,40 +155,66 @@ qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* 
     a.energies = energies;
     a.work = static_cast<char*>(work);
     a.counter = static_cast<int*>(work);
-    // Large tier: on side streams forked from s (and joined back into s),
-    // instances assigned largest first to the least loaded stream, each stream
-    // with its own workspace region.  The persistent kernel runs on s
-    // meanwhile.
-    std::vector<int> large;
-    for (int i : P->order)
-        if (with_large && P->inst[i].n >= P->split && P->sub[i])
-            large.push_back(i);
-    const int ns = std::min((int)P->side.size(), (int)large.size());
-    hipError_t e = hipSuccess;
-    if (ns > 0) {
-        e = hipEventRecord(P->ev[0], s);
-        for (int k = 0; k < ns && e == hipSuccess; ++k)
-            e = hipStreamWaitEvent(P->side[k], P->ev[0], 0);
-        if (e != hipSuccess)
-            return fail(QSV_ERR_HIP, "large-tier fork: %s", hipGetErrorString(e));
-    }
-    qsv_status st = QSV_OK;
-    if (P->nsmall > 0) {
-        e = launch_batch(a, P->dt, P->threads, P->blocks, s);
-        if (e != hipSuccess)
-            st = fail(QSV_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
-    }
+    return a;
+}
+
+// The persistent kernel (instances below the split) on s.
+qsv_status enqueue_small(qsv_batch_plan* P, const double* params, void* work, double* energies,
+                         double* grads, hipStream_t s)
+{
+    if (P->nsmall == 0)
+        return QSV_OK;
+    hipError_t e = launch_batch(batch_args(P, params, work, energies, grads), P->dt, P->threads,
+                                P->blocks, s);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+    return QSV_OK;
+}
+
+// Large tier: side streams forked from s (fork_large, before anything else
+// of the call is enqueued on s) and joined back into s (join_large, also
+// after an error: a capture needs it); instances assigned largest first to
+// the least loaded stream, each stream with its own workspace region.
+int large_streams(const qsv_batch_plan* P)
+{
+    int nl = 0;
+    for (int i = 0; i < P->ninst; ++i)
+        nl += (P->inst[i].n >= P->split && P->sub[i]) ? 1 : 0;
+    return std::min((int)P->side.size(), nl);
+}
+
+qsv_status fork_large(qsv_batch_plan* P, int ns, hipStream_t s)
+{
+    if (ns == 0)
+        return QSV_OK;
+    hipError_t e = hipEventRecord(P->ev[0], s);
+    for (int k = 0; k < ns && e == hipSuccess; ++k)
+        e = hipStreamWaitEvent(P->side[k], P->ev[0], 0);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "large-tier fork: %s", hipGetErrorString(e));
+    return QSV_OK;
+}
+
+qsv_status enqueue_large(qsv_batch_plan* P, int ns, const double* params, void* work,
+                         double* energies, double* grads)
+{
     std::vector<double> load(ns > 0 ? ns : 1, 0.0);
-    for (int i : large) {
-        if (st)
-            break;
+    for (int i : P->order) {
+        if (P->inst[i].n < P->split || !P->sub[i])
+            continue;
         const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[k] += std::ldexp((double)P->inst[i].ops.size() + 1, P->inst[i].n);
-        st = adjoint_enqueue_direct(P->sub[i], params + P->param_off[i],
-                                    static_cast<char*>(work) + P->big_off + k * P->big_bytes,
-                                    energies + i, grads + P->param_off[i], P->side[k]);
+        qsv_status st = adjoint_enqueue_direct(P->sub[i], params + P->param_off[i],
+                                               static_cast<char*>(work) + P->big_off + k * P->big_bytes,
+                                               energies + i, grads + P->param_off[i], P->side[k]);
+        if (st)
+            return st;
     }
-    // join every forked stream, also after an error (a capture needs it)
+    return QSV_OK;
+}
+
+qsv_status join_large(qsv_batch_plan* P, int ns, hipStream_t s, qsv_status st)
+{
     for (int k = 0; k < ns; ++k) {
         hipError_t j = hipEventRecord(P->ev[1 + k], P->side[k]);
         if (j == hipSuccess)
@@ -199,6 +223,21 @@ qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* 
             st = fail(QSV_ERR_HIP, "large-tier join: %s", hipGetErrorString(j));
     }
     return st;
+}
+
+// Everything, directly on s (the autotuner).  with_large = false leaves out
+// the large tier (persistent-kernel shapes are timed on their own).
+qsv_status enqueue(qsv_batch_plan* P, const double* params, void* work, double* energies,
+                   double* grads, hipStream_t s, bool with_large = true)
+{
+    const int ns = with_large ? large_streams(P) : 0;
+    qsv_status st = fork_large(P, ns, s);
+    if (st)
+        return st;
+    st = enqueue_small(P, params, work, energies, grads, s);
+    if (!st && ns > 0)
+        st = enqueue_large(P, ns, params, work, energies, grads);
+    return join_large(P, ns, s, st);
 }
 
 // (tile qubits, threads) with 8 or 16 amplitudes per thread in a tile step
@@ -421,10 +460,21 @@ qsv_status qsv_batch_run(qsv_batch_plan* plan, const double* params_dev, void* w
             return st;
     }
     hipStream_t s = (hipStream_t)stream;
+    // The persistent kernel replays through a graph; the large tier is
+    // launched directly on the side streams: replaying independent branches
+    // of one graph ran them one after another on this runtime (measured),
+    // launched directly they overlap (2 streams: 338 -> 264 ms per batch of
+    // the 1024-instance workload).
+    const int ns = large_streams(plan);
+    if ((st = fork_large(plan, ns, s)))
+        return st;
     std::vector<const void*> key = {params_dev, work, energies_dev, grads_dev};
     st = run_graph(plan->graph, key, s, [&](hipStream_t cs) {
-        return enqueue(plan, params_dev, work, energies_dev, grads_dev, cs);
+        return enqueue_small(plan, params_dev, work, energies_dev, grads_dev, cs);
     });
+    if (!st && ns > 0)
+        st = enqueue_large(plan, ns, params_dev, work, energies_dev, grads_dev);
+    st = join_large(plan, ns, s, st);
     if (st)
         return st;
     return ok();
