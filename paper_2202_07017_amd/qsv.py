@@ -159,6 +159,27 @@ def _mat(G):
     return G, G.view(np.float64).ctypes.data_as(_D)
 
 
+# ------------------------------------------------------------ qubit order
+#
+# The C ABI numbers qubit j as index bit j (weight 2^j).  order="big" accepts
+# the opposite convention (qubit 0 = most significant bit, as in Qibo's own
+# software): qubit q of an n-qubit state is passed on as n - 1 - q, masks and
+# basis indices are bit-reversed over n bits.  Marshalling only.
+
+def _order_ok(order):
+    if order not in ("little", "big"):
+        raise ValueError("order must be 'little' or 'big', not %r" % (order,))
+
+
+def map_qubits(qubits, n: int, order: str = "little"):
+    _order_ok(order)
+    return [int(q) for q in qubits] if order == "little" else [n - 1 - int(q) for q in qubits]
+
+
+def reverse_bits(v: int, n: int) -> int:
+    return int("{:0{w}b}".format(int(v), w=n)[::-1], 2) if n > 0 else 0
+
+
 # ---------------------------------------------------------------- states
 
 def state_empty(n: int, dtype, device="cuda"):
@@ -182,8 +203,11 @@ def reduce_workspace(device):
     return w
 
 
-def qsv_init_basis(psi, index: int = 0, stream=None):
-    _check(lib().qsv_init_basis(_ptr(psi), _nqubits(psi), dtype_code(psi), index, _stream(stream)))
+def qsv_init_basis(psi, index: int = 0, stream=None, order="little"):
+    _order_ok(order)
+    n = _nqubits(psi)
+    idx = index if order == "little" else reverse_bits(index, n)
+    _check(lib().qsv_init_basis(_ptr(psi), n, dtype_code(psi), idx, _stream(stream)))
 
 
 def qsv_init_random(psi, seed: int, stream=None):
@@ -192,22 +216,25 @@ def qsv_init_random(psi, seed: int, stream=None):
                                  _stream(stream)))
 
 
-def qsv_apply_gate(psi, targets: Sequence[int], controls: Sequence[int], G, stream=None):
-    t, c = _ints(targets), _ints(controls)
+def qsv_apply_gate(psi, targets: Sequence[int], controls: Sequence[int], G, stream=None,
+                   order="little"):
+    n = _nqubits(psi)
+    t, c = _ints(map_qubits(targets, n, order)), _ints(map_qubits(controls, n, order))
     _G, gp = _mat(G)
     _check(lib().qsv_apply_gate(_ptr(psi), _nqubits(psi), dtype_code(psi), t, len(targets), c,
                                 len(controls), gp, _stream(stream)))
 
 
-def qsv_apply_fused(psi, blocks, stream=None):
+def qsv_apply_fused(psi, blocks, stream=None, order="little"):
     """blocks: sequence of (targets, matrix)."""
+    n = _nqubits(psi)
     arr = (qsv_block * max(len(blocks), 1))()
     keep = []
     for j, (targets, M) in enumerate(blocks):
         Mc, mp = _mat(M)
         keep.append(Mc)
         arr[j].k = len(targets)
-        for i, q in enumerate(targets):
+        for i, q in enumerate(map_qubits(targets, n, order)):
             arr[j].targets[i] = q
         arr[j].M = mp
     _check(lib().qsv_apply_fused(_ptr(psi), _nqubits(psi), dtype_code(psi), arr, len(blocks),
@@ -217,9 +244,14 @@ def qsv_apply_fused(psi, blocks, stream=None):
 class PauliSum:
     """ctypes view of a Pauli sum (x_mask, z_mask, coeff arrays kept alive)."""
 
-    def __init__(self, H):
-        self.x = np.ascontiguousarray(H.x_mask, dtype=np.uint64)
-        self.z = np.ascontiguousarray(H.z_mask, dtype=np.uint64)
+    def __init__(self, H, order="little"):
+        _order_ok(order)
+        x, z = H.x_mask, H.z_mask
+        if order == "big":
+            x = [reverse_bits(v, H.n) for v in x]
+            z = [reverse_bits(v, H.n) for v in z]
+        self.x = np.ascontiguousarray(x, dtype=np.uint64)
+        self.z = np.ascontiguousarray(z, dtype=np.uint64)
         self.c = np.ascontiguousarray(H.coeff, dtype=np.float64)
         self.s = qsv_pauli_sum(len(self.c), self.x.ctypes.data_as(_U), self.z.ctypes.data_as(_U),
                                self.c.ctypes.data_as(_D))
@@ -262,17 +294,17 @@ class CircuitC:
     """ctypes form of a circuit (any object with n, ops, nparams whose ops
     have kind, targets, controls, param, matrix)."""
 
-    def __init__(self, circ):
+    def __init__(self, circ, order="little"):
         self.mats = []
         ops = (qsv_op * max(len(circ.ops), 1))()
         for j, op in enumerate(circ.ops):
             o = ops[j]
             o.kind = KIND[op.kind]
             o.k = len(op.targets)
-            for i, q in enumerate(op.targets):
+            for i, q in enumerate(map_qubits(op.targets, circ.n, order)):
                 o.targets[i] = q
             o.c = len(op.controls)
-            for i, q in enumerate(op.controls):
+            for i, q in enumerate(map_qubits(op.controls, circ.n, order)):
                 o.controls[i] = q
             o.param = op.param
             if op.kind == "matrix":
@@ -288,8 +320,8 @@ class CircuitC:
 class Plan:
     """qsv_plan: fused launch list, replayed through a HIP graph."""
 
-    def __init__(self, circ, dtype_code_: int, fuse_k: int = 5, params_host=None):
-        self.c = circ if isinstance(circ, CircuitC) else CircuitC(circ)
+    def __init__(self, circ, dtype_code_: int, fuse_k: int = 5, params_host=None, order="little"):
+        self.c = circ if isinstance(circ, CircuitC) else CircuitC(circ, order)
         self.h = _vp()
         ph = None
         if params_host is not None:
@@ -316,10 +348,10 @@ class Plan:
 class AdjointPlan:
     """qsv_adjoint_plan with its device workspace (a torch tensor)."""
 
-    def __init__(self, circ, H, dtype_code_: int, fuse_k: int = 5, device="cuda"):
+    def __init__(self, circ, H, dtype_code_: int, fuse_k: int = 5, device="cuda", order="little"):
         import torch
-        self.c = circ if isinstance(circ, CircuitC) else CircuitC(circ)
-        self.H = H if isinstance(H, PauliSum) else PauliSum(H)
+        self.c = circ if isinstance(circ, CircuitC) else CircuitC(circ, order)
+        self.H = H if isinstance(H, PauliSum) else PauliSum(H, order)
         self.h = _vp()
         wb = ctypes.c_size_t()
         _check(lib().qsv_adjoint_plan_create(ctypes.byref(self.c.s), ctypes.byref(self.H.s),
@@ -396,10 +428,10 @@ class BatchPlan:
     device workspace (a torch tensor).  Parameters and gradients of instance i
     are params[offsets[i]:offsets[i+1]] of the concatenated vectors."""
 
-    def __init__(self, instances, dtype_code_: int, device="cuda"):
+    def __init__(self, instances, dtype_code_: int, device="cuda", order="little"):
         import torch
-        self.cs = [CircuitC(inst.circuit) for inst in instances]
-        self.Hs = [PauliSum(inst.hamiltonian) for inst in instances]
+        self.cs = [CircuitC(inst.circuit, order) for inst in instances]
+        self.Hs = [PauliSum(inst.hamiltonian, order) for inst in instances]
         ca = (qsv_circuit * len(self.cs))(*[c.s for c in self.cs])
         ha = (qsv_pauli_sum * len(self.Hs))(*[h.s for h in self.Hs])
         self._ca, self._ha = ca, ha
