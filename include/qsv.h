@@ -43,6 +43,16 @@
  *    the call.  Plans belong to the caller and are released with *_destroy.
  *  - Calls on different streams may run concurrently as long as they do not
  *    share buffers.  Library-internal caches are guarded by a mutex.
+ *
+ * Environment switches (read when a plan is created or a gate is launched;
+ * results are the same with any setting, only the kernels differ):
+ *    QSV_TUNE_CACHE=<file>      batch autotuner cache (JSON)
+ *    QSV_BATCH_SHAPE=m,t[,s]    batch tile qubits, threads, split (skips the cache)
+ *    QSV_NO_GRAPH=1             plans enqueue their launches instead of replaying a graph
+ *    QSV_NO_MFMA=1              4- and 5-qubit blocks on the vector units
+ *    QSV_NO_TILES=1             per-gate adjoint instead of cache-blocked tile programs
+ *    QSV_NO_LANE_SWEEP=1        no cross-lane exchange for low single-qubit targets
+ *    QSV_SWEEP_NT=0|1           force the nontemporal hint of sweeps off or on
  */
 #ifndef QSV_H
 #define QSV_H
