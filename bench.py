@@ -294,14 +294,37 @@ def configs_leg(qsv, W, torch, np, dev, stream):
     (graph replay, state resident): n = 20 complex128 U(2) + CZ layers
     (depth 10); n = 28 random pairs (depth 20) unfused and fused to
     k = 2..5 in complex64 and complex128; n = 32 random 1-3-qubit unitaries
-    (depth 12) fused to k = 5 in complex64 and complex128.  GB/s counts the
-    plan's algorithmic bytes, TFLOP/s its algorithmic flops."""
+    (depth 12) fused to k = 5 in complex64 and complex128; and at n = 32 the
+    single-gate GB/s at every target plus k = 2, 3 gates on low, spread and
+    high targets.  GB/s counts algorithmic bytes, TFLOP/s algorithmic flops."""
     cases = [("n20_u2cz_depth10", W.random_u2_cz(n=20, depth=10, seed=1000), None, ["c128"], [1, 5])]
     c2, p2 = W.random_u2_pairs(n=28, depth=20, seed=1001)
     cases.append(("n28_pairs_depth20", c2, p2, ["c64", "c128"], [1, 2, 3, 4, 5]))
     cases.append(("n32_dense123_depth12", W.random_dense_123(n=32, depth=12, seed=1002), None,
                   ["c64", "c128"], [5]))
     out = {}
+    # per-gate GB/s by target position at n = 32: k = 1 at every target, and
+    # k = 2, 3 Haar gates on low, spread and high target sets
+    rng = np.random.default_rng(1006)
+    sets = [(0, 1), (0, 31), (30, 31), (0, 1, 2), (0, 16, 31), (29, 30, 31)]
+    for dt, S in (("c64", 8), ("c128", 16)):
+        psi = torch.empty(1 << 32, dtype=torch.complex64 if dt == "c64" else torch.complex128,
+                          device=dev)
+        qsv.qsv_init_random(psi, 9)
+        row = []
+        for t in range(32):
+            G = W.haar_unitary(rng, 2)
+            tt = event_time(lambda: qsv.qsv_apply_gate(psi, (t,), (), G), 3, stream)
+            row.append(round(2.0 * S * (1 << 32) / tt / 1e9, 1))
+        multi = {}
+        for ts in sets:
+            G = W.haar_unitary(rng, 1 << len(ts))
+            tt = event_time(lambda: qsv.qsv_apply_gate(psi, ts, (), G), 3, stream)
+            multi[",".join(map(str, ts))] = round(2.0 * S * (1 << 32) / tt / 1e9, 1)
+        out["n32_per_target_gbs_%s" % dt] = row
+        out["n32_k23_gbs_%s" % dt] = multi
+        del psi
+        torch.cuda.empty_cache()
     for name, circ, params, dts, fuses in cases:
         for dt in dts:
             tdt = torch.complex64 if dt == "c64" else torch.complex128
