@@ -576,13 +576,17 @@ __global__ void __launch_bounds__(kBlock) k_rand_fill(R* __restrict__ psi, uint6
 
 // ------------------------------------------------------------- launching
 
+// Blocks for `items` work items: one item per thread (sweeps are fastest
+// without grid-stride loops), up to 2^23 - 1 blocks (a grid of < 2^31 work
+// items, so a 32-qubit complex64 sweep still takes one item per thread);
+// larger jobs loop.
 inline unsigned grid_for(uint64_t items, int per_thread)
 {
     uint64_t b = (items + (uint64_t)kBlock * per_thread - 1) / ((uint64_t)kBlock * per_thread);
     if (b < 1)
         b = 1;
-    if (b > (1u << 22))
-        b = 1u << 22;
+    if (b > (1u << 23) - 1)
+        b = (1u << 23) - 1;
     return (unsigned)b;
 }
 
