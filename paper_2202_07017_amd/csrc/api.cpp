@@ -267,10 +267,57 @@ Built build_launch(int n, int dt, const int* ct, int k, const int* ctl, int c, c
         return b;
     }
     // dense
+    const char* nomfma = getenv("QSV_NO_MFMA");
+    // An uncontrolled dense 2- or 3-qubit gate with a target among the three
+    // lowest bits of the 16-byte unit index (complex128: qubits 0-2;
+    // complex64, two amplitudes to a unit: qubits 1-3) gives each lane a
+    // group of 2-8 contiguous units, so one load instruction of a wave
+    // spreads over up to 8 times the bytes it uses.  Such a gate runs as the
+    // 4-qubit block G (x) I (the added qubits the lowest free ones) on the
+    // matrix cores, whose tiles are contiguous runs of >= 2 KiB: measured at
+    // n = 30 and 32 it is never slower and up to 1.6 times faster (e.g.
+    // complex128 (0,1,2) 3.95 -> 5.9 TB/s, complex64 (1,2,3) 3.8 -> 6.0).
+    if (allow_mfma && c == 0 && (k == 2 || k == 3) && n >= 10 && !(nomfma && nomfma[0] == '1')) {
+        const int lo = dt == QSV_C64 ? 1 : 0;
+        bool low = false;
+        for (int j = 0; j < k; ++j)
+            low |= ct[j] >= lo && ct[j] < lo + 3;
+        if (low) {
+            int ct4[4];
+            std::vector<int> all(ct, ct + k);
+            for (int q = 0; (int)all.size() < 4; ++q)
+                if (std::find(all.begin(), all.end(), q) == all.end())
+                    all.push_back(q);
+            std::sort(all.begin(), all.end());
+            std::copy(all.begin(), all.end(), ct4);
+            int idx[3];  // canonical tau bit of original target j inside ct4
+            for (int j = 0; j < k; ++j)
+                idx[j] = (int)(std::find(all.begin(), all.end(), ct[j]) - all.begin());
+            int extra = 0;  // tau bits of the added qubits
+            for (int j = 0; j < 4; ++j)
+                if (std::find(ct, ct + k, ct4[j]) == ct + k)
+                    extra |= 1 << j;
+            auto orig = [&](int t4) {
+                int t = 0;
+                for (int j = 0; j < k; ++j)
+                    t |= ((t4 >> idx[j]) & 1) << j;
+                return t;
+            };
+            std::vector<double> G4((size_t)2 * 16 * 16, 0.0);
+            for (int r = 0; r < 16; ++r)
+                for (int col = 0; col < 16; ++col)
+                    if ((r & extra) == (col & extra)) {
+                        G4[((size_t)r * 16 + col) * 2] = G(orig(r), orig(col), 0);
+                        G4[((size_t)r * 16 + col) * 2 + 1] = G(orig(r), orig(col), 1);
+                    }
+            Built b4 = build_launch(n, dt, ct4, 4, ctl, 0, G4.data(), true);
+            b4.L.flops = 8.0 * D * std::ldexp(1.0, n);
+            return b4;
+        }
+    }
     L.K = k;
     L.flops = 8.0 * D * std::ldexp(1.0, n - c);
     L.bytes = 2.0 * S * std::ldexp(1.0, n - c);
-    const char* nomfma = getenv("QSV_NO_MFMA");
     if (allow_mfma && c == 0 && k >= 4 && n >= k + 6 && !(nomfma && nomfma[0] == '1')) {
         L.type = L_MFMA;
         std::vector<int> B = tgt;

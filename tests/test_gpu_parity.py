@@ -179,6 +179,27 @@ def test_four_and_five_qubit_gates(q, orc, n):
     os.environ.pop("QSV_NO_MFMA", None)
 
 
+@pytest.mark.parametrize("n", [10, 13])
+def test_low_dense_gates_as_four_qubit_blocks(q, orc, n):
+    """Dense 2- and 3-qubit gates with a target on the three lowest bits of
+    the 16-byte unit index (complex128: qubits 0-2; complex64: qubits 1-3)
+    run as G (x) I on the matrix cores; every target order, beside the
+    vector-unit path, and sets that stay on the vector units."""
+    rng = np.random.default_rng(250 + n)
+    sets = [(0, 1), (0, n - 1), (1, 2), (3, 4), (2, n - 1), (4, 5), (0, 1, 2), (1, 2, n - 1),
+            (0, 5, n - 1), (0, 2, 3), (2, 1, 4), (3, 6, 8)]
+    for name in DTYPES:
+        psi = rand_state(n, rng, name)
+        for base in sets:
+            for t in itertools.permutations(base):
+                G = W.haar_unitary(rng, 2 ** len(t))
+                for mfma in ["1", "0"]:
+                    os.environ["QSV_NO_MFMA"] = "0" if mfma == "1" else "1"
+                    say("low dense", name, n, t, "mfma" if mfma == "1" else "valu")
+                    gate_case(q, orc, psi, name, t, (), G)
+    os.environ.pop("QSV_NO_MFMA", None)
+
+
 def test_apply_fused(q, orc):
     rng = np.random.default_rng(8)
     for name in DTYPES:
