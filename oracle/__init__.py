@@ -64,6 +64,8 @@ def lib():
             L.orc_grad.argtypes = circ + [_D, ctypes.c_int, ctypes.c_int, _U, _U, _D, _I,
                                           ctypes.c_int, ctypes.c_int, ctypes.c_double, _D]
             L.orc_adjoint.argtypes = circ + [_D, ctypes.c_int, ctypes.c_int, _U, _U, _D, _D, _D]
+            L.orc_probabilities.argtypes = [ctypes.c_int, _D, _I, ctypes.c_int, _D]
+            L.orc_sample.argtypes = [ctypes.c_int, _D, _D, ctypes.c_longlong, _L]
             _lib = L
     return _lib
 
@@ -113,6 +115,29 @@ def norm2(psi) -> float:
     out = np.zeros(1)
     lib().orc_norm2(int(psi.size).bit_length() - 1, _p(psi, _D), _p(out, _D))
     return float(out[0])
+
+
+def probabilities(psi, qubits) -> np.ndarray:
+    """Marginal Born probabilities of `qubits` (first listed = most significant
+    bit of the outcome index), length 2**len(qubits), FP64."""
+    psi = _as_c128(psi)
+    n = int(psi.size).bit_length() - 1
+    q = _ints(list(qubits))
+    out = np.zeros(1 << len(qubits))
+    _check(lib().orc_probabilities(n, _p(psi, _D), _p(q, _I), len(qubits), _p(out, _D)),
+           "probabilities")
+    return out
+
+
+def sample(psi, u) -> np.ndarray:
+    """Whole-register outcomes for the uniforms `u` by inverse-transform
+    sampling of the Born probabilities (int64, one per uniform)."""
+    psi = _as_c128(psi)
+    n = int(psi.size).bit_length() - 1
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(max(u.size, 1), dtype=np.int64)
+    _check(lib().orc_sample(n, _p(psi, _D), _p(u, _D), u.size, _p(out, _L)), "sample")
+    return out[:u.size]
 
 
 def expect(psi, H, per_term: bool = False):

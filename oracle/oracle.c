@@ -666,3 +666,81 @@ int orc_adjoint(int n, int nops, const int* kind, const int* k, const int* tgt, 
     free(mu);
     return rc;
 }
+
+/* ------------------------------------------------------------ measurement */
+
+/* Simulated measurement (Sec. 3: measurements are simulated by sampling from
+ * the state).  Born rule: outcome i has probability |psi_i|^2 (no
+ * normalisation is applied; the state's own norm is the total mass). */
+
+/* Marginal distribution of the qubits q[0..m-1]: out[b] = sum of |psi_i|^2
+ * over every i whose bits at q[0..m-1] spell b, q[0] being the most
+ * significant bit of b (the same order as gate targets).  Plain loop over i in
+ * index order. */
+int orc_probabilities(int n, const double* psi, const int* q, int m, double* out)
+{
+    if (m < 1 || check_qubits(n, q, m, NULL, 0) != 0)
+        return -1;
+    const uint64_t N = 1ULL << n;
+    const uint64_t M = 1ULL << m;
+    for (uint64_t b = 0; b < M; ++b)
+        out[b] = 0.0;
+    for (uint64_t i = 0; i < N; ++i) {
+        const double p = psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];
+        out[tau_of(i, q, m)] += p;
+    }
+    return 0;
+}
+
+/* Inverse-transform sampling of whole-register outcomes.  With the running
+ * sums C_i = sum_{j <= i} |psi_j|^2 (taken in index order) and T = C_{N-1},
+ * shot s maps its uniform u[s] to t = u[s] * T and returns the smallest i
+ * with C_i > t.  If no such i exists (t >= T, which only rounding, u >= 1 or
+ * a NaN can cause) it returns the smallest i with C_i == T, i.e. the last
+ * outcome of nonzero probability (0 for the zero vector).  A negative u counts
+ * as 0.  Outcomes of zero probability are never returned otherwise either:
+ * C_i > t >= C_{i-1} means |psi_i|^2 > 0. */
+int orc_sample(int n, const double* psi, const double* u, int64_t nshots, int64_t* out)
+{
+    if (n < 1 || n > 40 || nshots < 0)
+        return -1;
+    const uint64_t N = 1ULL << n;
+    double* C = (double*)malloc(N * sizeof(double));
+    if (!C)
+        return -2;
+    double run = 0.0;
+    for (uint64_t i = 0; i < N; ++i) {
+        run += psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];
+        C[i] = run;
+    }
+    const double T = C[N - 1];
+    for (int64_t s = 0; s < nshots; ++s) {
+        double t = u[s] * T;
+        if (t < 0.0) /* u < 0 counts as u = 0 */
+            t = 0.0;
+        /* C is nondecreasing, so "the smallest i with C_i > t" is found by
+         * bisection: lo is the answer once the range closes. */
+        uint64_t lo = 0, hi = N;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (C[mid] > t)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        if (lo == N) {
+            lo = 0;
+            hi = N - 1;
+            while (lo < hi) { /* smallest i with C_i >= T */
+                const uint64_t mid = lo + (hi - lo) / 2;
+                if (C[mid] >= T)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+        }
+        out[s] = (int64_t)lo;
+    }
+    free(C);
+    return 0;
+}

@@ -1,0 +1,138 @@
+"""Pins of the oracle's measurement sampling (Sec. 3: simulated measurements
+draw outcomes from the state's Born probabilities) against mathematics that
+does not come from the oracle: numpy reshapes of |psi|^2, exact closed forms of
+the uniform and GHZ distributions, product-state factorisation, numpy's
+sorted-search on a running sum, and a chi-square goodness-of-fit test.  A
+swapped bit order, an exclusive/inclusive slip in the running sum, a >= for >
+or a dropped imaginary part fails one of them.
+"""
+import numpy as np
+import pytest
+import scipy.stats
+
+import workloads as W
+
+
+def rand_state(n, seed):
+    r = np.random.default_rng(seed)
+    v = r.standard_normal(1 << n) + 1j * r.standard_normal(1 << n)
+    return v / np.linalg.norm(v)
+
+
+def marginal_by_reshape(psi, n, qubits):
+    """|psi|^2 as an n-axis array (axis a = qubit n-1-a), summed over the other
+    axes, measured axes ordered as listed, flattened with the first listed
+    qubit most significant."""
+    p = (np.abs(psi) ** 2).reshape([2] * n)
+    keep = [n - 1 - q for q in qubits]
+    drop = tuple(a for a in range(n) if a not in keep)
+    s = p.sum(axis=drop)
+    remaining = [a for a in range(n) if a in keep]          # ascending axis order
+    s = np.transpose(s, [remaining.index(a) for a in keep])
+    return s.reshape(-1)
+
+
+@pytest.mark.parametrize("n,qubits", [(1, [0]), (3, [0, 1, 2]), (3, [2, 0]), (5, [1]),
+                                      (5, [4, 0, 2]), (6, [3, 5, 0, 1]), (7, [6, 5, 4, 3, 2, 1, 0])])
+def test_probabilities_match_reshape(orc, n, qubits):
+    psi = rand_state(n, 11 + n)
+    got = orc.probabilities(psi, qubits)
+    ref = marginal_by_reshape(psi, n, qubits)
+    assert got.shape == (1 << len(qubits),)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-15)
+
+
+def test_probabilities_product_state(orc):
+    """A product state's marginal is the product of its one-qubit marginals."""
+    n = 5
+    r = np.random.default_rng(3)
+    singles = []
+    psi = np.ones(1, dtype=np.complex128)
+    for q in range(n):                       # qubit q is bit q: kron puts later factors low
+        a = r.standard_normal(2) + 1j * r.standard_normal(2)
+        a /= np.linalg.norm(a)
+        singles.append(np.abs(a) ** 2)
+        psi = np.kron(a, psi)
+    qubits = [3, 0, 4]
+    got = orc.probabilities(psi, qubits)
+    for b in range(8):
+        bits = [(b >> (2 - j)) & 1 for j in range(3)]
+        want = np.prod([singles[q][bit] for q, bit in zip(qubits, bits)])
+        assert abs(got[b] - want) <= 1e-15
+
+
+def test_probabilities_full_register_is_abs2(orc):
+    n = 6
+    psi = rand_state(n, 5)
+    got = orc.probabilities(psi, list(range(n - 1, -1, -1)))   # qubit n-1 most significant
+    assert np.array_equal(got, psi.real ** 2 + psi.imag ** 2)
+
+
+def test_probabilities_reject_bad_qubits(orc):
+    psi = rand_state(3, 1)
+    for q in ([3], [0, 0], [-1]):
+        with pytest.raises(ValueError):
+            orc.probabilities(psi, q)
+
+
+def test_sample_uniform_closed_form(orc):
+    """Equal superposition of n qubits (n even: every |psi_i|^2 = 2^-n exactly,
+    every running sum exact): outcome = floor(u 2^n), also on the grid points
+    u = k 2^-n where a >= in place of > would return k - 1."""
+    n = 8
+    N = 1 << n
+    psi = np.full(N, 2.0 ** (-n / 2), dtype=np.complex128)
+    u = np.concatenate([np.arange(N) / N, W.uniforms(4000, 21)])
+    got = orc.sample(psi, u)
+    assert np.array_equal(got, np.floor(u * N).astype(np.int64))
+
+
+def test_sample_basis_state_and_ghz(orc):
+    n = 6
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[37] = -1j
+    u = W.uniforms(500, 3)
+    assert np.all(orc.sample(psi, u) == 37)
+    ghz = np.zeros(1 << n, dtype=np.complex128)
+    ghz[0] = ghz[-1] = 1 / np.sqrt(2)
+    u = np.concatenate([np.linspace(0, 0.49, 50), np.linspace(0.51, 0.999999, 50)])
+    got = orc.sample(ghz, u)
+    assert np.array_equal(got, np.where(u < 0.5, 0, (1 << n) - 1))
+
+
+def test_sample_matches_sorted_search(orc):
+    """numpy's searchsorted (side='right') on a running sum is the smallest i
+    with C_i > t; the oracle must agree on every shot."""
+    for n, seed in ((1, 1), (4, 2), (9, 3), (12, 4)):
+        psi = rand_state(n, seed)
+        psi[::5] = 0                                   # zero-probability outcomes
+        psi[3 % psi.size] *= 1e-9                      # a tiny one
+        C = np.cumsum(np.abs(psi) ** 2)
+        u = W.uniforms(3000, 100 + n)
+        want = np.searchsorted(C, u * C[-1], side="right")
+        got = orc.sample(psi, u)
+        assert np.array_equal(got, want)
+        assert np.all(np.abs(psi[got]) > 0)
+
+
+def test_sample_edges(orc):
+    """u >= 1 (and NaN) give the last outcome of nonzero probability; u < 0
+    gives the first; the zero vector gives 0; no shots gives nothing."""
+    psi = np.zeros(16, dtype=np.complex128)
+    psi[[2, 9, 11]] = [0.6, 0.0, 0.8j]
+    got = orc.sample(psi, [1.0, 2.5, np.nan, -0.5, 0.0])
+    assert list(got) == [11, 11, 11, 2, 2]
+    assert list(orc.sample(np.zeros(8, dtype=np.complex128), [0.0, 0.7])) == [0, 0]
+    assert orc.sample(psi, np.zeros(0)).size == 0
+
+
+def test_sample_frequencies_chi_square(orc):
+    """Frequencies of 200000 seeded shots fit |psi|^2 (chi-square test at the
+    1e-4 level; the seed is fixed, so the test is deterministic)."""
+    n = 5
+    psi = rand_state(n, 9)
+    p = np.abs(psi) ** 2
+    u = W.uniforms(200000, 77)
+    counts = np.bincount(orc.sample(psi, u), minlength=1 << n)
+    stat, pval = scipy.stats.chisquare(counts, p * u.size / p.sum())
+    assert pval > 1e-4, (stat, pval)

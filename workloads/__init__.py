@@ -231,3 +231,8 @@ def random_gate(rng: np.random.Generator, n: int, k: int, c: int = 0):
 def random_state_seed_list(count: int, seed: int) -> List[int]:
     rng = np.random.default_rng(seed)
     return [int(v) for v in rng.integers(1, 2 ** 62, size=count)]
+
+
+def uniforms(count: int, seed: int) -> np.ndarray:
+    """Seeded uniforms in [0, 1) (float64) that drive measurement sampling."""
+    return np.random.default_rng(seed).random(count)
