@@ -679,8 +679,14 @@ int orc_adjoint(int n, int nops, const int* kind, const int* k, const int* tgt, 
  * index order. */
 int orc_probabilities(int n, const double* psi, const int* q, int m, double* out)
 {
-    if (m < 1 || check_qubits(n, q, m, NULL, 0) != 0)
+    if (n < 1 || n > 40 || m < 1 || m > n)
         return -1;
+    uint64_t seen = 0;
+    for (int j = 0; j < m; ++j) {
+        if (q[j] < 0 || q[j] >= n || ((seen >> q[j]) & 1ULL))
+            return -1;
+        seen |= 1ULL << q[j];
+    }
     const uint64_t N = 1ULL << n;
     const uint64_t M = 1ULL << m;
     for (uint64_t b = 0; b < M; ++b)

@@ -33,7 +33,8 @@ def marginal_by_reshape(psi, n, qubits):
 
 
 @pytest.mark.parametrize("n,qubits", [(1, [0]), (3, [0, 1, 2]), (3, [2, 0]), (5, [1]),
-                                      (5, [4, 0, 2]), (6, [3, 5, 0, 1]), (7, [6, 5, 4, 3, 2, 1, 0])])
+                                      (5, [4, 0, 2]), (6, [3, 5, 0, 1]), (7, [6, 5, 4, 3, 2, 1, 0]),
+                                      (13, [12, 0, 5, 7, 1, 9, 2, 11, 3, 10, 4, 8, 6])])
 def test_probabilities_match_reshape(orc, n, qubits):
     psi = rand_state(n, 11 + n)
     got = orc.probabilities(psi, qubits)
