@@ -171,7 +171,7 @@ def main():
     ap.add_argument("--profile-mfma", action="store_true",
                     help="only fused k = 4, 5 blocks (matrix-core counter runs)")
     ap.add_argument("--legs", default="",
-                    help="comma list of side legs to run alone (adjoint, adjoint26, batched, configs): profiling runs")
+                    help="comma list of side legs to run alone (adjoint, adjoint26, batched, configs, measure): profiling runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X and this build has no "
@@ -201,6 +201,8 @@ def main():
             out["batched"] = batched_leg(qsv, W, torch, np, dev)
         if "configs" in legs:
             out["configs"] = configs_leg(qsv, W, torch, np, dev, torch.cuda.current_stream())
+        if "measure" in legs:
+            out["measure"] = measure_leg(qsv, W, torch, np, dev, torch.cuda.current_stream())
         print(json.dumps(out), flush=True)
         return
 
@@ -285,8 +287,38 @@ def main():
         out["adjoint_n26"] = adjoint_leg_large(qsv, W, torch, np, dev)
         out["batched"] = batched_leg(qsv, W, torch, np, dev)
         out["configs"] = configs_leg(qsv, W, torch, np, dev, stream)
+        out["measure"] = measure_leg(qsv, W, torch, np, dev, stream)
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+
+
+def measure_leg(qsv, W, torch, np, dev, stream, n=30, shots=1 << 20):
+    """Simulated measurement on the seeded 30-qubit state: marginal
+    probabilities of 1, 10 (lowest / highest) and 20 qubits (GB/s = one read
+    of the state / time), and shot sampling: the prefix pass alone (one shot)
+    and 2^20 shots, giving the pass's GB/s and the per-shot rate."""
+    res = {}
+    u = torch.from_numpy(W.uniforms(shots, 2024)).to(dev)
+    for name, dt, S in (("c64", torch.complex64, 8), ("c128", torch.complex128, 16)):
+        psi = torch.empty(1 << n, dtype=dt, device=dev)
+        qsv.qsv_init_random(psi, 2024)
+        out = torch.empty(1 << 20, dtype=torch.float64, device=dev)
+        row = {}
+        for tag, qs in (("q15", [15]), ("low10", list(range(9, -1, -1))),
+                        ("high10", list(range(29, 19, -1))),
+                        ("spread20", list(range(0, 30, 3)) + list(range(1, 30, 3)))):
+            a = event_time(lambda: qsv.qsv_probabilities(psi, qs, out=out), 5, stream)
+            row["probabilities_" + tag + "_gbs"] = round(S * (1 << n) / a / 1e9, 1)
+        samples = torch.empty(shots, dtype=torch.int64, device=dev)
+        t1 = event_time(lambda: qsv.qsv_sample(psi, u[:1], out=samples[:1]), 5, stream)
+        tn = event_time(lambda: qsv.qsv_sample(psi, u, out=samples), 5, stream)
+        row["sample_prefix_pass_gbs"] = round(S * (1 << n) / t1 / 1e9, 1)
+        row["sample_%d_shots_ms" % shots] = round(tn * 1e3, 3)
+        row["shots_per_s_after_pass"] = round(shots / max(tn - t1, 1e-9), 1)
+        res[name] = row
+        del psi, out, samples
+        torch.cuda.empty_cache()
+    return res
 
 
 def configs_leg(qsv, W, torch, np, dev, stream):

@@ -173,6 +173,40 @@ qsv_status qsv_inner(const void* a, const void* b, int n, qsv_dtype dt, double* 
 qsv_status qsv_apply_pauli_sum(const void* psi, void* out, int n, qsv_dtype dt,
                                const qsv_pauli_sum* H, void* stream);
 
+/* ---------------------------------------------------------- measurement */
+
+/* Simulated measurement (Sec. 3: measurement outcomes are sampled from the
+ * state).  Outcome i has Born weight |psi_i|^2; no normalisation is applied,
+ * the state's own norm is the total mass.  Weights and sums are FP64. */
+
+/* Size in bytes of the scratch buffer qsv_probabilities and qsv_sample need
+ * for an n-qubit state (about 2^(n-10) doubles; 8 MiB at n = 30). */
+qsv_status qsv_measure_workspace_bytes(int n, qsv_dtype dt, size_t* bytes);
+
+/* Marginal distribution of the m distinct qubits qubits[0..m-1] (host array,
+ * 1 <= m <= n): out_dev[b] = sum of |psi_i|^2 over every i whose bits at
+ * qubits[0..m-1] spell b, qubits[0] being the MOST significant bit of b (the
+ * order of gate targets).  out_dev: 2^m doubles, device.  Every entry is
+ * summed in a fixed order (deterministic).  Errors: as for gates
+ * (QSV_ERR_ARG for m outside [1, n], QSV_ERR_QUBIT for a repeated or
+ * out-of-range qubit), NULL out_dev or work. */
+qsv_status qsv_probabilities(const void* psi, int n, qsv_dtype dt, const int* qubits, int m,
+                             double* out_dev, void* work, void* stream);
+
+/* Whole-register outcomes by inverse-transform sampling.  With the running
+ * sums C_i = sum_{j <= i} |psi_j|^2 and T = C_(2^n - 1), shot s takes
+ * t = u_dev[s] * T and returns out_dev[s] = the smallest i with C_i > t, or,
+ * if there is none (t >= T: rounding, u >= 1 or NaN), the last outcome of
+ * nonzero probability (0 for the zero vector); u < 0 counts as 0.  So an
+ * outcome of zero probability is never returned.  u_dev: nshots uniforms in
+ * [0, 1) (device, FP64, supplied by the caller, which owns the random
+ * stream); out_dev: nshots int64, device.  The running sums are formed in a
+ * fixed two-level order; an outcome can differ from a sequential running sum
+ * only when t lies within rounding of a boundary C_i.  nshots == 0 enqueues
+ * nothing; nshots < 0 is QSV_ERR_ARG. */
+qsv_status qsv_sample(const void* psi, int n, qsv_dtype dt, const double* u_dev, int64_t nshots,
+                      int64_t* out_dev, void* work, void* stream);
+
 /* ------------------------------------------------------------- circuits */
 
 /* Gate kinds (Sec. 3: circuits of 1-, 2- and 3-qubit gates).  Rotations are

@@ -1004,3 +1004,53 @@ qsv_status qsv_apply_pauli_sum(const void* psi, void* out, int n, qsv_dtype dt,
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ measurement
+
+qsv_status qsv_measure_workspace_bytes(int n, qsv_dtype dt, size_t* bytes)
+{
+    qsv_status st = check_n_dt(n, dt);
+    if (st)
+        return st;
+    if (!bytes)
+        return fail(QSV_ERR_ARG, "bytes is NULL");
+    const size_t a = sample_workspace_doubles(n), b = marginal_workspace_doubles();
+    *bytes = (a > b ? a : b) * sizeof(double);
+    return ok();
+}
+
+qsv_status qsv_probabilities(const void* psi, int n, qsv_dtype dt, const int* qubits, int m,
+                             double* out_dev, void* work, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if ((st = check_qubits(n, qubits, m, n, nullptr, 0)))
+        return st;
+    if (!out_dev || !work)
+        return fail(QSV_ERR_ARG, "out_dev or work is NULL");
+    hipError_t e = launch_marginal(psi, n, dt, qubits, m, out_dev, static_cast<double*>(work),
+                                   (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "probabilities launch: %s", hipGetErrorString(e));
+    return ok();
+}
+
+qsv_status qsv_sample(const void* psi, int n, qsv_dtype dt, const double* u_dev, int64_t nshots,
+                      int64_t* out_dev, void* work, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if (nshots < 0)
+        return fail(QSV_ERR_ARG, "nshots = %lld is negative", (long long)nshots);
+    if (nshots == 0)
+        return ok();
+    if (!u_dev || !out_dev || !work)
+        return fail(QSV_ERR_ARG, "u_dev, out_dev or work is NULL");
+    hipError_t e = launch_sample(psi, n, dt, u_dev, nshots, out_dev, static_cast<double*>(work),
+                                 (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "sample launch: %s", hipGetErrorString(e));
+    return ok();
+}

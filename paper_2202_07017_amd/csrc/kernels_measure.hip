@@ -1,0 +1,429 @@
+// Simulated measurement (Sec. 3: measurements are simulated by sampling
+// kernels): marginal Born probabilities of a qubit subset, and whole-register
+// outcomes drawn by inverse-transform sampling from caller-supplied uniforms.
+// Probabilities |psi_i|^2 are formed and summed in FP64 (amplitudes widened
+// first); every sum has a fixed order, so results are deterministic.
+//
+// Sampling keeps no probability vector.  One streaming pass writes a sum
+// tree into the workspace: level 0 holds the sums of chunks of 2^cb
+// consecutive amplitudes (cb = min(n, 10)), level L + 1 the sums of 64
+// consecutive level-L entries, up to a top level of at most 64 entries.
+// A shot descends the tree one wave-wide 64-way choice per level and
+// resolves the outcome inside one chunk (one 8 or 16 KiB read).
+#include "qsv_internal.h"
+
+namespace qsv {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kPrepThreads = 1024;       // 16 waves per group block
+constexpr int kMargWaves = 1 << 14;      // wave items targeted by the sliced marginal pass
+
+template <typename R>
+struct A2;
+template <>
+struct A2<float> {
+    using T = float2;
+};
+template <>
+struct A2<double> {
+    using T = double2;
+};
+
+template <typename R>
+__device__ __forceinline__ double prob(const R* psi, uint64_t i)
+{
+    const typename A2<R>::T a = reinterpret_cast<const typename A2<R>::T*>(psi)[i];
+    const double re = (double)a.x, im = (double)a.y;
+    return re * re + im * im;
+}
+
+// Sum of |psi|^2 over one 16-byte vector: two complex64 or one complex128 amplitude.
+__device__ __forceinline__ double prob16(const float* psi, uint64_t v)
+{
+    const float4 f = reinterpret_cast<const float4*>(psi)[v];
+    const double a = (double)f.x, b = (double)f.y, c = (double)f.z, d = (double)f.w;
+    return (a * a + b * b) + (c * c + d * d);
+}
+
+__device__ __forceinline__ double prob16(const double* psi, uint64_t v)
+{
+    const double2 f = reinterpret_cast<const double2*>(psi)[v];
+    return f.x * f.x + f.y * f.y;
+}
+
+// Butterfly sum over the 64 lanes; every lane ends with the same value.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Inclusive prefix over the 64 lanes (lane order).
+__device__ __forceinline__ double wave_incl_scan(double v, int lane)
+{
+    for (int off = 1; off < kWave; off <<= 1) {
+        const double y = __shfl_up(v, off, kWave);
+        if (lane >= off)
+            v += y;
+    }
+    return v;
+}
+
+// Descent step over up to 64 children with masses m (0 for lanes past the
+// end): picks the first child whose running mass exceeds t among children of
+// nonzero mass, else the last child of nonzero mass (t beyond the node's
+// mass: rounding, u >= 1 or NaN), else child 0 (a node of zero mass).  t is
+// then made relative to the chosen child.  Only children of nonzero mass are
+// taken, so an outcome of zero probability is never reached, whatever the
+// rounding of the sums.
+__device__ __forceinline__ int descend(double m, double& t, int lane)
+{
+    const double incl = wave_incl_scan(m, lane);
+    const uint64_t c = __ballot(incl > t && m > 0.0);
+    int L;
+    if (c) {
+        L = __builtin_ctzll(c);
+    } else {
+        const uint64_t nz = __ballot(m > 0.0);
+        L = nz ? 63 - __builtin_clzll(nz) : 0;
+    }
+    t -= __shfl(incl - m, L, kWave);
+    return L;
+}
+
+// One block per group of 2^gb chunks: wave w sums chunks w, w + 16, ...
+// (coalesced 16-byte loads) into level 0; wave 0 adds the group's chunk sums
+// into level 1 when the tree has a level above the chunks (lev1 != NULL).
+template <typename R>
+__global__ void __launch_bounds__(kPrepThreads) k_sample_prep(const R* __restrict__ psi, int cb, int gb,
+                                                             double* __restrict__ lev0,
+                                                             double* __restrict__ lev1)
+{
+    __shared__ double csum[kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int G = 1 << gb;
+    const uint64_t nvec = sizeof(R) == 4 ? (1ull << cb) / 2 : (1ull << cb);
+    const uint64_t grp = blockIdx.x;
+    for (int c = wave; c < G; c += kPrepThreads / kWave) {
+        const uint64_t v0 = ((grp << gb) + (uint64_t)c) * nvec;
+        double s = 0.0;
+#pragma unroll 8
+        for (uint64_t v = lane; v < nvec; v += kWave)
+            s += prob16(psi, v0 + v);
+        s = wave_sum(s);
+        if (lane == 0)
+            csum[c] = s;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const double x = lane < G ? csum[lane] : 0.0;
+        if (lane < G)
+            lev0[(grp << gb) + lane] = x;
+        const double g = wave_sum(x);
+        if (lev1 && lane == 0)
+            lev1[grp] = g;
+    }
+}
+
+// out[i] = sum of in[64 i .. 64 i + 63] (entries past nin count as 0); one
+// wave per output entry.
+__global__ void __launch_bounds__(256) k_tree_up(const double* __restrict__ in, uint64_t nin,
+                                                 double* __restrict__ out, uint64_t nout)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t i = (uint64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    if (i >= nout)
+        return;
+    const uint64_t j = i * kWave + (uint64_t)lane;
+    const double s = wave_sum(j < nin ? in[j] : 0.0);
+    if (lane == 0)
+        out[i] = s;
+}
+
+constexpr int kMaxLevels = 8;
+
+// Sum tree over the state: level 0 holds the chunk sums, level L + 1 the sums
+// of 64 consecutive level-L entries, up to a top level of <= 64 entries.
+struct SampleTree {
+    int cb;                        // log2(chunk length)
+    int nlev;
+    uint64_t count[kMaxLevels];
+    uint64_t off[kMaxLevels];      // offsets (in doubles) into the workspace
+};
+
+// One wave per shot (grid-stride over shots): descend the tree, then resolve
+// the outcome inside the chosen chunk, where lane l owns amplitudes
+// [l E, l E + E), E = max(2^cb / 64, 1).
+template <typename R>
+__global__ void __launch_bounds__(256) k_sample(const R* __restrict__ psi, SampleTree tr,
+                                                const double* __restrict__ work,
+                                                const double* __restrict__ u, int64_t nshots,
+                                                int64_t* __restrict__ out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (256 / kWave) + threadIdx.x / kWave));
+    const int64_t nw = (int64_t)gridDim.x * (256 / kWave);
+    const uint64_t csize = 1ull << tr.cb;
+    const int E = tr.cb >= 6 ? (int)(csize >> 6) : 1;
+    const int cnt = (uint64_t)lane * E < csize ? E : 0;
+    const int top = tr.nlev - 1;
+    const double* topv = work + tr.off[top];
+    const double T = wave_sum((uint64_t)lane < tr.count[top] ? topv[lane] : 0.0);
+    for (int64_t s = wid; s < nshots; s += nw) {
+        double t = u[s] * T;
+        if (t < 0.0)
+            t = 0.0;
+        uint64_t node = 0;
+        for (int L = top; L >= 0; --L) {
+            const uint64_t idx = node * kWave + (uint64_t)lane;
+            const double m = idx < tr.count[L] ? work[tr.off[L] + idx] : 0.0;
+            node = node * kWave + (uint64_t)descend(m, t, lane);
+        }
+        const uint64_t a0 = (node << tr.cb) + (uint64_t)lane * E;
+        double p[16];
+        double ls = 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            p[j] = j < cnt ? prob(psi, a0 + j) : 0.0;
+            ls += p[j];
+        }
+        const int L = descend(ls, t, lane);
+        if (lane == L) {
+            int jsel = -1, jlast = 0;
+            double run = 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                run += p[j];
+                if (p[j] > 0.0) {
+                    jlast = j;
+                    if (jsel < 0 && run > t)
+                        jsel = j;
+                }
+            }
+            out[s] = (int64_t)(a0 + (uint64_t)(jsel >= 0 ? jsel : jlast));
+        }
+    }
+}
+
+// Deposit the low bits of v into the set bit positions of mask, in order.
+__device__ __forceinline__ uint64_t deposit(uint64_t v, uint64_t mask)
+{
+    uint64_t r = 0;
+    while (mask) {
+        const uint64_t low = mask & (~mask + 1);
+        if (v & 1)
+            r |= low;
+        v >>= 1;
+        mask ^= low;
+    }
+    return r;
+}
+
+// Next index in the enumeration of the positions of mask: adds the deposited
+// step d, carrying through the positions outside mask.
+__device__ __forceinline__ uint64_t masked_add(uint64_t x, uint64_t d, uint64_t mask)
+{
+    return ((x | ~mask) + d) & mask;
+}
+
+struct MeasSpec {
+    int m;
+    int q[kMaxIns];      // measured qubits, q[0] = most significant outcome bit
+    uint64_t umask;      // unmeasured positions of the state index
+};
+
+__device__ __forceinline__ uint64_t outcome_bits(uint64_t b, const MeasSpec& M)
+{
+    uint64_t r = 0;
+    for (int j = 0; j < M.m; ++j)
+        r |= ((b >> (M.m - 1 - j)) & 1ull) << M.q[j];
+    return r;
+}
+
+// 2^(n-m) >= 64: one wave per (outcome b, slice s); the lanes walk the slice's
+// unmeasured indices 64 apart.  nslices == 1 writes out[b] directly, otherwise
+// part[s * 2^m + b].
+template <typename R>
+__global__ void __launch_bounds__(256) k_marginal_wave(const R* __restrict__ psi, MeasSpec M, int lsl,
+                                                       uint64_t nitems, double* __restrict__ dst)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t nb = 1ull << M.m;
+    const uint64_t d = deposit(kWave, M.umask);
+    const uint64_t iters = (1ull << lsl) / kWave;
+    const uint64_t stride = (uint64_t)gridDim.x * (256 / kWave);
+    for (uint64_t w = (uint64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; w < nitems; w += stride) {
+        const uint64_t b = w & (nb - 1);
+        const uint64_t s = w >> M.m;
+        const uint64_t hi = outcome_bits(b, M);
+        uint64_t x = deposit((s << lsl) + (uint64_t)lane, M.umask);
+        double acc = 0.0;
+        for (uint64_t j = 0; j < iters; ++j) {
+            acc += prob(psi, hi | x);
+            x = masked_add(x, d, M.umask);
+        }
+        acc = wave_sum(acc);
+        if (lane == 0)
+            dst[w] = acc;
+    }
+}
+
+// 2^(n-m) < 64: one thread per outcome, walking its 2^(n-m) indices in order.
+template <typename R>
+__global__ void __launch_bounds__(256) k_marginal_thread(const R* __restrict__ psi, MeasSpec M, int nr,
+                                                         double* __restrict__ out)
+{
+    const uint64_t nb = 1ull << M.m;
+    const uint64_t d = deposit(1, M.umask);
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t b = (uint64_t)blockIdx.x * 256 + threadIdx.x; b < nb; b += stride) {
+        const uint64_t hi = outcome_bits(b, M);
+        uint64_t x = 0;
+        double acc = 0.0;
+        for (int r = 0; r < (1 << nr); ++r) {
+            acc += prob(psi, hi | x);
+            x = masked_add(x, d, M.umask);
+        }
+        out[b] = acc;
+    }
+}
+
+// out[b] = sum over s < nslices of part[s * nb + b], in s order.
+__global__ void __launch_bounds__(256) k_marginal_finalize(const double* __restrict__ part, uint64_t nb,
+                                                           uint64_t nslices, double* __restrict__ out)
+{
+    const uint64_t b = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= nb)
+        return;
+    double acc = 0.0;
+    for (uint64_t s = 0; s < nslices; ++s)
+        acc += part[s * nb + b];
+    out[b] = acc;
+}
+
+SampleTree sample_tree(int n)
+{
+    SampleTree tr{};
+    tr.cb = n < 10 ? n : 10;
+    uint64_t c = 1ull << (n - tr.cb);
+    uint64_t off = 0;
+    for (;;) {
+        tr.count[tr.nlev] = c;
+        tr.off[tr.nlev] = off;
+        off += c;
+        ++tr.nlev;
+        if (c <= (uint64_t)kWave)
+            break;
+        c = (c + kWave - 1) / kWave;
+    }
+    return tr;
+}
+
+// Slices of the unmeasured range for the wave-per-item marginal pass:
+// returns log2(slice length); nslices = 2^(n - m - lsl).
+int marginal_slice_log(int n, int m)
+{
+    const int r = n - m;              // >= 6
+    int ls = 0;                       // log2(nslices)
+    while (ls < r - 6 && ((1ull << (m + ls + 1)) <= (uint64_t)kMargWaves))
+        ++ls;
+    return r - ls;
+}
+
+}  // namespace
+
+size_t sample_workspace_doubles(int n)
+{
+    const SampleTree tr = sample_tree(n);
+    return (size_t)(tr.off[tr.nlev - 1] + tr.count[tr.nlev - 1]);
+}
+
+size_t marginal_workspace_doubles()
+{
+    return (size_t)kMargWaves;
+}
+
+
+hipError_t launch_sample(const void* psi, int n, int dt, const double* u, int64_t nshots, int64_t* out,
+                         double* work, hipStream_t s)
+{
+    const SampleTree tr = sample_tree(n);
+    const int gb = n - tr.cb < 6 ? n - tr.cb : 6;
+    const unsigned ngroups = (unsigned)(1ull << (n - tr.cb - gb));
+    double* lev1 = tr.nlev > 1 ? work + tr.off[1] : nullptr;
+    if (dt == C64)
+        hipLaunchKernelGGL(k_sample_prep<float>, dim3(ngroups), dim3(kPrepThreads), 0, s,
+                           static_cast<const float*>(psi), tr.cb, gb, work, lev1);
+    else
+        hipLaunchKernelGGL(k_sample_prep<double>, dim3(ngroups), dim3(kPrepThreads), 0, s,
+                           static_cast<const double*>(psi), tr.cb, gb, work, lev1);
+    hipError_t e = hipGetLastError();
+    for (int L = 2; L < tr.nlev && e == hipSuccess; ++L) {
+        const unsigned grid = (unsigned)((tr.count[L] + 3) / 4);
+        hipLaunchKernelGGL(k_tree_up, dim3(grid), dim3(256), 0, s, (const double*)(work + tr.off[L - 1]),
+                           tr.count[L - 1], work + tr.off[L], tr.count[L]);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess || nshots == 0)
+        return e;
+    const int64_t waves = nshots < (int64_t)(1 << 20) ? nshots : (int64_t)(1 << 20);
+    const unsigned grid = (unsigned)((waves + 3) / 4);
+    if (dt == C64)
+        hipLaunchKernelGGL(k_sample<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(psi), tr,
+                           (const double*)work, u, nshots, out);
+    else
+        hipLaunchKernelGGL(k_sample<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(psi), tr,
+                           (const double*)work, u, nshots, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_marginal(const void* psi, int n, int dt, const int* q, int m, double* out, double* work,
+                           hipStream_t s)
+{
+    MeasSpec M{};
+    M.m = m;
+    uint64_t mm = 0;
+    for (int j = 0; j < m; ++j) {
+        M.q[j] = q[j];
+        mm |= 1ull << q[j];
+    }
+    M.umask = ((n >= 64) ? ~0ull : ((1ull << n) - 1)) & ~mm;
+    const int r = n - m;
+    if (r < 6) {
+        const uint64_t nb = 1ull << m;
+        const uint64_t blocks = (nb + 255) / 256;
+        const unsigned grid = (unsigned)(blocks < (1ull << 20) ? blocks : (1ull << 20));
+        if (dt == C64)
+            hipLaunchKernelGGL(k_marginal_thread<float>, dim3(grid), dim3(256), 0, s,
+                               static_cast<const float*>(psi), M, r, out);
+        else
+            hipLaunchKernelGGL(k_marginal_thread<double>, dim3(grid), dim3(256), 0, s,
+                               static_cast<const double*>(psi), M, r, out);
+        return hipGetLastError();
+    }
+    const int lsl = marginal_slice_log(n, m);
+    const uint64_t nslices = 1ull << (r - lsl);
+    const uint64_t nitems = nslices << m;
+    double* dst = nslices > 1 ? work : out;
+    const uint64_t blocks = (nitems + 3) / 4;
+    const unsigned grid = (unsigned)(blocks < (1ull << 20) ? blocks : (1ull << 20));
+    if (dt == C64)
+        hipLaunchKernelGGL(k_marginal_wave<float>, dim3(grid), dim3(256), 0, s,
+                           static_cast<const float*>(psi), M, lsl, nitems, dst);
+    else
+        hipLaunchKernelGGL(k_marginal_wave<double>, dim3(grid), dim3(256), 0, s,
+                           static_cast<const double*>(psi), M, lsl, nitems, dst);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nslices == 1)
+        return e;
+    const uint64_t nb = 1ull << m;
+    hipLaunchKernelGGL(k_marginal_finalize, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s,
+                       (const double*)work, nb, nslices, out);
+    return hipGetLastError();
+}
+
+}  // namespace qsv

@@ -101,6 +101,14 @@ hipError_t launch_hpsi_pair(const void* psi, void* lam, int n, int dt, uint64_t 
                             const TermChunk& t, hipStream_t s);
 hipError_t launch_fill_zero(double* p, uint64_t count, hipStream_t s);
 
+// kernels_measure.hip
+size_t sample_workspace_doubles(int n);
+size_t marginal_workspace_doubles();
+hipError_t launch_sample(const void* psi, int n, int dt, const double* u, int64_t nshots, int64_t* out,
+                         double* work, hipStream_t s);
+hipError_t launch_marginal(const void* psi, int n, int dt, const int* q, int m, double* out, double* work,
+                           hipStream_t s);
+
 // kernels_adjoint.hip
 // One reverse step of the adjoint sweep for the rotation described by L (a
 // dense K=1 launch with rot = ROT_X / ROT_Y, or a diag launch with

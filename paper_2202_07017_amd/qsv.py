@@ -74,6 +74,12 @@ _SIGS = {
     "qsv_inner": ([_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
     "qsv_apply_pauli_sum": ([_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsv_pauli_sum),
                              _vp], ctypes.c_int),
+    "qsv_measure_workspace_bytes": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+                                    ctypes.c_int),
+    "qsv_probabilities": ([_vp, ctypes.c_int, ctypes.c_int, _I, ctypes.c_int, _vp, _vp, _vp],
+                          ctypes.c_int),
+    "qsv_sample": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int64, _vp, _vp, _vp],
+                   ctypes.c_int),
     "qsv_plan_create": ([ctypes.POINTER(qsv_circuit), ctypes.c_int, ctypes.c_int, _D,
                          ctypes.POINTER(_vp)], ctypes.c_int),
     "qsv_plan_run": ([_vp, _vp, _vp, _vp], ctypes.c_int),
@@ -286,6 +292,54 @@ def qsv_apply_pauli_sum(psi, out, H, stream=None):
     P = H if isinstance(H, PauliSum) else PauliSum(H)
     _check(lib().qsv_apply_pauli_sum(_ptr(psi), _ptr(out), _nqubits(psi), dtype_code(psi),
                                      ctypes.byref(P.s), _stream(stream)))
+
+
+# ----------------------------------------------------------- measurement
+
+_measure_cache = {}
+
+
+def measure_workspace(n: int, dtype_code_: int, device):
+    """A cached device buffer of at least qsv_measure_workspace_bytes(n) bytes
+    (grown on demand, one per device and stream)."""
+    import torch
+    size = ctypes.c_size_t()
+    _check(lib().qsv_measure_workspace_bytes(n, dtype_code_, ctypes.byref(size)))
+    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
+    w = _measure_cache.get(key)
+    if w is None or w.numel() * 8 < size.value:
+        w = torch.empty((size.value + 7) // 8, dtype=torch.float64, device=device)
+        _measure_cache[key] = w
+    return w
+
+
+def qsv_probabilities(psi, qubits: Sequence[int], out=None, stream=None, order="little"):
+    """Marginal Born probabilities of `qubits` (first listed = most significant
+    outcome bit): a float64 device tensor of 2**len(qubits) entries."""
+    import torch
+    n = _nqubits(psi)
+    q = _ints(map_qubits(qubits, n, order))
+    out = out if out is not None else torch.empty(1 << len(qubits), dtype=torch.float64,
+                                                  device=psi.device)
+    work = measure_workspace(n, dtype_code(psi), psi.device)
+    _check(lib().qsv_probabilities(_ptr(psi), n, dtype_code(psi), q, len(qubits), _ptr(out),
+                                   _ptr(work), _stream(stream)))
+    return out
+
+
+def qsv_sample(psi, u, out=None, stream=None):
+    """Whole-register outcomes (int64 device tensor, amplitude indices with
+    qubit j at bit j) for the float64 device uniforms `u`, by inverse-transform
+    sampling of the Born probabilities."""
+    import torch
+    n = _nqubits(psi)
+    if u.dtype != torch.float64 or not u.is_contiguous():
+        raise ValueError("u must be a contiguous float64 device tensor")
+    out = out if out is not None else torch.empty(u.numel(), dtype=torch.int64, device=psi.device)
+    work = measure_workspace(n, dtype_code(psi), psi.device)
+    _check(lib().qsv_sample(_ptr(psi), n, dtype_code(psi), _ptr(u), u.numel(), _ptr(out),
+                            _ptr(work), _stream(stream)))
+    return out
 
 
 # -------------------------------------------------------------- circuits

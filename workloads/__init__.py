@@ -236,3 +236,23 @@ def random_state_seed_list(count: int, seed: int) -> List[int]:
 def uniforms(count: int, seed: int) -> np.ndarray:
     """Seeded uniforms in [0, 1) (float64) that drive measurement sampling."""
     return np.random.default_rng(seed).random(count)
+
+
+def qft(n: int, swaps: bool = True) -> Circuit:
+    """Quantum Fourier transform (the QFT circuit of the paper's built-in
+    models, Sec. 3) as a gate list: taking bit n-1 as the most significant,
+    for each bit b from n-1 down to 0 a Hadamard on b, then for each lower bit
+    c < b a phase diag(1, exp(2 pi i / 2^(b-c+1))) on b controlled by c; then
+    swaps (b, n-1-b) that reverse the bit order.  The map is
+    |x> -> 2^(-n/2) sum_y exp(+2 pi i x y / 2^n) |y>."""
+    c = Circuit(n)
+    for b in range(n - 1, -1, -1):
+        c.ops.append(Op("h", (b,)))
+        for ctl in range(b - 1, -1, -1):
+            phi = TWO_PI / float(1 << (b - ctl + 1))
+            c.ops.append(Op("matrix", (b,), controls=(ctl,),
+                            matrix=np.diag([1.0, np.exp(1j * phi)]).astype(np.complex128)))
+    if swaps:
+        for b in range(n // 2):
+            c.ops.append(Op("swap", (b, n - 1 - b)))
+    return c
