@@ -18,7 +18,8 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kPrepThreads = 1024;       // 16 waves per group block
-constexpr int kMargWaves = 1 << 14;      // wave items targeted by the sliced marginal pass
+constexpr int kMargItems = 1 << 14;      // wave items targeted by the marginal pass
+constexpr int kMargPartLog = 20;         // log2(doubles of per-slice partial sums)
 
 template <typename R>
 struct A2;
@@ -236,59 +237,72 @@ struct MeasSpec {
     uint64_t umask;      // unmeasured positions of the state index
 };
 
-__device__ __forceinline__ uint64_t outcome_bits(uint64_t b, const MeasSpec& M)
+// The outcome b of state index i: bit (m - 1 - j) of b is bit q[j] of i.
+__device__ __forceinline__ uint64_t outcome_index(uint64_t i, const MeasSpec& M)
 {
-    uint64_t r = 0;
+    uint64_t b = 0;
     for (int j = 0; j < M.m; ++j)
-        r |= ((b >> (M.m - 1 - j)) & 1ull) << M.q[j];
-    return r;
+        b |= ((i >> M.q[j]) & 1ull) << (M.m - 1 - j);
+    return b;
 }
 
-// 2^(n-m) >= 64: one wave per (outcome b, slice s); the lanes walk the slice's
-// unmeasured indices 64 apart.  nslices == 1 writes out[b] directly, otherwise
-// part[s * 2^m + b].
+// Lanes read 64 consecutive amplitudes (address bits 0..5 = lane bits), so
+// every load is coalesced whatever qubits are measured.  A wave item fixes
+// the measured address bits above bit 5 (h) and a slice s of the unmeasured
+// address bits above bit 5, which the wave walks in order (four independent
+// partial sums, combined in a fixed order).  The lanes then add over their
+// unmeasured lane bits (xor butterfly on those bits only), and each lane whose
+// unmeasured lane bits are 0 holds the sum of one outcome b: written to
+// out[b] (one slice) or part[s * 2^m + b].
+struct MargLanes {
+    uint64_t mhi;        // measured positions >= 6
+    uint64_t uhi;        // unmeasured positions >= 6 (below n)
+    int lane_umask;      // lane bits whose position is unmeasured or >= n
+    int mhi_bits;        // popcount(mhi)
+    int iters_log;       // log2(unmeasured steps per item)
+    uint64_t nstate;     // 2^n
+};
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_marginal_wave(const R* __restrict__ psi, MeasSpec M, int lsl,
-                                                       uint64_t nitems, double* __restrict__ dst)
+__global__ void __launch_bounds__(256) k_marginal_lanes(const R* __restrict__ psi, MeasSpec M, MargLanes G,
+                                                        uint64_t nitems, double* __restrict__ dst)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const uint64_t nb = 1ull << M.m;
-    const uint64_t d = deposit(kWave, M.umask);
-    const uint64_t iters = (1ull << lsl) / kWave;
+    const uint64_t d = deposit(1, G.uhi);
+    const uint64_t iters = 1ull << G.iters_log;
     const uint64_t stride = (uint64_t)gridDim.x * (256 / kWave);
+    const bool live = (uint64_t)lane < G.nstate;
     for (uint64_t w = (uint64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; w < nitems; w += stride) {
-        const uint64_t b = w & (nb - 1);
-        const uint64_t s = w >> M.m;
-        const uint64_t hi = outcome_bits(b, M);
-        uint64_t x = deposit((s << lsl) + (uint64_t)lane, M.umask);
-        double acc = 0.0;
-        for (uint64_t j = 0; j < iters; ++j) {
-            acc += prob(psi, hi | x);
-            x = masked_add(x, d, M.umask);
+        const uint64_t h = w & ((1ull << G.mhi_bits) - 1);
+        const uint64_t s = w >> G.mhi_bits;
+        const uint64_t base = deposit(h, G.mhi) | (uint64_t)lane;
+        uint64_t x = deposit(s << G.iters_log, G.uhi);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        uint64_t j = 0;
+        if (live) {
+            for (; j + 4 <= iters; j += 4) {
+                const uint64_t x1 = masked_add(x, d, G.uhi);
+                const uint64_t x2 = masked_add(x1, d, G.uhi);
+                const uint64_t x3 = masked_add(x2, d, G.uhi);
+                a0 += prob(psi, base | x);
+                a1 += prob(psi, base | x1);
+                a2 += prob(psi, base | x2);
+                a3 += prob(psi, base | x3);
+                x = masked_add(x3, d, G.uhi);
+            }
+            for (; j < iters; ++j) {
+                a0 += prob(psi, base | x);
+                x = masked_add(x, d, G.uhi);
+            }
         }
-        acc = wave_sum(acc);
-        if (lane == 0)
-            dst[w] = acc;
-    }
-}
-
-// 2^(n-m) < 64: one thread per outcome, walking its 2^(n-m) indices in order.
-template <typename R>
-__global__ void __launch_bounds__(256) k_marginal_thread(const R* __restrict__ psi, MeasSpec M, int nr,
-                                                         double* __restrict__ out)
-{
-    const uint64_t nb = 1ull << M.m;
-    const uint64_t d = deposit(1, M.umask);
-    const uint64_t stride = (uint64_t)gridDim.x * 256;
-    for (uint64_t b = (uint64_t)blockIdx.x * 256 + threadIdx.x; b < nb; b += stride) {
-        const uint64_t hi = outcome_bits(b, M);
-        uint64_t x = 0;
-        double acc = 0.0;
-        for (int r = 0; r < (1 << nr); ++r) {
-            acc += prob(psi, hi | x);
-            x = masked_add(x, d, M.umask);
+        double acc = (a0 + a1) + (a2 + a3);
+        for (int k = 0; k < 6; ++k)
+            if ((G.lane_umask >> k) & 1)
+                acc += __shfl_xor(acc, 1 << k, kWave);
+        if ((lane & G.lane_umask) == 0) {
+            const uint64_t b = outcome_index(base, M);
+            dst[(s << M.m) + b] = acc;
         }
-        out[b] = acc;
     }
 }
 
@@ -323,17 +337,6 @@ SampleTree sample_tree(int n)
     return tr;
 }
 
-// Slices of the unmeasured range for the wave-per-item marginal pass:
-// returns log2(slice length); nslices = 2^(n - m - lsl).
-int marginal_slice_log(int n, int m)
-{
-    const int r = n - m;              // >= 6
-    int ls = 0;                       // log2(nslices)
-    while (ls < r - 6 && ((1ull << (m + ls + 1)) <= (uint64_t)kMargWaves))
-        ++ls;
-    return r - ls;
-}
-
 }  // namespace
 
 size_t sample_workspace_doubles(int n)
@@ -344,7 +347,7 @@ size_t sample_workspace_doubles(int n)
 
 size_t marginal_workspace_doubles()
 {
-    return (size_t)kMargWaves;
+    return (size_t)1 << kMargPartLog;
 }
 
 
@@ -391,38 +394,37 @@ hipError_t launch_marginal(const void* psi, int n, int dt, const int* q, int m, 
         M.q[j] = q[j];
         mm |= 1ull << q[j];
     }
-    M.umask = ((n >= 64) ? ~0ull : ((1ull << n) - 1)) & ~mm;
-    const int r = n - m;
-    if (r < 6) {
-        const uint64_t nb = 1ull << m;
-        const uint64_t blocks = (nb + 255) / 256;
-        const unsigned grid = (unsigned)(blocks < (1ull << 20) ? blocks : (1ull << 20));
-        if (dt == C64)
-            hipLaunchKernelGGL(k_marginal_thread<float>, dim3(grid), dim3(256), 0, s,
-                               static_cast<const float*>(psi), M, r, out);
-        else
-            hipLaunchKernelGGL(k_marginal_thread<double>, dim3(grid), dim3(256), 0, s,
-                               static_cast<const double*>(psi), M, r, out);
-        return hipGetLastError();
-    }
-    const int lsl = marginal_slice_log(n, m);
-    const uint64_t nslices = 1ull << (r - lsl);
-    const uint64_t nitems = nslices << m;
-    double* dst = nslices > 1 ? work : out;
+    const uint64_t all = (1ull << n) - 1;
+    M.umask = all & ~mm;
+    MargLanes G{};
+    G.mhi = mm & ~63ull;
+    G.uhi = M.umask & ~63ull;
+    G.lane_umask = (int)(~mm & 63ull);
+    G.mhi_bits = __builtin_popcountll(G.mhi);
+    G.nstate = 1ull << n;
+    const int ubits = __builtin_popcountll(G.uhi);
+    // slices: as many as keep the item count near kMargItems and the
+    // partial sums within the workspace
+    int ls = 0;
+    while (ls < ubits && G.mhi_bits + ls + 1 <= 14 && m + ls + 1 <= kMargPartLog)
+        ++ls;
+    G.iters_log = ubits - ls;
+    const uint64_t nitems = 1ull << (G.mhi_bits + ls);
+    double* dst = ls ? work : out;
     const uint64_t blocks = (nitems + 3) / 4;
     const unsigned grid = (unsigned)(blocks < (1ull << 20) ? blocks : (1ull << 20));
     if (dt == C64)
-        hipLaunchKernelGGL(k_marginal_wave<float>, dim3(grid), dim3(256), 0, s,
-                           static_cast<const float*>(psi), M, lsl, nitems, dst);
+        hipLaunchKernelGGL(k_marginal_lanes<float>, dim3(grid), dim3(256), 0, s,
+                           static_cast<const float*>(psi), M, G, nitems, dst);
     else
-        hipLaunchKernelGGL(k_marginal_wave<double>, dim3(grid), dim3(256), 0, s,
-                           static_cast<const double*>(psi), M, lsl, nitems, dst);
+        hipLaunchKernelGGL(k_marginal_lanes<double>, dim3(grid), dim3(256), 0, s,
+                           static_cast<const double*>(psi), M, G, nitems, dst);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || nslices == 1)
+    if (e != hipSuccess || ls == 0)
         return e;
     const uint64_t nb = 1ull << m;
     hipLaunchKernelGGL(k_marginal_finalize, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s,
-                       (const double*)work, nb, nslices, out);
+                       (const double*)work, nb, 1ull << ls, out);
     return hipGetLastError();
 }
 
