@@ -171,7 +171,7 @@ def main():
     ap.add_argument("--profile-mfma", action="store_true",
                     help="only fused k = 4, 5 blocks (matrix-core counter runs)")
     ap.add_argument("--legs", default="",
-                    help="comma list of side legs to run alone (adjoint, adjoint26, batched, configs, measure): profiling runs")
+                    help="comma list of side legs to run alone (adjoint, adjoint26, batched, configs, measure, circuits): profiling runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X and this build has no "
@@ -203,6 +203,8 @@ def main():
             out["configs"] = configs_leg(qsv, W, torch, np, dev, torch.cuda.current_stream())
         if "measure" in legs:
             out["measure"] = measure_leg(qsv, W, torch, np, dev, torch.cuda.current_stream())
+        if "circuits" in legs:
+            out["qft_trotter"] = qft_trotter_leg(qsv, W, torch, np, dev, torch.cuda.current_stream())
         print(json.dumps(out), flush=True)
         return
 
@@ -288,6 +290,7 @@ def main():
         out["batched"] = batched_leg(qsv, W, torch, np, dev)
         out["configs"] = configs_leg(qsv, W, torch, np, dev, stream)
         out["measure"] = measure_leg(qsv, W, torch, np, dev, stream)
+        out["qft_trotter"] = qft_trotter_leg(qsv, W, torch, np, dev, stream)
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
@@ -317,6 +320,32 @@ def measure_leg(qsv, W, torch, np, dev, stream, n=30, shots=1 << 20):
         row["shots_per_s_after_pass"] = round(shots / max(tn - t1, 1e-9), 1)
         res[name] = row
         del psi, out, samples
+        torch.cuda.empty_cache()
+    return res
+
+
+def qft_trotter_leg(qsv, W, torch, np, dev, stream, n=30):
+    """Two more workloads at n = 30 as whole plans: the QFT (Hadamards,
+    controlled phases, swaps) and one symmetric Trotter step of the TFIM
+    (h = 1), each unfused and fused to k = 5; ms per run, launches, and GB/s
+    and TFLOP/s of the plan's algorithmic bytes and flops."""
+    res = {}
+    for name, dt, code in (("c64", torch.complex64, qsv.C64), ("c128", torch.complex128, qsv.C128)):
+        psi = torch.empty(1 << n, dtype=dt, device=dev)
+        qsv.qsv_init_random(psi, 3003)
+        for tag, make in (("qft", lambda k: qsv.Plan(W.qft(n), code, k)),
+                          ("trotter_tfim_order2", lambda k: qsv.TrotterPlan(W.tfim_chain(n), 0.05, 1, 2,
+                                                                            code, k))):
+            for k in (1, 5):
+                plan = make(k)
+                nl, b, f = plan.info()
+                plan.run(psi)
+                a = event_time(lambda: plan.run(psi), 2, stream)
+                res["%s_n%d_%s_fuse%d" % (tag, n, name, k)] = {
+                    "ms": round(a * 1e3, 3), "launches": nl, "gbs": round(b / a / 1e9, 1),
+                    "hbm_frac": round(b / a / 1e9 / HBM_PEAK_GBS, 4), "tflops": round(f / a / 1e12, 2)}
+                del plan
+        del psi
         torch.cuda.empty_cache()
     return res
 

@@ -271,6 +271,23 @@ qsv_status qsv_plan_info(const qsv_plan* plan, int* nlaunches, double* bytes, do
 
 qsv_status qsv_plan_destroy(qsv_plan* plan);
 
+/* Trotterised time evolution (Sec. 3: Hamiltonian objects interfaced with a
+ * time-evolution solver through the Trotter decomposition).  Compiles `steps`
+ * steps of length tau approximating exp(-i steps tau H), H = sum_j c_j P_j,
+ * into a plan (run, info and destroy as for qsv_plan_create).  Each factor
+ * exp(-i theta P_j) = cos(theta) I - i sin(theta) P_j is a dense gate on the
+ * support of P_j (an identity string is the global phase exp(-i theta)).
+ * order 1: per step, terms j = 0..T-1 with theta = tau c_j.  order 2
+ * (symmetric): terms 0..T-1 then T-1..0, each with theta = tau c_j / 2, so
+ * the step with -tau is the exact inverse of the step with tau.  Factors
+ * fuse into blocks of at most fuse_k qubits like circuit gates.  Errors:
+ * QSV_ERR_ARG for steps < 0, order not 1 or 2, non-finite tau or a bad Pauli
+ * sum; QSV_ERR_UNSUPPORTED for a term on more than QSV_MAX_TARGETS qubits.
+ * steps == 0 gives an empty plan. */
+qsv_status qsv_trotter_plan_create(const qsv_pauli_sum* H, int n, double tau, int steps, int order,
+                                   qsv_dtype dt, int fuse_k, qsv_plan** plan);
+
+
 /* ------------------------------------------------------------ gradients */
 
 typedef struct qsv_adjoint_plan qsv_adjoint_plan;

@@ -140,6 +140,46 @@ def sample(psi, u) -> np.ndarray:
     return out[:u.size]
 
 
+_PAULI2 = {(0, 0): np.eye(2, dtype=np.complex128),
+           (1, 0): np.array([[0, 1], [1, 0]], dtype=np.complex128),
+           (1, 1): np.array([[0, -1j], [1j, 0]], dtype=np.complex128),
+           (0, 1): np.array([[1, 0], [0, -1]], dtype=np.complex128)}
+
+
+def pauli_factor(x: int, z: int, theta: float):
+    """exp(-i theta P) for the Pauli string (x, z) on its support (targets in
+    descending qubit order, first target = most significant), by the matrix
+    exponential of the Kronecker product of its 2x2 factors.  The identity
+    string gives exp(-i theta) I on qubit 0."""
+    import scipy.linalg
+    supp = [q for q in range(63, -1, -1) if ((x | z) >> q) & 1]
+    if not supp:
+        return [0], scipy.linalg.expm(-1j * theta * _PAULI2[(0, 0)])
+    P = np.ones((1, 1), dtype=np.complex128)
+    for q in supp:
+        P = np.kron(P, _PAULI2[((x >> q) & 1, (z >> q) & 1)])
+    return supp, scipy.linalg.expm(-1j * theta * P)
+
+
+def trotter(psi, H, tau: float, steps: int, order: int = 1) -> np.ndarray:
+    """Trotterised exp(-i steps tau H) psi (Sec. 3, time evolution with the
+    Trotter decomposition): per step, order 1 applies exp(-i tau c_j P_j) for
+    j = 0..T-1; order 2 applies exp(-i tau c_j P_j / 2) for j = 0..T-1 and
+    then for j = T-1..0.  Each factor goes through eq. (1) (`apply`)."""
+    if order not in (1, 2):
+        raise ValueError("order must be 1 or 2")
+    terms = list(zip(H.x_mask, H.z_mask, H.coeff))
+    w = tau if order == 1 else tau / 2
+    seq = [pauli_factor(int(x), int(z), w * float(c)) for x, z, c in terms]
+    if order == 2:
+        seq = seq + seq[::-1]
+    out = _as_c128(psi).copy()
+    for _ in range(steps):
+        for t, G in seq:
+            out = apply(out, t, [], G)
+    return out
+
+
 def expect(psi, H, per_term: bool = False):
     """sum_j c_j <psi|P_j|psi> as a complex number (imaginary part ~ 0)."""
     psi = _as_c128(psi)

@@ -18,7 +18,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kPrepThreads = 1024;       // 16 waves per group block
-constexpr int kMargItems = 1 << 14;      // wave items targeted by the marginal pass
+constexpr int kMargItemsLog = 16;        // log2(wave items targeted by the marginal pass)
 constexpr int kMargPartLog = 20;         // log2(doubles of per-slice partial sums)
 
 template <typename R>
@@ -306,17 +306,21 @@ __global__ void __launch_bounds__(256) k_marginal_lanes(const R* __restrict__ ps
     }
 }
 
-// out[b] = sum over s < nslices of part[s * nb + b], in s order.
+// out[b] = sum over s < nslices of part[s * nb + b]: one wave per outcome,
+// lane l adding slices l, l + 64, ... in order, then a butterfly.
 __global__ void __launch_bounds__(256) k_marginal_finalize(const double* __restrict__ part, uint64_t nb,
                                                            uint64_t nslices, double* __restrict__ out)
 {
-    const uint64_t b = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t b = (uint64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
     if (b >= nb)
         return;
     double acc = 0.0;
-    for (uint64_t s = 0; s < nslices; ++s)
+    for (uint64_t s = lane; s < nslices; s += kWave)
         acc += part[s * nb + b];
-    out[b] = acc;
+    acc = wave_sum(acc);
+    if (lane == 0)
+        out[b] = acc;
 }
 
 SampleTree sample_tree(int n)
@@ -403,10 +407,10 @@ hipError_t launch_marginal(const void* psi, int n, int dt, const int* q, int m, 
     G.mhi_bits = __builtin_popcountll(G.mhi);
     G.nstate = 1ull << n;
     const int ubits = __builtin_popcountll(G.uhi);
-    // slices: as many as keep the item count near kMargItems and the
+    // slices: as many as keep the item count near 2^kMargItemsLog and the
     // partial sums within the workspace
     int ls = 0;
-    while (ls < ubits && G.mhi_bits + ls + 1 <= 14 && m + ls + 1 <= kMargPartLog)
+    while (ls < ubits && G.mhi_bits + ls + 1 <= kMargItemsLog && m + ls + 1 <= kMargPartLog)
         ++ls;
     G.iters_log = ubits - ls;
     const uint64_t nitems = 1ull << (G.mhi_bits + ls);
@@ -423,7 +427,7 @@ hipError_t launch_marginal(const void* psi, int n, int dt, const int* q, int m, 
     if (e != hipSuccess || ls == 0)
         return e;
     const uint64_t nb = 1ull << m;
-    hipLaunchKernelGGL(k_marginal_finalize, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_marginal_finalize, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s,
                        (const double*)work, nb, 1ull << ls, out);
     return hipGetLastError();
 }

@@ -82,6 +82,9 @@ _SIGS = {
                    ctypes.c_int),
     "qsv_plan_create": ([ctypes.POINTER(qsv_circuit), ctypes.c_int, ctypes.c_int, _D,
                          ctypes.POINTER(_vp)], ctypes.c_int),
+    "qsv_trotter_plan_create": ([ctypes.POINTER(qsv_pauli_sum), ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(_vp)], ctypes.c_int),
     "qsv_plan_run": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "qsv_plan_info": ([_vp, _I, _D, _D], ctypes.c_int),
     "qsv_plan_destroy": ([_vp], ctypes.c_int),
@@ -259,6 +262,7 @@ class PauliSum:
         self.x = np.ascontiguousarray(x, dtype=np.uint64)
         self.z = np.ascontiguousarray(z, dtype=np.uint64)
         self.c = np.ascontiguousarray(H.coeff, dtype=np.float64)
+        self.n = H.n
         self.s = qsv_pauli_sum(len(self.c), self.x.ctypes.data_as(_U), self.z.ctypes.data_as(_U),
                                self.c.ctypes.data_as(_D))
 
@@ -397,6 +401,18 @@ class Plan:
     def __del__(self):
         if getattr(self, "h", None) and self.h.value and _lib is not None:
             _lib.qsv_plan_destroy(self.h)
+
+
+class TrotterPlan(Plan):
+    """qsv_trotter_plan_create: `steps` Trotter steps of length tau for the
+    Pauli sum H (order 1 or 2), fused into blocks of at most fuse_k qubits."""
+
+    def __init__(self, H, tau: float, steps: int, order: int, dtype_code_: int, fuse_k: int = 5):
+        self.P = H if isinstance(H, PauliSum) else PauliSum(H)
+        self.h = _vp()
+        n = H.n
+        _check(lib().qsv_trotter_plan_create(ctypes.byref(self.P.s), n, float(tau), int(steps),
+                                             int(order), dtype_code_, fuse_k, ctypes.byref(self.h)))
 
 
 class AdjointPlan:
