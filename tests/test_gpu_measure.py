@@ -171,3 +171,23 @@ def test_full_size_n30(q):
         assert np.max(np.abs(pr - want)) <= 1e-12, np.max(np.abs(pr - want))
     del d
     torch.cuda.empty_cache()
+
+
+def test_full_size_n32_uniform(q):
+    """n = 32 (32 GiB complex64, 64 GiB complex128): the equal superposition,
+    exact in both precisions, samples floor(u 2^32) on every shot (outcome
+    indices past 2^31) and every marginal entry is exactly 2^-m."""
+    import torch
+    n = 32
+    N = 1 << n
+    u = np.concatenate([W.uniforms(50000, 32), [0.5, 1.0 - 2.0 ** -40]])
+    for name in DTYPES:
+        say("n32 uniform", name)
+        psi = torch.full((N,), 2.0 ** (-n / 2), dtype=torch_dtype(name), device="cuda")
+        got = q.qsv_sample(psi, _u_gpu(u)).cpu().numpy()
+        assert np.array_equal(got, np.floor(u * N).astype(np.int64))
+        for qs in ([31], [0, 31, 16], list(range(31, 19, -1))):
+            pr = q.qsv_probabilities(psi, qs).cpu().numpy()
+            assert np.all(pr == 2.0 ** -len(qs))
+        del psi
+        torch.cuda.empty_cache()
