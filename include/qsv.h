@@ -50,6 +50,7 @@
  *    QSV_BATCH_SHAPE=m,t[,s]    batch tile qubits, threads, split (skips the cache)
  *    QSV_NO_GRAPH=1             plans enqueue their launches instead of replaying a graph
  *    QSV_NO_MFMA=1              4- and 5-qubit blocks on the vector units
+ *    QSV_NO_DIAG_RUN=1          plans keep consecutive diagonal gates as separate launches
  *    QSV_NO_TILES=1             per-gate adjoint instead of cache-blocked tile programs
  *    QSV_NO_LANE_SWEEP=1        no cross-lane exchange for low single-qubit targets
  *    QSV_SWEEP_NT=0|1           force the nontemporal hint of sweeps off or on

@@ -290,6 +290,104 @@ static Built item_launch(const qsv_circuit* C, const Item& it, int dt, const dou
 
 }  // namespace qsv
 
+namespace qsv {
+
+// Estimated traffic of a diagonal launch as a fraction of a full read+write
+// sweep: the touched fraction 2^-(fixed bits), scaled up when the touched runs
+// (2^(lowest fixed bit) amplitudes) are shorter than a 128-byte line.
+static double diag_cost(uint64_t fix, int S)
+{
+    if (!fix)
+        return 1.0;
+    const int pmin = __builtin_ctzll(fix);
+    double frac = std::ldexp(1.0, -__builtin_popcountll(fix));
+    const double run = std::ldexp((double)S, pmin);
+    if (run < 128.0)
+        frac *= 128.0 / run;
+    return frac < 1.0 ? frac : 1.0;
+}
+
+static bool as_factor(const GateLaunch& L, uint64_t& fix, uint64_t& val)
+{
+    if (L.type != L_DIAG || L.rot != ROT_NONE || L.K > 2 || L.ngroups == 0)
+        return false;
+    const int shift = L.mode == W2 ? 1 : 0;
+    fix = 0;
+    for (int j = 0; j < L.ins.nins; ++j)
+        fix |= 1ull << (__builtin_popcountll(L.ins.low[j]) + shift);
+    val = L.ins.setmask << shift;
+    return true;
+}
+
+// Diagonal gates commute with each other and with any gate on other qubits,
+// so a run collects diagonal launches and lets every other launch that acts
+// on none of the run's qubits go ahead of it; a launch that touches one of
+// them closes the run.  A closed run of >= 2 launches whose separate traffic
+// is estimated at >= 1.25 full sweeps becomes one L_DIAGRUN sweep (at most
+// kMaxRunFactors factors); otherwise its launches are kept as they are.
+void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& upload_off, int n, int dt)
+{
+    const int S = dt == C64 ? 8 : 16;
+    std::vector<GateLaunch> out;
+    std::vector<long long> offs;
+    std::vector<size_t> run;
+    uint64_t runq = 0;
+    double cost = 0.0;
+    auto close = [&]() {
+        if (run.size() >= 2 && cost >= 1.25) {
+            GateLaunch R{};
+            R.type = L_DIAGRUN;
+            R.dt = dt;
+            R.n = n;
+            R.mode = W1;
+            R.ngroups = dt == C64 ? (1ull << n) / 2 : (1ull << n);
+            R.qmask = runq;
+            for (size_t k : run) {
+                const GateLaunch& D = Ls[k];
+                const int f = R.run_nf++;
+                as_factor(D, R.run_fix[f], R.run_val[f]);
+                R.run_nt[f] = D.K;
+                for (int b = 0; b < D.K; ++b)
+                    R.run_tpos[f][b] = D.tpos[b];
+                for (int t = 0; t < (2 << D.K); ++t)
+                    R.run_d[f][t] = D.g[t];
+                R.flops += 6.0 * std::ldexp(1.0, n);
+            }
+            R.bytes = 2.0 * S * std::ldexp(1.0, n);
+            out.push_back(R);
+            offs.push_back(-1);
+        } else {
+            for (size_t k : run) {
+                out.push_back(Ls[k]);
+                offs.push_back(upload_off[k]);
+            }
+        }
+        run.clear();
+        runq = 0;
+        cost = 0.0;
+    };
+    for (size_t j = 0; j < Ls.size(); ++j) {
+        uint64_t fix, val;
+        if (as_factor(Ls[j], fix, val)) {
+            if (run.size() == (size_t)kMaxRunFactors)
+                close();
+            run.push_back(j);
+            runq |= Ls[j].qmask;
+            cost += diag_cost(fix, S);
+            continue;
+        }
+        if (!run.empty() && (Ls[j].qmask & runq))
+            close();
+        out.push_back(Ls[j]);
+        offs.push_back(upload_off[j]);
+    }
+    close();
+    Ls.swap(out);
+    upload_off.swap(offs);
+}
+
+}  // namespace qsv
+
 // ================================================================= plans
 
 struct qsv_plan {
@@ -332,6 +430,16 @@ struct qsv_adjoint_plan {
 
 namespace {
 
+static uint64_t op_qubits(const qsv_op& op)
+{
+    uint64_t m = 0;
+    for (int j = 0; j < op.k; ++j)
+        m |= 1ull << op.targets[j];
+    for (int j = 0; j < op.c; ++j)
+        m |= 1ull << op.controls[j];
+    return m;
+}
+
 qsv_status build_plan(const qsv_circuit* circ, int dt, int fuse_k, const double* params_host,
                       qsv_plan* P)
 {
@@ -346,6 +454,7 @@ qsv_status build_plan(const qsv_circuit* circ, int dt, int fuse_k, const double*
                                            op.param);
             P->bytes += L.bytes;
             P->flops += L.flops;
+            L.qmask = op_qubits(op);
             P->launches.push_back(L);
             P->upload_off.push_back(-1);
             continue;
@@ -353,10 +462,22 @@ qsv_status build_plan(const qsv_circuit* circ, int dt, int fuse_k, const double*
         Built b = item_launch(circ, it, dt, params_host, false);
         if (b.noop)
             continue;
+        b.L.qmask = 0;
+        for (int o : it.ops)
+            b.L.qmask |= op_qubits(circ->ops[o]);
         P->bytes += b.L.bytes;
         P->flops += b.L.flops;
         P->upload_off.push_back(b.upload.empty() ? -1 : (long long)P->dev.add(std::move(b.upload)));
         P->launches.push_back(b.L);
+    }
+    const char* nodr = getenv("QSV_NO_DIAG_RUN");
+    if (!nodr || nodr[0] != '1') {
+        merge_diagonal_runs(P->launches, P->upload_off, P->n, dt);
+        P->bytes = P->flops = 0.0;
+        for (const GateLaunch& L : P->launches) {
+            P->bytes += L.bytes;
+            P->flops += L.flops;
+        }
     }
     qsv_status st = P->dev.commit();
     if (st)

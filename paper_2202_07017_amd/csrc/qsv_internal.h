@@ -23,7 +23,9 @@ enum Dt : int { C64 = 1, C128 = 2 };
 //          of the same group.
 enum Mode : int { W1 = 0, W2 = 1, INTRA = 2 };
 
-enum LaunchType : int { L_DENSE = 0, L_DIAG = 1, L_PERM = 2, L_MFMA = 3 };
+enum LaunchType : int { L_DENSE = 0, L_DIAG = 1, L_PERM = 2, L_MFMA = 3, L_DIAGRUN = 4 };
+
+constexpr int kMaxRunFactors = 16;  // diagonal gates merged into one L_DIAGRUN sweep
 
 // Rotation kinds read from a device parameter vector (values follow qsv_op_kind).
 enum Rot : int { ROT_NONE = 0, ROT_X = 5, ROT_Y = 6, ROT_Z = 7 };
@@ -63,10 +65,26 @@ struct GateLaunch {
     uint64_t choff[32] = {};
     int tloc[5] = {};
     int floc[6] = {};
+    // diagonal run: amplitude i is multiplied by run_d[f][tau_f(i)] for every
+    // factor f with (i & run_fix[f]) == run_val[f]; tau_f bit j = bit
+    // run_tpos[f][j] of i (run_nt[f] <= 2 varying bits)
+    int run_nf = 0;
+    uint64_t run_fix[kMaxRunFactors] = {};
+    uint64_t run_val[kMaxRunFactors] = {};
+    int run_nt[kMaxRunFactors] = {};
+    int run_tpos[kMaxRunFactors][2] = {};
+    double run_d[kMaxRunFactors][8] = {};
+    uint64_t qmask = ~0ull;  // every qubit the launch reads or writes (targets and controls)
     // accounting
     double bytes = 0.0;
     double flops = 0.0;
 };
+
+// plan.cpp
+// Merge runs of diagonal launches (no device parameters, at most two varying
+// bits each) into L_DIAGRUN sweeps where a full sweep is cheaper than the
+// separate launches' estimated traffic.
+void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& upload_off, int n, int dt);
 
 // kernels_gate.hip
 hipError_t launch_gate(const GateLaunch& L, void* psi, void* psi2, hipStream_t s);

@@ -61,3 +61,61 @@ def test_qft_full_size_basis(q, name):
         assert err <= TOL[name] and err / np.max(np.abs(want)) <= 1e-5, (fuse, err)
     del d
     torch.cuda.empty_cache()
+
+
+def _diag_circuit(n, seed):
+    """Runs of diagonal gates (CZ, controlled phases with 1-2 controls, random
+    two-qubit diagonals including non-unitary ones, Z, phases on low and high
+    qubits) separated by Hadamards."""
+    rng = np.random.default_rng(seed)
+    c = W.Circuit(n)
+    for layer in range(4):
+        for _ in range(3 * n):
+            kind = rng.integers(0, 5)
+            qs = [int(v) for v in rng.permutation(n)[:3]]
+            if kind == 0 and n >= 2:
+                c.ops.append(W.Op("z", (qs[0],), controls=(qs[1],)))
+            elif kind == 1 and n >= 3:
+                ph = np.exp(1j * rng.uniform(0, 2 * np.pi))
+                c.ops.append(W.Op("matrix", (qs[0],), controls=(qs[1], qs[2]),
+                                  matrix=np.diag([1.0, ph]).astype(np.complex128)))
+            elif kind == 2 and n >= 2:
+                d = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+                c.ops.append(W.Op("matrix", (qs[0], qs[1]), matrix=np.diag(d).astype(np.complex128)))
+            elif kind == 3:
+                c.ops.append(W.Op("z", (qs[0],)))
+            else:
+                ph = np.exp(1j * rng.uniform(0, 2 * np.pi, 2))
+                c.ops.append(W.Op("matrix", (qs[0],), matrix=np.diag(ph).astype(np.complex128)))
+        c.ops.append(W.Op("h", (layer % n,)))
+    return c
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("n", [3, 7, 12, 17])
+@pytest.mark.parametrize("fuse", [1, 3])
+def test_diagonal_runs(q, orc, name, n, fuse):
+    """Plans merge consecutive diagonal launches into single sweeps; results
+    match the oracle and the unmerged plan, with fewer launches."""
+    import os
+    circ = _diag_circuit(n, 40 + n)
+    rng = np.random.default_rng(n)
+    psi = rand_state(n, rng, name)
+    ref = orc.run(circ, psi0=psi)
+    say("diag runs", name, n, fuse)
+    d = to_gpu(psi, name)
+    merged = q.Plan(circ, _code(q, name), fuse)
+    merged.run(d)
+    got = to_np(d)
+    os.environ["QSV_NO_DIAG_RUN"] = "1"
+    try:
+        plain = q.Plan(circ, _code(q, name), fuse)
+    finally:
+        del os.environ["QSV_NO_DIAG_RUN"]
+    d2 = to_gpu(psi, name)
+    plain.run(d2)
+    scale = max(1.0, float(np.max(np.abs(ref))))
+    assert np.max(np.abs(got - ref)) <= TOL[name] * scale, np.max(np.abs(got - ref))
+    assert np.max(np.abs(to_np(d2) - ref)) <= TOL[name] * scale
+    if n >= 7:
+        assert merged.info()[0] < plain.info()[0], (merged.info(), plain.info())
