@@ -528,7 +528,11 @@ qsv_status stage_upload(const void* host, size_t bytes, hipStream_t s, const voi
 
 qsv_status launch_checked(const GateLaunch& L, void* psi, void* psi2, hipStream_t s)
 {
-    hipError_t e = launch_gate(L, psi, psi2, s);
+    hipError_t e;
+    if (L.type == L_DIAGRUN)
+        e = psi2 ? hipErrorInvalidValue : launch_diag_run(L, psi, s);
+    else
+        e = launch_gate(L, psi, psi2, s);
     if (e != hipSuccess)
         return fail(QSV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     return QSV_OK;

@@ -17,7 +17,6 @@
 // contiguous eighth of the state), nontemporal loads and stores once the
 // contiguous runs are >= 128 bytes, and a lane-exchange kernel for
 // uncontrolled single-qubit gates whose partner sits within 64 units.
-#include <cmath>
 #include <cstdlib>
 
 #include "qsv_internal.h"
@@ -448,66 +447,6 @@ __global__ void __launch_bounds__(kBlock) k_diag(R* __restrict__ psi0, R* __rest
     }
 }
 
-// ------------------------------------------------------------ diagonal runs
-
-// A run of diagonal gates applied in one sweep (diagonal matrices commute, so
-// the product's order is free): amplitude i is multiplied by d_f[tau_f(i)]
-// for every factor f whose fixed bits match.
-template <typename R>
-struct DiagRunK {
-    uint64_t nunits;  // 16-byte units of the state
-    int nf;
-    uint64_t fix[kMaxRunFactors];
-    uint64_t val[kMaxRunFactors];
-    int nt[kMaxRunFactors];
-    int tpos[kMaxRunFactors][2];
-    R d[kMaxRunFactors][8];
-};
-
-template <typename R>
-__device__ __forceinline__ void run_factor(const DiagRunK<R>& a, int f, uint64_t i, R& re, R& im)
-{
-    if ((i & a.fix[f]) != a.val[f])
-        return;
-    int t = 0;
-    if (a.nt[f] > 0)
-        t = (int)((i >> a.tpos[f][0]) & 1u);
-    if (a.nt[f] > 1)
-        t |= (int)((i >> a.tpos[f][1]) & 1u) << 1;
-    // uniform table, per-lane selection
-    const R dr = t == 0 ? a.d[f][0] : t == 1 ? a.d[f][2] : t == 2 ? a.d[f][4] : a.d[f][6];
-    const R di = t == 0 ? a.d[f][1] : t == 1 ? a.d[f][3] : t == 2 ? a.d[f][5] : a.d[f][7];
-    const R r = re * dr - im * di;
-    im = re * di + im * dr;
-    re = r;
-}
-
-template <typename R, bool NT>
-__global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const DiagRunK<R> a)
-{
-    const uint64_t step = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t u = xcd_block() * kBlock + threadIdx.x; u < a.nunits; u += step) {
-        if constexpr (sizeof(R) == 4) {
-            float4* p = reinterpret_cast<float4*>(psi);
-            const float4 x = ldv<NT>(&p[u]);
-            float ar = 1.0f, ai = 0.0f, br = 1.0f, bi = 0.0f;
-            for (int f = 0; f < a.nf; ++f) {
-                run_factor(a, f, u << 1, ar, ai);
-                run_factor(a, f, (u << 1) | 1u, br, bi);
-            }
-            stv<NT>(&p[u], make_float4(ar * x.x - ai * x.y, ar * x.y + ai * x.x, br * x.z - bi * x.w,
-                                       br * x.w + bi * x.z));
-        } else {
-            double2* p = reinterpret_cast<double2*>(psi);
-            const double2 x = ldv<NT>(&p[u]);
-            double ar = 1.0, ai = 0.0;
-            for (int f = 0; f < a.nf; ++f)
-                run_factor(a, f, u, ar, ai);
-            stv<NT>(&p[u], make_double2(ar * x.x - ai * x.y, ar * x.y + ai * x.x));
-        }
-    }
-}
-
 // ------------------------------------------------------------ permutation
 
 struct PermK {
@@ -839,26 +778,6 @@ hipError_t perm_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
 
 }  // namespace
 
-template <typename R>
-hipError_t diag_run_go(const GateLaunch& L, void* p, hipStream_t s)
-{
-    DiagRunK<R> a{};
-    a.nunits = L.ngroups;
-    a.nf = L.run_nf;
-    for (int f = 0; f < L.run_nf; ++f) {
-        a.fix[f] = L.run_fix[f];
-        a.val[f] = L.run_val[f];
-        a.nt[f] = L.run_nt[f];
-        a.tpos[f][0] = L.run_tpos[f][0];
-        a.tpos[f][1] = L.run_tpos[f][1];
-        for (int j = 0; j < 8; ++j)
-            a.d[f][j] = (R)L.run_d[f][j];
-    }
-    hipLaunchKernelGGL((k_diag_run<R, true>), dim3(grid_for(a.nunits, 1)), dim3(kBlock), 0, s,
-                       static_cast<R*>(p), a);
-    return hipGetLastError();
-}
-
 hipError_t launch_gate(const GateLaunch& L, void* psi, void* psi2, hipStream_t s)
 {
     if (L.ngroups == 0)
@@ -874,10 +793,6 @@ hipError_t launch_gate(const GateLaunch& L, void* psi, void* psi2, hipStream_t s
         return perm_go<uint4>(L, psi, psi2, s);
     case L_MFMA:
         return launch_mfma(L, psi, psi2, s);
-    case L_DIAGRUN:
-        if (psi2)
-            return hipErrorInvalidValue;
-        return L.dt == C64 ? diag_run_go<float>(L, psi, s) : diag_run_go<double>(L, psi, s);
     default:
         return hipErrorInvalidValue;
     }

@@ -86,6 +86,9 @@ struct GateLaunch {
 // separate launches' estimated traffic.
 void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& upload_off, int n, int dt);
 
+// kernels_diagrun.hip (L_DIAGRUN launches)
+hipError_t launch_diag_run(const GateLaunch& L, void* psi, hipStream_t s);
+
 // kernels_gate.hip
 hipError_t launch_gate(const GateLaunch& L, void* psi, void* psi2, hipStream_t s);
 hipError_t launch_init_basis(void* psi, int n, int dt, uint64_t index, hipStream_t s);
