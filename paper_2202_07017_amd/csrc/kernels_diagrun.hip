@@ -58,23 +58,24 @@ struct DiagRunK {
     uint64_t val[kMaxRunFactors];
     uint64_t dep[kMaxRunFactors];  // every bit the factor reads (fixed and varying)
     int nt[kMaxRunFactors];
-    int tpos[kMaxRunFactors][2];
-    R d[kMaxRunFactors][8];
+    int tpos[kMaxRunFactors][5];
+    int off[kMaxRunFactors];       // first complex entry of the factor's table
+    const R* tab;                  // all tables, (re, im), state precision
+    int ntab;                      // complex entries in tab
 };
 
+// Multiplies (re, im) by factor f's entry for amplitude i, if i's fixed bits
+// match; the tables sit in LDS.
 template <typename R>
-__device__ __forceinline__ void run_factor(const DiagRunK<R>& a, int f, uint64_t i, R& re, R& im)
+__device__ __forceinline__ void run_factor(const DiagRunK<R>& a, const R* sd, int f, uint64_t i, R& re,
+                                           R& im)
 {
     if ((i & a.fix[f]) != a.val[f])
         return;
     int t = 0;
-    if (a.nt[f] > 0)
-        t = (int)((i >> a.tpos[f][0]) & 1u);
-    if (a.nt[f] > 1)
-        t |= (int)((i >> a.tpos[f][1]) & 1u) << 1;
-    // uniform table, per-lane selection
-    const R dr = t == 0 ? a.d[f][0] : t == 1 ? a.d[f][2] : t == 2 ? a.d[f][4] : a.d[f][6];
-    const R di = t == 0 ? a.d[f][1] : t == 1 ? a.d[f][3] : t == 2 ? a.d[f][5] : a.d[f][7];
+    for (int b = 0; b < a.nt[f]; ++b)
+        t |= (int)((i >> a.tpos[f][b]) & 1u) << b;
+    const R dr = sd[2 * (a.off[f] + t)], di = sd[2 * (a.off[f] + t) + 1];
     const R r = re * dr - im * di;
     im = re * di + im * dr;
     re = r;
@@ -93,12 +94,16 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
     const uint64_t vary = (sizeof(R) == 4 ? 1ull : 0ull) | ((uint64_t)(kRunUPT - 1) << (8 + AS));
     const uint64_t seglen = (uint64_t)kBlock * kRunUPT;
     const uint64_t nseg = (a.nunits + seglen - 1) / seglen;
+    __shared__ R sd[2 * kMaxRunEntries];
+    for (int k = threadIdx.x; k < 2 * a.ntab; k += kBlock)
+        sd[k] = a.tab[k];
+    __syncthreads();
     for (uint64_t seg = xcd_block(); seg < nseg; seg += gridDim.x) {
         const uint64_t u0 = seg * seglen + threadIdx.x;
         R cr = (R)1, ci = (R)0;
         for (int f = 0; f < a.nf; ++f)
             if (!(a.dep[f] & vary))
-                run_factor(a, f, u0 << AS, cr, ci);
+                run_factor(a, sd, f, u0 << AS, cr, ci);
         for (int r = 0; r < kRunUPT; ++r) {
             const uint64_t u = u0 + (uint64_t)r * kBlock;
             if (u >= a.nunits)
@@ -109,8 +114,8 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
                 float ar = cr, ai = ci, br = cr, bi = ci;
                 for (int f = 0; f < a.nf; ++f)
                     if (a.dep[f] & vary) {
-                        run_factor(a, f, u << 1, ar, ai);
-                        run_factor(a, f, (u << 1) | 1u, br, bi);
+                        run_factor(a, sd, f, u << 1, ar, ai);
+                        run_factor(a, sd, f, (u << 1) | 1u, br, bi);
                     }
                 st_nt(&p[u], make_float4(ar * x.x - ai * x.y, ar * x.y + ai * x.x, br * x.z - bi * x.w,
                                            br * x.w + bi * x.z));
@@ -120,7 +125,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
                 double ar = cr, ai = ci;
                 for (int f = 0; f < a.nf; ++f)
                     if (a.dep[f] & vary)
-                        run_factor(a, f, u, ar, ai);
+                        run_factor(a, sd, f, u, ar, ai);
                 st_nt(&p[u], make_double2(ar * x.x - ai * x.y, ar * x.y + ai * x.x));
             }
         }
@@ -147,14 +152,17 @@ hipError_t diag_run_go(const GateLaunch& L, void* p, hipStream_t s)
         a.fix[f] = L.run_fix[f];
         a.val[f] = L.run_val[f];
         a.nt[f] = L.run_nt[f];
-        a.tpos[f][0] = L.run_tpos[f][0];
-        a.tpos[f][1] = L.run_tpos[f][1];
+        a.off[f] = L.run_off[f];
         a.dep[f] = L.run_fix[f];
-        for (int b = 0; b < L.run_nt[f]; ++b)
+        for (int b = 0; b < L.run_nt[f]; ++b) {
+            a.tpos[f][b] = L.run_tpos[f][b];
             a.dep[f] |= 1ull << L.run_tpos[f][b];
-        for (int j = 0; j < 8; ++j)
-            a.d[f][j] = (R)L.run_d[f][j];
+        }
     }
+    a.tab = static_cast<const R*>(L.gdev);
+    a.ntab = (int)(L.run_tab.size() / 2);
+    if (!a.tab || a.ntab > kMaxRunEntries)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_diag_run<R>), dim3(run_grid(a.nunits)), dim3(kBlock), 0, s,
                        static_cast<R*>(p), a);
     return hipGetLastError();

@@ -309,7 +309,7 @@ static double diag_cost(uint64_t fix, int S)
 
 static bool as_factor(const GateLaunch& L, uint64_t& fix, uint64_t& val)
 {
-    if (L.type != L_DIAG || L.rot != ROT_NONE || L.K > 2 || L.ngroups == 0)
+    if (L.type != L_DIAG || L.rot != ROT_NONE || L.K > 5 || L.ngroups == 0)
         return false;
     const int shift = L.mode == W2 ? 1 : 0;
     fix = 0;
@@ -349,8 +349,8 @@ void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& up
                 R.run_nt[f] = D.K;
                 for (int b = 0; b < D.K; ++b)
                     R.run_tpos[f][b] = D.tpos[b];
-                for (int t = 0; t < (2 << D.K); ++t)
-                    R.run_d[f][t] = D.g[t];
+                R.run_off[f] = (int)(R.run_tab.size() / 2);
+                R.run_tab.insert(R.run_tab.end(), D.g.begin(), D.g.begin() + (2 << D.K));
                 R.flops += 6.0 * std::ldexp(1.0, n);
             }
             R.bytes = 2.0 * S * std::ldexp(1.0, n);
@@ -473,6 +473,21 @@ qsv_status build_plan(const qsv_circuit* circ, int dt, int fuse_k, const double*
     const char* nodr = getenv("QSV_NO_DIAG_RUN");
     if (!nodr || nodr[0] != '1') {
         merge_diagonal_runs(P->launches, P->upload_off, P->n, dt);
+        for (size_t j = 0; j < P->launches.size(); ++j) {
+            const GateLaunch& L = P->launches[j];
+            if (L.type != L_DIAGRUN)
+                continue;
+            std::vector<unsigned char> bytes;
+            if (dt == QSV_C64) {
+                const std::vector<float> f(L.run_tab.begin(), L.run_tab.end());
+                const unsigned char* b = reinterpret_cast<const unsigned char*>(f.data());
+                bytes.assign(b, b + f.size() * sizeof(float));
+            } else {
+                const unsigned char* b = reinterpret_cast<const unsigned char*>(L.run_tab.data());
+                bytes.assign(b, b + L.run_tab.size() * sizeof(double));
+            }
+            P->upload_off[j] = (long long)P->dev.add(std::move(bytes));
+        }
         P->bytes = P->flops = 0.0;
         for (const GateLaunch& L : P->launches) {
             P->bytes += L.bytes;

@@ -26,6 +26,7 @@ enum Mode : int { W1 = 0, W2 = 1, INTRA = 2 };
 enum LaunchType : int { L_DENSE = 0, L_DIAG = 1, L_PERM = 2, L_MFMA = 3, L_DIAGRUN = 4 };
 
 constexpr int kMaxRunFactors = 16;  // diagonal gates merged into one L_DIAGRUN sweep
+constexpr int kMaxRunEntries = kMaxRunFactors * 32;  // table entries of one run
 
 // Rotation kinds read from a device parameter vector (values follow qsv_op_kind).
 enum Rot : int { ROT_NONE = 0, ROT_X = 5, ROT_Y = 6, ROT_Z = 7 };
@@ -65,15 +66,18 @@ struct GateLaunch {
     uint64_t choff[32] = {};
     int tloc[5] = {};
     int floc[6] = {};
-    // diagonal run: amplitude i is multiplied by run_d[f][tau_f(i)] for every
-    // factor f with (i & run_fix[f]) == run_val[f]; tau_f bit j = bit
-    // run_tpos[f][j] of i (run_nt[f] <= 2 varying bits)
+    // diagonal run: amplitude i is multiplied by entry tau_f(i) of factor f's
+    // table for every factor f with (i & run_fix[f]) == run_val[f]; tau_f bit j
+    // = bit run_tpos[f][j] of i (run_nt[f] <= 5 varying bits).  The tables
+    // (complex128, concatenated; factor f starts at complex entry run_off[f])
+    // are uploaded in state precision and reached through gdev.
     int run_nf = 0;
     uint64_t run_fix[kMaxRunFactors] = {};
     uint64_t run_val[kMaxRunFactors] = {};
     int run_nt[kMaxRunFactors] = {};
-    int run_tpos[kMaxRunFactors][2] = {};
-    double run_d[kMaxRunFactors][8] = {};
+    int run_tpos[kMaxRunFactors][5] = {};
+    int run_off[kMaxRunFactors] = {};
+    std::vector<double> run_tab;
     uint64_t qmask = ~0ull;  // every qubit the launch reads or writes (targets and controls)
     // accounting
     double bytes = 0.0;
