@@ -66,6 +66,7 @@ def lib():
             L.orc_adjoint.argtypes = circ + [_D, ctypes.c_int, ctypes.c_int, _U, _U, _D, _D, _D]
             L.orc_probabilities.argtypes = [ctypes.c_int, _D, _I, ctypes.c_int, _D]
             L.orc_sample.argtypes = [ctypes.c_int, _D, _D, ctypes.c_longlong, _L]
+            L.orc_frequencies.argtypes = [ctypes.c_int, _L, ctypes.c_longlong, _I, ctypes.c_int, _L]
             _lib = L
     return _lib
 
@@ -177,6 +178,17 @@ def trotter(psi, H, tau: float, steps: int, order: int = 1) -> np.ndarray:
     for _ in range(steps):
         for t, G in seq:
             out = apply(out, t, [], G)
+    return out
+
+
+def frequencies(n: int, samples, qubits) -> np.ndarray:
+    """Counts of the outcomes of `qubits` (first listed = most significant)
+    over whole-register samples of an n-qubit state (int64, 2**len(qubits))."""
+    smp = np.ascontiguousarray(samples, dtype=np.int64)
+    q = _ints(list(qubits))
+    out = np.zeros(1 << len(qubits), dtype=np.int64)
+    _check(lib().orc_frequencies(n, _p(smp, _L), smp.size, _p(q, _I), len(qubits), _p(out, _L)),
+           "frequencies")
     return out
 
 

@@ -750,3 +750,23 @@ int orc_sample(int n, const double* psi, const double* u, int64_t nshots, int64_
     free(C);
     return 0;
 }
+
+/* Frequencies of measured outcomes: counts[b] = number of shots s whose
+ * whole-register outcome samples[s] has bits q[0..m-1] spelling b (q[0] the
+ * most significant bit of b, as for marginals).  Plain loop over shots. */
+int orc_frequencies(int n, const int64_t* samples, int64_t nshots, const int* q, int m, int64_t* counts)
+{
+    if (n < 1 || n > 40 || m < 1 || m > n || nshots < 0)
+        return -1;
+    uint64_t seen = 0;
+    for (int j = 0; j < m; ++j) {
+        if (q[j] < 0 || q[j] >= n || ((seen >> q[j]) & 1ULL))
+            return -1;
+        seen |= 1ULL << q[j];
+    }
+    for (uint64_t b = 0; b < (1ULL << m); ++b)
+        counts[b] = 0;
+    for (int64_t s = 0; s < nshots; ++s)
+        counts[tau_of((uint64_t)samples[s], q, m)] += 1;
+    return 0;
+}

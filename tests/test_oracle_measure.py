@@ -137,3 +137,20 @@ def test_sample_frequencies_chi_square(orc):
     counts = np.bincount(orc.sample(psi, u), minlength=1 << n)
     stat, pval = scipy.stats.chisquare(counts, p * u.size / p.sum())
     assert pval > 1e-4, (stat, pval)
+
+
+def test_frequencies_match_bincount(orc):
+    """Counts over a qubit subset equal numpy's bincount of the outcome bits
+    extracted from each sample (first listed qubit most significant)."""
+    n = 9
+    r = np.random.default_rng(12)
+    samples = r.integers(0, 1 << n, 5000)
+    for qubits in ([0], [8, 0, 4], [3, 5, 7, 1], list(range(n - 1, -1, -1))):
+        m = len(qubits)
+        b = np.zeros(samples.size, dtype=np.int64)
+        for j, qq in enumerate(qubits):
+            b |= ((samples >> qq) & 1) << (m - 1 - j)
+        want = np.bincount(b, minlength=1 << m)
+        got = orc.frequencies(n, samples, qubits)
+        assert np.array_equal(got, want) and got.sum() == samples.size
+    assert orc.frequencies(n, np.zeros(0, dtype=np.int64), [2]).tolist() == [0, 0]
