@@ -208,6 +208,17 @@ qsv_status qsv_probabilities(const void* psi, int n, qsv_dtype dt, const int* qu
 qsv_status qsv_sample(const void* psi, int n, qsv_dtype dt, const double* u_dev, int64_t nshots,
                       int64_t* out_dev, void* work, void* stream);
 
+/* Frequencies of shot outcomes over the m distinct qubits qubits[0..m-1]
+ * (host array, 1 <= m <= min(n, 30)): counts_dev[b] = number of shots s whose
+ * outcome samples_dev[s] (whole-register indices, e.g. from qsv_sample) has
+ * bits qubits[0..m-1] spelling b, qubits[0] the MOST significant bit of b.
+ * samples_dev: nshots int64, device; counts_dev: 2^m int64, device, zeroed by
+ * the call itself (also for nshots == 0).  Only the measured bits of a sample
+ * are read.  Integer counts: the result is exact and deterministic.  Errors:
+ * as for qsv_probabilities, QSV_ERR_UNSUPPORTED for m > 30, nshots < 0. */
+qsv_status qsv_frequencies(const int64_t* samples_dev, int64_t nshots, int n, const int* qubits, int m,
+                           int64_t* counts_dev, void* stream);
+
 /* ------------------------------------------------------------- circuits */
 
 /* Gate kinds (Sec. 3: circuits of 1-, 2- and 3-qubit gates).  Rotations are

@@ -1058,3 +1058,23 @@ qsv_status qsv_sample(const void* psi, int n, qsv_dtype dt, const double* u_dev,
         return fail(QSV_ERR_HIP, "sample launch: %s", hipGetErrorString(e));
     return ok();
 }
+
+qsv_status qsv_frequencies(const int64_t* samples_dev, int64_t nshots, int n, const int* qubits, int m,
+                           int64_t* counts_dev, void* stream)
+{
+    if (n < 1 || n > QSV_MAX_QUBITS)
+        return fail(QSV_ERR_ARG, "n = %d outside [1, %d]", n, QSV_MAX_QUBITS);
+    qsv_status st = check_qubits(n, qubits, m, n, nullptr, 0);
+    if (st)
+        return st;
+    if (m > 30)
+        return fail(QSV_ERR_UNSUPPORTED, "m = %d measured qubits: at most 30 (2^m counters)", m);
+    if (nshots < 0)
+        return fail(QSV_ERR_ARG, "nshots = %lld is negative", (long long)nshots);
+    if (!counts_dev || (nshots > 0 && !samples_dev))
+        return fail(QSV_ERR_ARG, "samples_dev or counts_dev is NULL");
+    hipError_t e = launch_frequencies(samples_dev, nshots, n, qubits, m, counts_dev, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "frequencies launch: %s", hipGetErrorString(e));
+    return ok();
+}

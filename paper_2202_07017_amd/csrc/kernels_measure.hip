@@ -323,6 +323,46 @@ __global__ void __launch_bounds__(256) k_marginal_finalize(const double* __restr
         out[b] = acc;
 }
 
+// counts[b] += 1 for every shot whose outcome bits spell b.  Small outcome
+// spaces (2^m <= 4096) count per block in LDS first, then add each nonzero
+// bin once; larger ones add straight into device memory.  Integer sums, so
+// the result does not depend on the order of the atomics.
+constexpr int kFreqLds = 4096;
+
+template <bool LDSH>
+__global__ void __launch_bounds__(256) k_frequencies(const int64_t* __restrict__ samples, int64_t nshots,
+                                                     MeasSpec M, unsigned long long* __restrict__ counts)
+{
+    __shared__ unsigned int h[LDSH ? kFreqLds : 1];
+    const uint64_t nb = 1ull << M.m;
+    if (LDSH) {
+        for (uint64_t k = threadIdx.x; k < nb; k += 256)
+            h[k] = 0u;
+        __syncthreads();
+    }
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < nshots; s += stride) {
+        const uint64_t b = outcome_index((uint64_t)samples[s], M);
+        if (LDSH)
+            atomicAdd(&h[b], 1u);
+        else
+            atomicAdd(&counts[b], 1ull);
+    }
+    if (LDSH) {
+        __syncthreads();
+        for (uint64_t k = threadIdx.x; k < nb; k += 256)
+            if (h[k])
+                atomicAdd(&counts[k], (unsigned long long)h[k]);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_zero_counts(unsigned long long* p, uint64_t count)
+{
+    const uint64_t step = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += step)
+        p[i] = 0ull;
+}
+
 SampleTree sample_tree(int n)
 {
     SampleTree tr{};
@@ -429,6 +469,33 @@ hipError_t launch_marginal(const void* psi, int n, int dt, const int* q, int m, 
     const uint64_t nb = 1ull << m;
     hipLaunchKernelGGL(k_marginal_finalize, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s,
                        (const double*)work, nb, 1ull << ls, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_frequencies(const int64_t* samples, int64_t nshots, int n, const int* q, int m,
+                              int64_t* counts, hipStream_t s)
+{
+    MeasSpec M{};
+    M.m = m;
+    uint64_t mm = 0;
+    for (int j = 0; j < m; ++j) {
+        M.q[j] = q[j];
+        mm |= 1ull << q[j];
+    }
+    M.umask = ((1ull << n) - 1) & ~mm;
+    const uint64_t nb = 1ull << m;
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(counts);
+    const uint64_t zb = (nb + 255) / 256;
+    hipLaunchKernelGGL(k_zero_counts, dim3((unsigned)(zb < 65536 ? zb : 65536)), dim3(256), 0, s, c, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nshots == 0)
+        return e;
+    const int64_t blocks = (nshots + 255) / 256;
+    const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
+    if (nb <= (uint64_t)kFreqLds)
+        hipLaunchKernelGGL(k_frequencies<true>, dim3(grid), dim3(256), 0, s, samples, nshots, M, c);
+    else
+        hipLaunchKernelGGL(k_frequencies<false>, dim3(grid), dim3(256), 0, s, samples, nshots, M, c);
     return hipGetLastError();
 }
 

@@ -80,6 +80,8 @@ _SIGS = {
                           ctypes.c_int),
     "qsv_sample": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int64, _vp, _vp, _vp],
                    ctypes.c_int),
+    "qsv_frequencies": ([_vp, ctypes.c_int64, ctypes.c_int, _I, ctypes.c_int, _vp, _vp],
+                        ctypes.c_int),
     "qsv_plan_create": ([ctypes.POINTER(qsv_circuit), ctypes.c_int, ctypes.c_int, _D,
                          ctypes.POINTER(_vp)], ctypes.c_int),
     "qsv_trotter_plan_create": ([ctypes.POINTER(qsv_pauli_sum), ctypes.c_int, ctypes.c_double,
@@ -343,6 +345,20 @@ def qsv_sample(psi, u, out=None, stream=None):
     work = measure_workspace(n, dtype_code(psi), psi.device)
     _check(lib().qsv_sample(_ptr(psi), n, dtype_code(psi), _ptr(u), u.numel(), _ptr(out),
                             _ptr(work), _stream(stream)))
+    return out
+
+
+def qsv_frequencies(samples, n: int, qubits: Sequence[int], out=None, stream=None, order="little"):
+    """Counts (int64 device tensor of 2**len(qubits)) of the outcomes of
+    `qubits` (first listed = most significant) over whole-register samples."""
+    import torch
+    if samples.dtype != torch.int64 or not samples.is_contiguous():
+        raise ValueError("samples must be a contiguous int64 device tensor")
+    q = _ints(map_qubits(qubits, n, order))
+    out = out if out is not None else torch.empty(1 << len(qubits), dtype=torch.int64,
+                                                  device=samples.device)
+    _check(lib().qsv_frequencies(_ptr(samples), samples.numel(), n, q, len(qubits), _ptr(out),
+                                 _stream(stream)))
     return out
 
 

@@ -191,3 +191,39 @@ def test_full_size_n32_uniform(q):
             assert np.all(pr == 2.0 ** -len(qs))
         del psi
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,qubits", [(12, [0]), (12, [11, 0, 5]), (12, list(range(11, -1, -1))),
+                                      (14, [13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2, 1]), (30, [29, 0, 15])])
+def test_frequencies_parity(q, orc, n, qubits):
+    """Counts of GPU shots over a qubit subset equal the oracle's counts of the
+    same shots exactly (the LDS path for 2^m <= 4096, the device path above)."""
+    import torch
+    rng = np.random.default_rng(70 + n)
+    if n <= 20:
+        psi = rand_state(n, rng, "c128")
+        d = to_gpu(psi, "c128")
+    else:
+        d = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+        q.qsv_init_random(d, 7)
+    u = W.uniforms(300000, 5 + n)
+    say("frequencies", n, qubits)
+    smp = q.qsv_sample(d, _u_gpu(u))
+    got = q.qsv_frequencies(smp, n, qubits).cpu().numpy()
+    want = orc.frequencies(n, smp.cpu().numpy(), qubits)
+    assert np.array_equal(got, want) and got.sum() == u.size
+    del d
+    torch.cuda.empty_cache()
+
+
+def test_frequencies_edges(q):
+    import torch
+    out = torch.full((4,), 9, dtype=torch.int64, device="cuda")
+    q.qsv_frequencies(torch.zeros(0, dtype=torch.int64, device="cuda"), 5, [4, 1], out=out)
+    assert out.cpu().tolist() == [0, 0, 0, 0]
+    s = torch.tensor([3, 3, 0, 31], dtype=torch.int64, device="cuda")
+    assert q.qsv_frequencies(s, 5, [1, 0]).cpu().tolist() == [1, 0, 0, 3]
+    with pytest.raises(q.QsvError):
+        q.qsv_frequencies(s, 5, [5])
+    with pytest.raises(q.QsvError):
+        q.qsv_frequencies(s, 5, [1, 1])
