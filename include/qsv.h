@@ -13,8 +13,10 @@
  * gates), fused dense blocks of up to 5 qubits, expectation values of
  * Pauli-sum Hamiltonians (Sec. 3, Hamiltonian primitives), adjoint-method
  * gradients of parametrised rotation circuits (the gradient role Sec. 2
- * gives to automatic differentiation, Sec. 3 variational layers / VQE), and
- * a batched mode that evaluates many small circuits in one persistent launch.
+ * gives to automatic differentiation, Sec. 3 variational layers / VQE), a
+ * batched mode that evaluates many small circuits in one persistent launch,
+ * simulated measurement (marginal probabilities, shot sampling, outcome
+ * frequencies; Sec. 3) and Trotterised time evolution of Pauli sums (Sec. 3).
  *
  * Conventions shared by every call
  * --------------------------------
