@@ -67,6 +67,8 @@ def lib():
             L.orc_probabilities.argtypes = [ctypes.c_int, _D, _I, ctypes.c_int, _D]
             L.orc_sample.argtypes = [ctypes.c_int, _D, _D, ctypes.c_longlong, _L]
             L.orc_frequencies.argtypes = [ctypes.c_int, _L, ctypes.c_longlong, _I, ctypes.c_int, _L]
+            L.orc_collapse.argtypes = [ctypes.c_int, _D, _D, _I, ctypes.c_int, ctypes.c_uint64,
+                                       ctypes.c_double]
             _lib = L
     return _lib
 
@@ -189,6 +191,18 @@ def frequencies(n: int, samples, qubits) -> np.ndarray:
     out = np.zeros(1 << len(qubits), dtype=np.int64)
     _check(lib().orc_frequencies(n, _p(smp, _L), smp.size, _p(q, _I), len(qubits), _p(out, _L)),
            "frequencies")
+    return out
+
+
+def collapse(psi, qubits, outcome: int, p: float) -> np.ndarray:
+    """State after measuring `qubits` (first listed = most significant) with
+    result `outcome` of probability p: projected and divided by sqrt(p)."""
+    psi = _as_c128(psi)
+    n = int(psi.size).bit_length() - 1
+    q = _ints(list(qubits))
+    out = np.empty_like(psi)
+    _check(lib().orc_collapse(n, _p(psi, _D), _p(out, _D), _p(q, _I), len(qubits), int(outcome),
+                              float(p)), "collapse")
     return out
 
 

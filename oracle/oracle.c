@@ -770,3 +770,27 @@ int orc_frequencies(int n, const int64_t* samples, int64_t nshots, const int* q,
         counts[tau_of((uint64_t)samples[s], q, m)] += 1;
     return 0;
 }
+
+/* Post-measurement state (Sec. 3: measurements; projective collapse): for the
+ * outcome b of qubits q[0..m-1] (q[0] the most significant bit of b) with
+ * probability p, out[i] = psi[i] / sqrt(p) where the bits of i at q spell b,
+ * and 0 elsewhere.  p <= 0 (an impossible outcome) gives the zero vector. */
+int orc_collapse(int n, const double* psi, double* out, const int* q, int m, uint64_t b, double p)
+{
+    if (n < 1 || n > 40 || m < 1 || m > n || (m < 64 && b >= (1ULL << m)))
+        return -1;
+    uint64_t seen = 0;
+    for (int j = 0; j < m; ++j) {
+        if (q[j] < 0 || q[j] >= n || ((seen >> q[j]) & 1ULL))
+            return -1;
+        seen |= 1ULL << q[j];
+    }
+    const uint64_t N = 1ULL << n;
+    const double s = p > 0.0 ? 1.0 / sqrt(p) : 0.0;
+    for (uint64_t i = 0; i < N; ++i) {
+        const int keep = tau_of(i, q, m) == b;
+        out[2 * i] = keep ? psi[2 * i] * s : 0.0;
+        out[2 * i + 1] = keep ? psi[2 * i + 1] * s : 0.0;
+    }
+    return 0;
+}

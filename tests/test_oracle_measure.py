@@ -154,3 +154,40 @@ def test_frequencies_match_bincount(orc):
         got = orc.frequencies(n, samples, qubits)
         assert np.array_equal(got, want) and got.sum() == samples.size
     assert orc.frequencies(n, np.zeros(0, dtype=np.int64), [2]).tolist() == [0, 0]
+
+
+def test_collapse_matches_projector(orc):
+    """Collapse equals the normalised projection (I (x) |b><b| (x) I) psi built
+    from Kronecker products of 2x2 projectors; the result has unit norm and
+    the measured qubits then give outcome b with probability 1."""
+    n = 6
+    psi = rand_state(n, 21)
+    for qubits, b in (([0], 1), ([5, 2], 2), ([1, 3, 4], 5)):
+        P = np.ones((1, 1))
+        m = len(qubits)
+        for q in range(n - 1, -1, -1):                 # qubit n-1 is the leftmost factor
+            if q in qubits:
+                bit = (b >> (m - 1 - qubits.index(q))) & 1
+                P = np.kron(P, np.diag([1.0 - bit, float(bit)]))
+            else:
+                P = np.kron(P, np.eye(2))
+        proj = P @ psi
+        p = float(np.vdot(proj, proj).real)
+        got = orc.collapse(psi, qubits, b, p)
+        assert np.max(np.abs(got - proj / np.sqrt(p))) <= 1e-15
+        assert abs(np.linalg.norm(got) - 1) <= 1e-14
+        pr = orc.probabilities(got, qubits)
+        assert abs(pr[b] - 1) <= 1e-14 and abs(pr.sum() - 1) <= 1e-14
+
+
+def test_collapse_ghz_and_impossible(orc):
+    n = 5
+    ghz = np.zeros(1 << n, dtype=np.complex128)
+    ghz[0] = ghz[-1] = 1 / np.sqrt(2)
+    got = orc.collapse(ghz, [2], 1, 0.5)
+    want = np.zeros(1 << n)
+    want[-1] = 1.0
+    assert np.max(np.abs(got - want)) <= 1e-15
+    assert np.all(orc.collapse(ghz, [2], 1, 0.0) == 0)
+    with pytest.raises(ValueError):
+        orc.collapse(ghz, [2], 2, 0.5)
