@@ -221,6 +221,17 @@ qsv_status qsv_sample(const void* psi, int n, qsv_dtype dt, const double* u_dev,
 qsv_status qsv_frequencies(const int64_t* samples_dev, int64_t nshots, int n, const int* qubits, int m,
                            int64_t* counts_dev, void* stream);
 
+/* State after a measurement (Sec. 3: measurements; projective collapse):
+ * for the outcome `outcome` of the m distinct qubits qubits[0..m-1]
+ * (qubits[0] the MOST significant bit of the outcome), amplitudes whose bits
+ * at those qubits spell the outcome are divided by sqrt(prob_dev[0]) and every
+ * other amplitude is set to 0, in place.  prob_dev: 1 double, device (e.g. the
+ * outcome's entry of qsv_probabilities, so the call needs no host round
+ * trip); prob_dev[0] <= 0 leaves the zero vector.  Errors: as for
+ * qsv_probabilities, QSV_ERR_ARG for an outcome >= 2^m or a NULL prob_dev. */
+qsv_status qsv_collapse(void* psi, int n, qsv_dtype dt, const int* qubits, int m, uint64_t outcome,
+                        const double* prob_dev, void* stream);
+
 /* ------------------------------------------------------------- circuits */
 
 /* Gate kinds (Sec. 3: circuits of 1-, 2- and 3-qubit gates).  Rotations are

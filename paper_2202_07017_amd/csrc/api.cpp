@@ -1078,3 +1078,21 @@ qsv_status qsv_frequencies(const int64_t* samples_dev, int64_t nshots, int n, co
         return fail(QSV_ERR_HIP, "frequencies launch: %s", hipGetErrorString(e));
     return ok();
 }
+
+qsv_status qsv_collapse(void* psi, int n, qsv_dtype dt, const int* qubits, int m, uint64_t outcome,
+                        const double* prob_dev, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if ((st = check_qubits(n, qubits, m, n, nullptr, 0)))
+        return st;
+    if (m < 64 && outcome >> m)
+        return fail(QSV_ERR_ARG, "outcome %llu needs more than m = %d bits", (unsigned long long)outcome, m);
+    if (!prob_dev)
+        return fail(QSV_ERR_ARG, "prob_dev is NULL");
+    hipError_t e = launch_collapse(psi, n, dt, qubits, m, outcome, prob_dev, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "collapse launch: %s", hipGetErrorString(e));
+    return ok();
+}

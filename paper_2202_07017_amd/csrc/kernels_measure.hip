@@ -363,6 +363,33 @@ __global__ void __launch_bounds__(256) k_zero_counts(unsigned long long* p, uint
         p[i] = 0ull;
 }
 
+// Projective collapse: amplitudes whose measured bits (mask) differ from want
+// become 0, the others are scaled by 1 / sqrt(p), p read from device memory
+// (p <= 0: the zero vector).  One read+write sweep, 16-byte units.
+template <typename R>
+__global__ void __launch_bounds__(256) k_collapse(R* __restrict__ psi, uint64_t nunits, uint64_t mask,
+                                                  uint64_t want, const double* __restrict__ prob)
+{
+    const double p = *prob;
+    const double sd = p > 0.0 ? 1.0 / sqrt(p) : 0.0;
+    const R sc = (R)sd;
+    const uint64_t step = (uint64_t)gridDim.x * 256;
+    for (uint64_t u = (uint64_t)blockIdx.x * 256 + threadIdx.x; u < nunits; u += step) {
+        if constexpr (sizeof(R) == 4) {
+            float4* q = reinterpret_cast<float4*>(psi);
+            float4 x = q[u];
+            const float s0 = ((u << 1) & mask) == want ? sc : 0.0f;
+            const float s1 = (((u << 1) | 1u) & mask) == want ? sc : 0.0f;
+            q[u] = make_float4(x.x * s0, x.y * s0, x.z * s1, x.w * s1);
+        } else {
+            double2* q = reinterpret_cast<double2*>(psi);
+            double2 x = q[u];
+            const double s0 = (u & mask) == want ? sc : 0.0;
+            q[u] = make_double2(x.x * s0, x.y * s0);
+        }
+    }
+}
+
 SampleTree sample_tree(int n)
 {
     SampleTree tr{};
@@ -496,6 +523,26 @@ hipError_t launch_frequencies(const int64_t* samples, int64_t nshots, int n, con
         hipLaunchKernelGGL(k_frequencies<true>, dim3(grid), dim3(256), 0, s, samples, nshots, M, c);
     else
         hipLaunchKernelGGL(k_frequencies<false>, dim3(grid), dim3(256), 0, s, samples, nshots, M, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_collapse(void* psi, int n, int dt, const int* q, int m, uint64_t outcome,
+                           const double* prob, hipStream_t s)
+{
+    uint64_t mask = 0, want = 0;
+    for (int j = 0; j < m; ++j) {
+        mask |= 1ull << q[j];
+        want |= ((outcome >> (m - 1 - j)) & 1ull) << q[j];
+    }
+    const uint64_t nunits = dt == C64 ? (1ull << n) / 2 : (1ull << n);
+    const uint64_t blocks = (nunits + 1023) / 1024;
+    const unsigned grid = (unsigned)(blocks < (1ull << 20) ? (blocks ? blocks : 1) : (1ull << 20));
+    if (dt == C64)
+        hipLaunchKernelGGL(k_collapse<float>, dim3(grid), dim3(256), 0, s, static_cast<float*>(psi), nunits,
+                           mask, want, prob);
+    else
+        hipLaunchKernelGGL(k_collapse<double>, dim3(grid), dim3(256), 0, s, static_cast<double*>(psi), nunits,
+                           mask, want, prob);
     return hipGetLastError();
 }
 

@@ -133,6 +133,8 @@ hipError_t launch_sample(const void* psi, int n, int dt, const double* u, int64_
                          double* work, hipStream_t s);
 hipError_t launch_marginal(const void* psi, int n, int dt, const int* q, int m, double* out, double* work,
                            hipStream_t s);
+hipError_t launch_collapse(void* psi, int n, int dt, const int* q, int m, uint64_t outcome,
+                           const double* prob, hipStream_t s);
 hipError_t launch_frequencies(const int64_t* samples, int64_t nshots, int n, const int* q, int m,
                               int64_t* counts, hipStream_t s);
 

@@ -80,6 +80,8 @@ _SIGS = {
                           ctypes.c_int),
     "qsv_sample": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int64, _vp, _vp, _vp],
                    ctypes.c_int),
+    "qsv_collapse": ([_vp, ctypes.c_int, ctypes.c_int, _I, ctypes.c_int, ctypes.c_uint64, _vp, _vp],
+                     ctypes.c_int),
     "qsv_frequencies": ([_vp, ctypes.c_int64, ctypes.c_int, _I, ctypes.c_int, _vp, _vp],
                         ctypes.c_int),
     "qsv_plan_create": ([ctypes.POINTER(qsv_circuit), ctypes.c_int, ctypes.c_int, _D,
@@ -346,6 +348,19 @@ def qsv_sample(psi, u, out=None, stream=None):
     _check(lib().qsv_sample(_ptr(psi), n, dtype_code(psi), _ptr(u), u.numel(), _ptr(out),
                             _ptr(work), _stream(stream)))
     return out
+
+
+def qsv_collapse(psi, qubits: Sequence[int], outcome: int, prob, stream=None, order="little"):
+    """Project psi onto `outcome` of `qubits` (first listed = most significant)
+    and divide by sqrt(prob[0]) (prob: float64 device tensor, e.g. a slice of
+    qsv_probabilities' result), in place."""
+    import torch
+    if prob.dtype != torch.float64:
+        raise ValueError("prob must be a float64 device tensor")
+    n = _nqubits(psi)
+    q = _ints(map_qubits(qubits, n, order))
+    _check(lib().qsv_collapse(_ptr(psi), n, dtype_code(psi), q, len(qubits), int(outcome), _ptr(prob),
+                              _stream(stream)))
 
 
 def qsv_frequencies(samples, n: int, qubits: Sequence[int], out=None, stream=None, order="little"):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import rand_state, say, to_gpu, torch_dtype
+from gpu_util import TOL, rand_state, say, to_gpu, to_np, torch_dtype
 
 pytestmark = pytest.mark.gpu
 DTYPES = ("c128", "c64")
@@ -227,3 +227,51 @@ def test_frequencies_edges(q):
         q.qsv_frequencies(s, 5, [5])
     with pytest.raises(q.QsvError):
         q.qsv_frequencies(s, 5, [1, 1])
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("n,qubits", [(1, [0]), (5, [4, 1]), (12, [0, 11, 6]), (20, [19, 3, 7, 12, 0])])
+def test_collapse_parity(q, orc, name, n, qubits):
+    """Collapse on the outcome's probability taken from qsv_probabilities on
+    the device, against the oracle's projection with the oracle's marginal."""
+    rng = np.random.default_rng(300 + n)
+    psi = rand_state(n, rng, name)
+    d = to_gpu(psi, name)
+    pr = q.qsv_probabilities(d, qubits)
+    b = int(np.argmax(pr.cpu().numpy()))
+    say("collapse", name, n, qubits, b)
+    q.qsv_collapse(d, qubits, b, pr[b:b + 1])
+    ref = orc.collapse(psi, qubits, b, orc.probabilities(psi, qubits)[b])
+    err = np.max(np.abs(to_np(d) - ref))
+    assert err <= TOL[name], err
+    assert abs(float(q.qsv_norm2(d).cpu()[0]) - 1.0) <= (1e-12 if name == "c128" else 1e-5)
+
+
+def test_collapse_full_size_n30(q):
+    """n = 30 complex64: a product state collapsed on qubits (29, 0, 15) with
+    outcome 0b101 equals the product state with those qubits fixed to 1, 0, 1
+    (closed form, sampled), and has unit norm."""
+    import torch
+    n = 30
+    theta = np.random.default_rng(33).uniform(0.3, 2.8, n)
+    d = _product_state(q, n, "c64", theta)
+    qs, b = [29, 0, 15], 0b101
+    pr = q.qsv_probabilities(d, qs)
+    say("collapse n30")
+    q.qsv_collapse(d, qs, b, pr[b:b + 1])
+    rng = np.random.default_rng(34)
+    idx = rng.integers(0, 1 << n, 300)
+    idx = np.concatenate([idx, (idx | (1 << 29) | (1 << 15)) & ~1])   # half of them on the outcome
+    got = d[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().astype(np.complex128)
+    want = np.ones(idx.size, dtype=np.complex128)
+    for j in range(n):
+        bit = (idx >> j) & 1
+        if j in qs:
+            need = (b >> (2 - qs.index(j))) & 1
+            want *= (bit == need)
+        else:
+            want *= np.where(bit == 0, np.cos(theta[j] / 2), np.sin(theta[j] / 2))
+    assert np.max(np.abs(got - want)) <= 1e-5 * max(1.0, float(np.max(np.abs(want)))) + 1e-9
+    assert abs(float(q.qsv_norm2(d).cpu()[0]) - 1.0) <= 1e-5
+    del d
+    torch.cuda.empty_cache()
