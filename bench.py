@@ -299,8 +299,9 @@ def measure_leg(qsv, W, torch, np, dev, stream, n=30, shots=1 << 20):
     """Simulated measurement on the seeded 30-qubit state: marginal
     probabilities of 1, 10 (lowest / highest) and 20 qubits (GB/s = one read
     of the state / time), and shot sampling: the prefix pass alone (one shot)
-    and 2^20 shots, giving the pass's GB/s and the per-shot rate, and the
-    frequencies of those shots over 10 qubits."""
+    and 2^20 shots, giving the pass's GB/s and the per-shot rate, the
+    frequencies of those shots over 10 qubits, and the collapse sweep onto one
+    outcome of 3 qubits (GB/s = read + write of the state / time)."""
     res = {}
     u = torch.from_numpy(W.uniforms(shots, 2024)).to(dev)
     for name, dt, S in (("c64", torch.complex64, 8), ("c128", torch.complex128, 16)):
@@ -322,6 +323,9 @@ def measure_leg(qsv, W, torch, np, dev, stream, n=30, shots=1 << 20):
         cnt = torch.empty(1 << 10, dtype=torch.int64, device=dev)
         tf = event_time(lambda: qsv.qsv_frequencies(samples, n, list(range(9, -1, -1)), out=cnt), 5, stream)
         row["frequencies_10q_%d_shots_ms" % shots] = round(tf * 1e3, 3)
+        pr = qsv.qsv_probabilities(psi, [29, 0, 15])
+        tc = event_time(lambda: qsv.qsv_collapse(psi, [29, 0, 15], 5, pr[5:6]), 3, stream)
+        row["collapse_gbs"] = round(2.0 * S * (1 << n) / tc / 1e9, 1)
         res[name] = row
         del psi, out, samples
         torch.cuda.empty_cache()
