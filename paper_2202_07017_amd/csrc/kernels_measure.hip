@@ -364,8 +364,12 @@ __global__ void __launch_bounds__(256) k_zero_counts(unsigned long long* p, uint
 }
 
 // Projective collapse: amplitudes whose measured bits (mask) differ from want
-// become 0, the others are scaled by 1 / sqrt(p), p read from device memory
-// (p <= 0: the zero vector).  One read+write sweep, 16-byte units.
+// become +0, the others are scaled by 1 / sqrt(p), p read from device memory
+// (p <= 0: the zero vector).  One read+write sweep of 16-byte units with the
+// nontemporal hint (every line is touched once).
+typedef float nv4f __attribute__((ext_vector_type(4)));
+typedef double nv2d __attribute__((ext_vector_type(2)));
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_collapse(R* __restrict__ psi, uint64_t nunits, uint64_t mask,
                                                   uint64_t want, const double* __restrict__ prob)
@@ -376,16 +380,23 @@ __global__ void __launch_bounds__(256) k_collapse(R* __restrict__ psi, uint64_t 
     const uint64_t step = (uint64_t)gridDim.x * 256;
     for (uint64_t u = (uint64_t)blockIdx.x * 256 + threadIdx.x; u < nunits; u += step) {
         if constexpr (sizeof(R) == 4) {
-            float4* q = reinterpret_cast<float4*>(psi);
-            float4 x = q[u];
-            const float s0 = ((u << 1) & mask) == want ? sc : 0.0f;
-            const float s1 = (((u << 1) | 1u) & mask) == want ? sc : 0.0f;
-            q[u] = make_float4(x.x * s0, x.y * s0, x.z * s1, x.w * s1);
+            nv4f* q = reinterpret_cast<nv4f*>(psi);
+            const nv4f x = __builtin_nontemporal_load(&q[u]);
+            const bool k0 = ((u << 1) & mask) == want, k1 = (((u << 1) | 1u) & mask) == want;
+            nv4f y;
+            y[0] = k0 ? x[0] * sc : 0.0f;
+            y[1] = k0 ? x[1] * sc : 0.0f;
+            y[2] = k1 ? x[2] * sc : 0.0f;
+            y[3] = k1 ? x[3] * sc : 0.0f;
+            __builtin_nontemporal_store(y, &q[u]);
         } else {
-            double2* q = reinterpret_cast<double2*>(psi);
-            double2 x = q[u];
-            const double s0 = (u & mask) == want ? sc : 0.0;
-            q[u] = make_double2(x.x * s0, x.y * s0);
+            nv2d* q = reinterpret_cast<nv2d*>(psi);
+            const nv2d x = __builtin_nontemporal_load(&q[u]);
+            const bool k0 = (u & mask) == want;
+            nv2d y;
+            y[0] = k0 ? x[0] * sc : 0.0;
+            y[1] = k0 ? x[1] * sc : 0.0;
+            __builtin_nontemporal_store(y, &q[u]);
         }
     }
 }
