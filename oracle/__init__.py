@@ -67,6 +67,7 @@ def lib():
             L.orc_probabilities.argtypes = [ctypes.c_int, _D, _I, ctypes.c_int, _D]
             L.orc_sample.argtypes = [ctypes.c_int, _D, _D, ctypes.c_longlong, _L]
             L.orc_frequencies.argtypes = [ctypes.c_int, _L, ctypes.c_longlong, _I, ctypes.c_int, _L]
+            L.orc_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_longlong, _D]
             L.orc_collapse.argtypes = [ctypes.c_int, _D, _D, _I, ctypes.c_int, ctypes.c_uint64,
                                        ctypes.c_double]
             _lib = L
@@ -192,6 +193,14 @@ def frequencies(n: int, samples, qubits) -> np.ndarray:
     _check(lib().orc_frequencies(n, _p(smp, _L), smp.size, _p(q, _I), len(qubits), _p(out, _L)),
            "frequencies")
     return out
+
+
+def seeded_uniforms(seed: int, count: int) -> np.ndarray:
+    """u[s] = top 53 bits of SplitMix64(seed xor s) / 2^53 (the counter-based
+    stream that seeded sampling draws)."""
+    out = np.zeros(max(count, 1))
+    _check(lib().orc_uniforms(seed, count, _p(out, _D)), "uniforms")
+    return out[:count]
 
 
 def collapse(psi, qubits, outcome: int, p: float) -> np.ndarray:

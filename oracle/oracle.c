@@ -794,3 +794,14 @@ int orc_collapse(int n, const double* psi, double* out, const int* q, int m, uin
     }
     return 0;
 }
+
+/* Seeded uniforms for sampling: u[s] = (SplitMix64(seed xor s) >> 11) / 2^53,
+ * the top 53 bits of the generator's output at counter s, in [0, 1). */
+int orc_uniforms(uint64_t seed, int64_t count, double* u)
+{
+    if (count < 0)
+        return -1;
+    for (int64_t s = 0; s < count; ++s)
+        u[s] = (double)(splitmix64_at(seed ^ (uint64_t)s) >> 11) * (1.0 / 9007199254740992.0);
+    return 0;
+}

@@ -191,3 +191,15 @@ def test_collapse_ghz_and_impossible(orc):
     assert np.all(orc.collapse(ghz, [2], 1, 0.0) == 0)
     with pytest.raises(ValueError):
         orc.collapse(ghz, [2], 2, 0.5)
+
+
+def test_seeded_uniforms_are_uniform(orc):
+    """The counter-based uniforms (SplitMix64, whose output function is pinned
+    against its published vector elsewhere) lie in [0, 1), differ per seed and
+    pass a Kolmogorov-Smirnov test against U[0, 1)."""
+    u = orc.seeded_uniforms(2024, 100000)
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert scipy.stats.kstest(u, "uniform").pvalue > 1e-4
+    v = orc.seeded_uniforms(2025, 100000)
+    assert not np.array_equal(u[:100], v[:100])
+    assert np.array_equal(orc.seeded_uniforms(2024, 10), u[:10])
