@@ -210,6 +210,12 @@ qsv_status qsv_probabilities(const void* psi, int n, qsv_dtype dt, const int* qu
 qsv_status qsv_sample(const void* psi, int n, qsv_dtype dt, const double* u_dev, int64_t nshots,
                       int64_t* out_dev, void* work, void* stream);
 
+/* qsv_sample with the uniforms drawn on the device from a counter-based
+ * stream: u[s] = (SplitMix64(seed xor s) >> 11) / 2^53 (SplitMix64: Steele,
+ * Lea & Flood 2014), so no uniform array is needed. */
+qsv_status qsv_sample_seeded(const void* psi, int n, qsv_dtype dt, uint64_t seed, int64_t nshots,
+                             int64_t* out_dev, void* work, void* stream);
+
 /* Frequencies of shot outcomes over the m distinct qubits qubits[0..m-1]
  * (host array, 1 <= m <= min(n, 30)): counts_dev[b] = number of shots s whose
  * outcome samples_dev[s] (whole-register indices, e.g. from qsv_sample) has

@@ -1052,7 +1052,7 @@ qsv_status qsv_sample(const void* psi, int n, qsv_dtype dt, const double* u_dev,
         return ok();
     if (!u_dev || !out_dev || !work)
         return fail(QSV_ERR_ARG, "u_dev, out_dev or work is NULL");
-    hipError_t e = launch_sample(psi, n, dt, u_dev, nshots, out_dev, static_cast<double*>(work),
+    hipError_t e = launch_sample(psi, n, dt, u_dev, 0, 0, nshots, out_dev, static_cast<double*>(work),
                                  (hipStream_t)stream);
     if (e != hipSuccess)
         return fail(QSV_ERR_HIP, "sample launch: %s", hipGetErrorString(e));
@@ -1094,5 +1094,24 @@ qsv_status qsv_collapse(void* psi, int n, qsv_dtype dt, const int* qubits, int m
     hipError_t e = launch_collapse(psi, n, dt, qubits, m, outcome, prob_dev, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail(QSV_ERR_HIP, "collapse launch: %s", hipGetErrorString(e));
+    return ok();
+}
+
+qsv_status qsv_sample_seeded(const void* psi, int n, qsv_dtype dt, uint64_t seed, int64_t nshots,
+                             int64_t* out_dev, void* work, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if (nshots < 0)
+        return fail(QSV_ERR_ARG, "nshots = %lld is negative", (long long)nshots);
+    if (nshots == 0)
+        return ok();
+    if (!out_dev || !work)
+        return fail(QSV_ERR_ARG, "out_dev or work is NULL");
+    hipError_t e = launch_sample(psi, n, dt, nullptr, seed, 1, nshots, out_dev, static_cast<double*>(work),
+                                 (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "sample launch: %s", hipGetErrorString(e));
     return ok();
 }

@@ -54,6 +54,16 @@ __device__ __forceinline__ double prob16(const double* psi, uint64_t v)
     return f.x * f.x + f.y * f.y;
 }
 
+// SplitMix64 output function (Steele, Lea & Flood 2014) at state x: the
+// counter-based stream of seeded sampling, u = top 53 bits / 2^53.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 // Butterfly sum over the 64 lanes; every lane ends with the same value.
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -162,8 +172,8 @@ struct SampleTree {
 template <typename R>
 __global__ void __launch_bounds__(256) k_sample(const R* __restrict__ psi, SampleTree tr,
                                                 const double* __restrict__ work,
-                                                const double* __restrict__ u, int64_t nshots,
-                                                int64_t* __restrict__ out)
+                                                const double* __restrict__ u, uint64_t seed, int seeded,
+                                                int64_t nshots, int64_t* __restrict__ out)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (256 / kWave) + threadIdx.x / kWave));
@@ -175,7 +185,12 @@ __global__ void __launch_bounds__(256) k_sample(const R* __restrict__ psi, Sampl
     const double* topv = work + tr.off[top];
     const double T = wave_sum((uint64_t)lane < tr.count[top] ? topv[lane] : 0.0);
     for (int64_t s = wid; s < nshots; s += nw) {
-        double t = u[s] * T;
+        double us;
+        if (seeded)
+            us = (double)(splitmix64(seed ^ (uint64_t)s) >> 11) * 0x1.0p-53;
+        else
+            us = u[s];
+        double t = us * T;
         if (t < 0.0)
             t = 0.0;
         uint64_t node = 0;
@@ -433,8 +448,8 @@ size_t marginal_workspace_doubles()
 }
 
 
-hipError_t launch_sample(const void* psi, int n, int dt, const double* u, int64_t nshots, int64_t* out,
-                         double* work, hipStream_t s)
+hipError_t launch_sample(const void* psi, int n, int dt, const double* u, uint64_t seed, int seeded,
+                         int64_t nshots, int64_t* out, double* work, hipStream_t s)
 {
     const SampleTree tr = sample_tree(n);
     const int gb = n - tr.cb < 6 ? n - tr.cb : 6;
@@ -459,10 +474,10 @@ hipError_t launch_sample(const void* psi, int n, int dt, const double* u, int64_
     const unsigned grid = (unsigned)((waves + 3) / 4);
     if (dt == C64)
         hipLaunchKernelGGL(k_sample<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(psi), tr,
-                           (const double*)work, u, nshots, out);
+                           (const double*)work, u, seed, seeded, nshots, out);
     else
         hipLaunchKernelGGL(k_sample<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(psi), tr,
-                           (const double*)work, u, nshots, out);
+                           (const double*)work, u, seed, seeded, nshots, out);
     return hipGetLastError();
 }
 

@@ -129,8 +129,8 @@ hipError_t launch_fill_zero(double* p, uint64_t count, hipStream_t s);
 // kernels_measure.hip
 size_t sample_workspace_doubles(int n);
 size_t marginal_workspace_doubles();
-hipError_t launch_sample(const void* psi, int n, int dt, const double* u, int64_t nshots, int64_t* out,
-                         double* work, hipStream_t s);
+hipError_t launch_sample(const void* psi, int n, int dt, const double* u, uint64_t seed, int seeded,
+                         int64_t nshots, int64_t* out, double* work, hipStream_t s);
 hipError_t launch_marginal(const void* psi, int n, int dt, const int* q, int m, double* out, double* work,
                            hipStream_t s);
 hipError_t launch_collapse(void* psi, int n, int dt, const int* q, int m, uint64_t outcome,

@@ -80,6 +80,8 @@ _SIGS = {
                           ctypes.c_int),
     "qsv_sample": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int64, _vp, _vp, _vp],
                    ctypes.c_int),
+    "qsv_sample_seeded": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64, _vp, _vp,
+                           _vp], ctypes.c_int),
     "qsv_collapse": ([_vp, ctypes.c_int, ctypes.c_int, _I, ctypes.c_int, ctypes.c_uint64, _vp, _vp],
                      ctypes.c_int),
     "qsv_frequencies": ([_vp, ctypes.c_int64, ctypes.c_int, _I, ctypes.c_int, _vp, _vp],
@@ -347,6 +349,17 @@ def qsv_sample(psi, u, out=None, stream=None):
     work = measure_workspace(n, dtype_code(psi), psi.device)
     _check(lib().qsv_sample(_ptr(psi), n, dtype_code(psi), _ptr(u), u.numel(), _ptr(out),
                             _ptr(work), _stream(stream)))
+    return out
+
+
+def qsv_sample_seeded(psi, seed: int, nshots: int, out=None, stream=None):
+    """qsv_sample with device-drawn uniforms u[s] = (SplitMix64(seed ^ s) >> 11) / 2^53."""
+    import torch
+    n = _nqubits(psi)
+    out = out if out is not None else torch.empty(nshots, dtype=torch.int64, device=psi.device)
+    work = measure_workspace(n, dtype_code(psi), psi.device)
+    _check(lib().qsv_sample_seeded(_ptr(psi), n, dtype_code(psi), int(seed), int(nshots), _ptr(out),
+                                   _ptr(work), _stream(stream)))
     return out
 
 

@@ -275,3 +275,18 @@ def test_collapse_full_size_n30(q):
     assert abs(float(q.qsv_norm2(d).cpu()[0]) - 1.0) <= 1e-5
     del d
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("n", [3, 11, 20])
+def test_sample_seeded(q, orc, name, n):
+    """Device-drawn uniforms (SplitMix64 at seed xor shot) give the oracle's
+    outcomes for the oracle's own draw of the same counter-based stream."""
+    rng = np.random.default_rng(950 + n)
+    psi = rand_state(n, rng, name)
+    psi[::7] = 0
+    seed = 4242 + n
+    say("sample seeded", name, n)
+    got = q.qsv_sample_seeded(to_gpu(psi, name), seed, 30000).cpu().numpy()
+    u = orc.seeded_uniforms(seed, 30000)
+    _check_samples(psi, u, got, orc.sample(psi, u), 1e-13)
