@@ -106,11 +106,14 @@ qsv_status qsv_init_basis(void* psi, int n, qsv_dtype dt, uint64_t index, void* 
 
 /* Seeded synthetic state used by tests and benchmarks (not from the paper):
  * amplitude i = s * ((u(i,0) - 1/2) + i (u(i,1) - 1/2)), where
- * u(i,j) = (SplitMix64(seed XOR (2i+j)) >> 11) * 2^-53 (SplitMix64 output
- * function of Steele, Lea & Flood 2014 evaluated at that state) and
- * s = 1 / sqrt(sum_i |raw_i|^2) (FP64 sum).  Values are computed in FP64 and
- * rounded to the state's precision.  `work` is a device buffer of
- * qsv_reduce_workspace_bytes() bytes. */
+ * u(i,j) = (D(2i+j) >> 11) * 2^-53 and D(c) is draw c of the seed's
+ * counter-based SplitMix64 stream (Steele, Lea & Flood 2014): with f the
+ * generator's output function at a state and gamma = 0x9E3779B97F4A7C15,
+ * key = f(seed) and D(c) = f(key + c * gamma) -- the outputs of the
+ * generator restarted at its own first output, so nearby seeds give
+ * unrelated states -- and s = 1 / sqrt(sum_i |raw_i|^2) (FP64 sum).
+ * Values are computed in FP64 and rounded to the state's precision.  `work`
+ * is a device buffer of qsv_reduce_workspace_bytes() bytes. */
 qsv_status qsv_init_random(void* psi, int n, qsv_dtype dt, uint64_t seed, void* work, void* stream);
 
 /* ------------------------------------------------------ gate application */
@@ -210,9 +213,10 @@ qsv_status qsv_probabilities(const void* psi, int n, qsv_dtype dt, const int* qu
 qsv_status qsv_sample(const void* psi, int n, qsv_dtype dt, const double* u_dev, int64_t nshots,
                       int64_t* out_dev, void* work, void* stream);
 
-/* qsv_sample with the uniforms drawn on the device from a counter-based
- * stream: u[s] = (SplitMix64(seed xor s) >> 11) / 2^53 (SplitMix64: Steele,
- * Lea & Flood 2014), so no uniform array is needed. */
+/* qsv_sample with the uniforms drawn on the device from the seed's
+ * counter-based stream: u[s] = (D(s) >> 11) / 2^53 with D as for
+ * qsv_init_random (SplitMix64: Steele, Lea & Flood 2014), so no uniform
+ * array is needed. */
 qsv_status qsv_sample_seeded(const void* psi, int n, qsv_dtype dt, uint64_t seed, int64_t nshots,
                              int64_t* out_dev, void* work, void* stream);
 

@@ -196,8 +196,10 @@ def frequencies(n: int, samples, qubits) -> np.ndarray:
 
 
 def seeded_uniforms(seed: int, count: int) -> np.ndarray:
-    """u[s] = top 53 bits of SplitMix64(seed xor s) / 2^53 (the counter-based
-    stream that seeded sampling draws)."""
+    """u[s] = top 53 bits of draw s of the seed's counter-based stream / 2^53
+    (key = SplitMix64's first output from the seed, draw s = the output of the
+    generator started at the key after s + 1 steps); seeded sampling draws
+    these."""
     out = np.zeros(max(count, 1))
     _check(lib().orc_uniforms(seed, count, _p(out, _D)), "uniforms")
     return out[:count]

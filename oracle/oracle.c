@@ -303,13 +303,29 @@ uint64_t orc_splitmix64_at(uint64_t x)
     return splitmix64_at(x);
 }
 
+/* Counter-based stream of a seed.  The seed is first scrambled into a key,
+ * the generator's first output from state `seed`; draw c is then the output
+ * of the generator started at state `key` after c + 1 steps, i.e. the output
+ * function at key + c * golden gamma.  Distinct seeds give unrelated keys, so
+ * their streams are not reorderings of each other. */
+static uint64_t stream_draw(uint64_t seed, uint64_t c)
+{
+    const uint64_t key = splitmix64_at(seed);
+    return splitmix64_at(key + c * 0x9E3779B97F4A7C15ULL);
+}
+
+uint64_t orc_stream_draw(uint64_t seed, uint64_t c)
+{
+    return stream_draw(seed, c);
+}
+
 /* Unnormalised amplitude i: (u(i,0) - 1/2) + i (u(i,1) - 1/2) with
- * u(i,j) = top 53 bits of splitmix64(seed xor (2i+j)) / 2^53. */
+ * u(i,j) = top 53 bits of draw 2i+j of the seed's stream / 2^53. */
 static ocx raw_amp(uint64_t seed, uint64_t i)
 {
     ocx a;
-    a.re = (double)(splitmix64_at(seed ^ (2 * i)) >> 11) * 0x1.0p-53 - 0.5;
-    a.im = (double)(splitmix64_at(seed ^ (2 * i + 1)) >> 11) * 0x1.0p-53 - 0.5;
+    a.re = (double)(stream_draw(seed, 2 * i) >> 11) * 0x1.0p-53 - 0.5;
+    a.im = (double)(stream_draw(seed, 2 * i + 1) >> 11) * 0x1.0p-53 - 0.5;
     return a;
 }
 
@@ -795,13 +811,13 @@ int orc_collapse(int n, const double* psi, double* out, const int* q, int m, uin
     return 0;
 }
 
-/* Seeded uniforms for sampling: u[s] = (SplitMix64(seed xor s) >> 11) / 2^53,
- * the top 53 bits of the generator's output at counter s, in [0, 1). */
+/* Seeded uniforms for sampling: u[s] = (draw s of the seed's stream >> 11) /
+ * 2^53, the top 53 bits of the draw, in [0, 1). */
 int orc_uniforms(uint64_t seed, int64_t count, double* u)
 {
     if (count < 0)
         return -1;
     for (int64_t s = 0; s < count; ++s)
-        u[s] = (double)(splitmix64_at(seed ^ (uint64_t)s) >> 11) * (1.0 / 9007199254740992.0);
+        u[s] = (double)(stream_draw(seed, (uint64_t)s) >> 11) * (1.0 / 9007199254740992.0);
     return 0;
 }

@@ -518,18 +518,23 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x)
     return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ double unit_draw(uint64_t seed, uint64_t ctr)
+// Draw `ctr` of a seed's counter-based stream, shifted to [-1/2, 1/2): the
+// key is the generator's first output from state `seed` (so nearby seeds get
+// unrelated keys), and the draw is the output after ctr + 1 steps from the
+// key, i.e. the output function at key + ctr * golden gamma.
+__device__ __forceinline__ double unit_draw(uint64_t key, uint64_t ctr)
 {
-    return (double)(splitmix64(seed ^ ctr) >> 11) * 0x1.0p-53 - 0.5;
+    return (double)(splitmix64(key + ctr * 0x9E3779B97F4A7C15ull) >> 11) * 0x1.0p-53 - 0.5;
 }
 
 // partial[b] = sum over this block's amplitudes of |raw|^2 (fixed order).
 __global__ void __launch_bounds__(kBlock) k_rand_norm(uint64_t N, uint64_t seed, double* partial)
 {
+    const uint64_t key = splitmix64(seed);
     double s = 0.0;
     const uint64_t step = (uint64_t)gridDim.x * kBlock;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
-        const double re = unit_draw(seed, 2 * i), im = unit_draw(seed, 2 * i + 1);
+        const double re = unit_draw(key, 2 * i), im = unit_draw(key, 2 * i + 1);
         s += re * re + im * im;
     }
     __shared__ double red[kBlock];
@@ -567,10 +572,11 @@ __global__ void __launch_bounds__(kBlock) k_rand_fill(R* __restrict__ psi, uint6
                                                       const double* scale)
 {
     const double s = *scale;
+    const uint64_t key = splitmix64(seed);
     const uint64_t step = (uint64_t)gridDim.x * kBlock;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
-        psi[2 * i] = (R)(unit_draw(seed, 2 * i) * s);
-        psi[2 * i + 1] = (R)(unit_draw(seed, 2 * i + 1) * s);
+        psi[2 * i] = (R)(unit_draw(key, 2 * i) * s);
+        psi[2 * i + 1] = (R)(unit_draw(key, 2 * i + 1) * s);
     }
 }
 

@@ -54,8 +54,10 @@ __device__ __forceinline__ double prob16(const double* psi, uint64_t v)
     return f.x * f.x + f.y * f.y;
 }
 
-// SplitMix64 output function (Steele, Lea & Flood 2014) at state x: the
-// counter-based stream of seeded sampling, u = top 53 bits / 2^53.
+// SplitMix64 output function (Steele, Lea & Flood 2014) at state x.  Seeded
+// sampling draws u_s = top 53 bits / 2^53 of the output at key + s * golden
+// gamma, key = the output at state `seed` (the generator restarted at its own
+// first output, so nearby seeds give unrelated streams).
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x)
 {
     uint64_t z = x + 0x9E3779B97F4A7C15ull;
@@ -184,10 +186,11 @@ __global__ void __launch_bounds__(256) k_sample(const R* __restrict__ psi, Sampl
     const int top = tr.nlev - 1;
     const double* topv = work + tr.off[top];
     const double T = wave_sum((uint64_t)lane < tr.count[top] ? topv[lane] : 0.0);
+    const uint64_t key = splitmix64(seed);
     for (int64_t s = wid; s < nshots; s += nw) {
         double us;
         if (seeded)
-            us = (double)(splitmix64(seed ^ (uint64_t)s) >> 11) * 0x1.0p-53;
+            us = (double)(splitmix64(key + (uint64_t)s * 0x9E3779B97F4A7C15ull) >> 11) * 0x1.0p-53;
         else
             us = u[s];
         double t = us * T;

@@ -353,7 +353,8 @@ def qsv_sample(psi, u, out=None, stream=None):
 
 
 def qsv_sample_seeded(psi, seed: int, nshots: int, out=None, stream=None):
-    """qsv_sample with device-drawn uniforms u[s] = (SplitMix64(seed ^ s) >> 11) / 2^53."""
+    """qsv_sample with device-drawn uniforms: u[s] = top 53 bits of draw s of
+    the seed's counter-based SplitMix64 stream / 2^53 (see qsv.h)."""
     import torch
     n = _nqubits(psi)
     out = out if out is not None else torch.empty(nshots, dtype=torch.int64, device=psi.device)

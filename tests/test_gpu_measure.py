@@ -280,7 +280,7 @@ def test_collapse_full_size_n30(q):
 @pytest.mark.parametrize("name", DTYPES)
 @pytest.mark.parametrize("n", [3, 11, 20])
 def test_sample_seeded(q, orc, name, n):
-    """Device-drawn uniforms (SplitMix64 at seed xor shot) give the oracle's
+    """Device-drawn uniforms (draw s of the seed's keyed SplitMix64 stream) give the oracle's
     outcomes for the oracle's own draw of the same counter-based stream."""
     rng = np.random.default_rng(950 + n)
     psi = rand_state(n, rng, name)

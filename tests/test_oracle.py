@@ -382,17 +382,103 @@ def test_sampled_apply_matches_full(orc):
         assert np.max(np.abs(got - full[idx.astype(np.int64)])) < 1e-15
 
 
+class SplitMix64:
+    """The sequential generator as published (Steele, Lea & Flood 2014): the
+    state advances by the golden gamma, then the output function mixes it.
+    Written here independently of the oracle's counter-based form."""
+    G = 0x9E3779B97F4A7C15
+    M = (1 << 64) - 1
+
+    def __init__(self, state):
+        self.s = state & self.M
+
+    def next(self):
+        self.s = (self.s + self.G) & self.M
+        z = self.s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & self.M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & self.M
+        return z ^ (z >> 31)
+
+
+def test_sequential_splitmix64_published_vector():
+    g = SplitMix64(1234567)
+    assert [g.next() for _ in range(5)] == [6457827717110365317, 3203168211198807973,
+                                            9817491932198370423, 4593380528125082431,
+                                            16408922859458223821]
+
+
+def stream(seed, count):
+    """Draws 0..count-1 of a seed's stream: the generator restarted at the
+    key = its own first output from the seed."""
+    g = SplitMix64(SplitMix64(seed).next())
+    return [g.next() for _ in range(count)]
+
+
 def test_random_state_generator_definition(orc):
-    """Amplitude 0 of the seeded state uses u(0,0) = top-53 bits of the first
-    published SplitMix64 output for seed 1234567 over 2**53, shifted by -1/2;
-    the real parts are centred (mean ~ 0)."""
-    seed = 1234567
+    """Amplitude i of the seeded state is (u(2i) - 1/2) + i (u(2i+1) - 1/2)
+    with u(c) = top-53 bits of draw c of the seed's stream over 2**53, draws
+    taken from the sequential published generator; the real parts are
+    centred (mean ~ 0)."""
+    for seed in (1234567, 0, 2 ** 64 - 1):
+        draws = stream(seed, 64)
+        u = [(d >> 11) / 2.0 ** 53 for d in draws]
+        amps = orc.random_amps(seed, 1.0, np.arange(32, dtype=np.uint64))
+        assert np.array_equal(amps.real, np.array(u[0::2]) - 0.5)
+        assert np.array_equal(amps.imag, np.array(u[1::2]) - 0.5)
     n = 12
-    s2 = orc.random_norm2(n, seed)
-    a0 = orc.random_amps(seed, 1.0, np.array([0], np.uint64))[0]
-    assert a0.real == (6457827717110365317 >> 11) / 2.0 ** 53 - 0.5
-    psi = orc.random_state(n, seed) * np.sqrt(s2)
+    s2 = orc.random_norm2(n, 1234567)
+    psi = orc.random_state(n, 1234567) * np.sqrt(s2)
     assert abs(psi.real.mean()) < 0.02 and abs(psi.imag.mean()) < 0.02
+
+
+def test_random_states_of_nearby_seeds_unrelated(orc):
+    """States of seeds that differ in one low bit share no amplitude and are
+    not images of each other under an X on any qubit, a complex conjugation
+    or the two together (the structure a seed-xor-counter stream has)."""
+    n = 10
+    for seed in (0, 1000, 2024, 1234567):
+        base = orc.random_state(n, seed)
+        others = [orc.random_state(n, seed ^ d) for d in (1, 2, 3)]
+        others.append(orc.random_state(n, seed + 1))
+        idx = np.arange(1 << n)
+        for o in others:
+            assert np.intersect1d(np.abs(base.real), np.abs(o.real)).size == 0
+            for flip in [0] + [1 << q for q in range(n)]:
+                moved = o[idx ^ flip]
+                for cand in (moved, np.conj(moved)):
+                    # a relation up to a phase would give |overlap| = 1;
+                    # unrelated 2^10-amplitude states give about 2^-5
+                    assert abs(np.vdot(cand, base)) < 0.2
+                    assert abs(np.sum(cand * base)) < 0.2
+            assert abs(np.vdot(base, o)) < 0.2
+
+
+def test_inner_product_convention(orc):
+    """<a|b> conjugates its FIRST argument (the bra): closed forms
+    <0|(i|0>) = i and (i<0|)|0> = -i, numpy's vdot on random complex vectors
+    (real and imaginary parts, the chunked path from n = 11 on as well), and
+    swapping the arguments conjugates the result exactly."""
+    for n in (1, 3):
+        e0 = np.zeros(1 << n, np.complex128)
+        e0[0] = 1.0
+        assert orc.inner(e0, 1j * e0) == 1j
+        assert orc.inner(1j * e0, e0) == -1j
+        e1 = np.zeros(1 << n, np.complex128)
+        e1[1] = 1.0
+        assert orc.inner(e0, e1) == 0
+        assert orc.inner((1 + 2j) * e1, (3 - 1j) * e1) == (1 - 2j) * (3 - 1j)
+    rng = np.random.default_rng(11)
+    for n in (4, 10, 11, 13):
+        a = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+        b = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+        b = b + 0.5j * a  # Im <a|b> gains 0.5 |a|^2: far from zero
+        got, want = orc.inner(a, b), np.vdot(a, b)
+        scale = np.sum(np.abs(a) * np.abs(b))
+        assert abs(got.real - want.real) <= 1e-14 * scale
+        assert abs(got.imag - want.imag) <= 1e-14 * scale
+        assert abs(want.imag) > 1e-3 * scale
+        assert orc.inner(b, a) == np.conj(got)
+        assert abs(orc.inner(a, a).imag) <= 1e-15 * np.sum(np.abs(a) ** 2)
 
 
 def test_apply_hamiltonian_against_dense(orc):

@@ -203,3 +203,25 @@ def test_seeded_uniforms_are_uniform(orc):
     v = orc.seeded_uniforms(2025, 100000)
     assert not np.array_equal(u[:100], v[:100])
     assert np.array_equal(orc.seeded_uniforms(2024, 10), u[:10])
+
+
+def test_seeded_uniforms_of_nearby_seeds_are_different_sets(orc):
+    """Streams of nearby seeds are not reorderings of each other: their
+    sorted values differ and they share (almost) no value; the stream equals
+    the published sequential generator restarted at its first output."""
+    G, M = 0x9E3779B97F4A7C15, (1 << 64) - 1
+
+    def mix(z):
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    for seed in (0, 1, 1000, 2024):
+        key = mix((seed + G) & M)
+        want = [(mix((key + (s + 1) * G) & M) >> 11) / 2.0 ** 53 for s in range(200)]
+        assert np.array_equal(orc.seeded_uniforms(seed, 200), np.array(want))
+    count = 1 << 16
+    for a, b in ((2024, 2025), (0, 1000), (0, 1), (6, 7), (1 << 40, (1 << 40) + 2)):
+        ua, ub = orc.seeded_uniforms(a, count), orc.seeded_uniforms(b, count)
+        assert not np.array_equal(np.sort(ua), np.sort(ub))
+        assert np.intersect1d(ua, ub).size <= 2
