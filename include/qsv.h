@@ -358,11 +358,17 @@ qsv_status qsv_adjoint_state(const qsv_adjoint_plan* plan, void* work, int slot,
 
 qsv_status qsv_adjoint_plan_destroy(qsv_adjoint_plan* plan);
 
-/* One-shot form: plan, run, and release (host-synchronises the stream before
- * releasing).  work from qsv_adjoint_plan_create's size for the same input. */
+/* One-shot form of qsv_adjoint_plan_create + qsv_adjoint_run + destroy, with
+ * the same arguments and results.  work: device, 256-byte aligned,
+ * work_bytes >= the *work_bytes qsv_adjoint_plan_create reports for the same
+ * (circ, H, dt, fuse_k); a smaller buffer is QSV_ERR_ARG before anything is
+ * enqueued.  The plan's device memory is released at the end of the call, so
+ * the call host-synchronises `stream` (unlike every other call) and is not
+ * capturable; a failed synchronisation is QSV_ERR_HIP. */
 qsv_status qsv_adjoint_gradient(const qsv_circuit* circ, const double* params_dev,
-                                const qsv_pauli_sum* H, qsv_dtype dt, void* work,
-                                double* energy_dev, double* grad_dev, void* stream);
+                                const qsv_pauli_sum* H, qsv_dtype dt, int fuse_k, void* work,
+                                size_t work_bytes, double* energy_dev, double* grad_dev,
+                                void* stream);
 
 /* --------------------------------------------------------------- batches */
 

@@ -202,6 +202,15 @@ int orc_inner(int n, const double* a, const double* b, double* out2)
     return 0;
 }
 
+/* dst = src over 2^n amplitudes (a plain copy, split over threads). */
+static void copy_state(int n, double* dst, const double* src)
+{
+    const long long N2 = 2LL << n;
+#pragma omp parallel for schedule(static)
+    for (long long i = 0; i < N2; ++i)
+        dst[i] = src[i];
+}
+
 /* ------------------------------------------------------------ observables */
 
 static const double PX[8] = {0, 0, 1, 0, 1, 0, 0, 0};
@@ -212,15 +221,14 @@ static const double PZ[8] = {1, 0, 0, 0, 0, 0, -1, 0};
 static void apply_pauli_string(int n, const double* src, double* dst, double* tmp, uint64_t x,
                                uint64_t z)
 {
-    const size_t bytes = (sizeof(double) * 2) << n;
-    memcpy(dst, src, bytes);
+    copy_state(n, dst, src);
     for (int q = 0; q < n; ++q) {
         int xb = (int)((x >> q) & 1ULL), zb = (int)((z >> q) & 1ULL);
         if (!xb && !zb)
             continue;
         const double* m = xb && zb ? PY : (xb ? PX : PZ);
         orc_apply(n, dst, tmp, &q, 1, NULL, 0, m);
-        memcpy(dst, tmp, bytes);
+        copy_state(n, dst, tmp);
     }
 }
 
@@ -271,7 +279,8 @@ int orc_apply_hamiltonian(int n, const double* psi, double* lam, int nterms, con
     memset(lam, 0, bytes);
     for (int j = 0; j < nterms; ++j) {
         apply_pauli_string(n, psi, phi, tmp, x[j], z[j]);
-        for (uint64_t i = 0; i < 2 * N; ++i)
+#pragma omp parallel for schedule(static)
+        for (long long i = 0; i < (long long)(2 * N); ++i)
             lam[i] += coeff[j] * phi[i];
     }
     free(phi);
@@ -520,6 +529,8 @@ static int apply_op(int n, const orc_circ* C, int o, const double* params, int d
     return orc_apply(n, in, out, C->tgt + 5 * o, C->k[o], C->ctl + 4 * o, C->c[o], G);
 }
 
+/* psi = U_N..U_1 psi0 (psi0 NULL: |0..0>).  Each op maps the current state
+ * into the other buffer; the two buffers then trade roles. */
 static int run_circuit(int n, const orc_circ* C, const double* params, const double* psi0,
                        double* psi)
 {
@@ -528,21 +539,24 @@ static int run_circuit(int n, const orc_circ* C, const double* params, const dou
     if (!tmp)
         return -5;
     if (psi0) {
-        memcpy(psi, psi0, bytes);
+        copy_state(n, psi, psi0);
     } else {
         memset(psi, 0, bytes);
         psi[0] = 1.0;
     }
-    for (int o = 0; o < C->nops; ++o) {
-        int rc = apply_op(n, C, o, params, 0, psi, tmp);
-        if (rc) {
-            free(tmp);
-            return rc;
-        }
-        memcpy(psi, tmp, bytes);
+    double* cur = psi;
+    double* other = tmp;
+    int rc = 0;
+    for (int o = 0; o < C->nops && !rc; ++o) {
+        rc = apply_op(n, C, o, params, 0, cur, other);
+        double* t = cur;
+        cur = other;
+        other = t;
     }
+    if (!rc && cur != psi)
+        copy_state(n, psi, cur);
     free(tmp);
-    return 0;
+    return rc;
 }
 
 int orc_run(int n, int nops, const int* kind, const int* k, const int* tgt, const int* c,
@@ -650,11 +664,16 @@ int orc_adjoint(int n, int nops, const int* kind, const int* k, const int* tgt, 
     }
     for (int p = 0; p < nparams; ++p)
         grad[p] = 0.0;
+    /* phi, lam and mu are three buffers; after U^dagger maps one of phi, lam
+     * into mu, the two pointers trade places (no copy). */
     for (int o = nops - 1; o >= 0 && !rc; --o) {
+        double* t;
         rc = apply_op(n, &C, o, params, 1, phi, mu);
         if (rc)
             break;
-        memcpy(phi, mu, bytes);
+        t = phi;
+        phi = mu;
+        mu = t;
         if (C.param[o] >= 0 && is_rotation(C.kind[o])) {
             double D[8];
             gate_derivative(C.kind[o], params[C.param[o]], D);
@@ -664,18 +683,23 @@ int orc_adjoint(int n, int nops, const int* kind, const int* k, const int* tgt, 
             uint64_t cmask = 0;
             for (int j = 0; j < C.c[o]; ++j)
                 cmask |= 1ULL << C.ctl[4 * o + j];
-            for (uint64_t i = 0; i < N; ++i)
-                if ((i & cmask) != cmask) {
-                    mu[2 * i] = 0.0;
-                    mu[2 * i + 1] = 0.0;
-                }
+            if (cmask != 0) {
+#pragma omp parallel for schedule(static)
+                for (long long ii = 0; ii < (long long)N; ++ii)
+                    if (((uint64_t)ii & cmask) != cmask) {
+                        mu[2 * ii] = 0.0;
+                        mu[2 * ii + 1] = 0.0;
+                    }
+            }
             ocx g = dot((const ocx*)lam, (const ocx*)mu, n);
             grad[C.param[o]] += 2.0 * g.re;
         }
         rc = apply_op(n, &C, o, params, 1, lam, mu);
         if (rc)
             break;
-        memcpy(lam, mu, bytes);
+        t = lam;
+        lam = mu;
+        mu = t;
     }
     free(phi);
     free(lam);

@@ -43,6 +43,15 @@ qsv_status ok()
     return QSV_OK;
 }
 
+qsv_status enqueue_gate()
+{
+    const char* v = std::getenv("QSV_TEST_FAIL_LAUNCH");
+    if (v && v[0] == '1' && v[1] == '\0')
+        return fail(QSV_ERR_HIP, "kernel launch failed: unspecified launch failure "
+                                 "(forced by QSV_TEST_FAIL_LAUNCH=1; nothing was enqueued)");
+    return QSV_OK;
+}
+
 size_t amp_bytes(int dt)
 {
     return dt == QSV_C64 ? 8 : 16;
@@ -848,6 +857,8 @@ qsv_status qsv_init_basis(void* psi, int n, qsv_dtype dt, uint64_t index, void* 
         return st;
     if (index >> n)
         return fail(QSV_ERR_ARG, "basis index %llu >= 2^%d", (unsigned long long)index, n);
+    if ((st = enqueue_gate()))
+        return st;
     hipError_t e = launch_init_basis(psi, n, dt, index, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail(QSV_ERR_HIP, "init launch: %s", hipGetErrorString(e));
@@ -869,6 +880,8 @@ qsv_status qsv_init_random(void* psi, int n, qsv_dtype dt, uint64_t seed, void* 
         return st;
     if (!work)
         return fail(QSV_ERR_ARG, "work is NULL");
+    if ((st = enqueue_gate()))
+        return st;
     hipError_t e = launch_init_random(psi, n, dt, seed, static_cast<double*>(work), (hipStream_t)stream);
     if (e != hipSuccess)
         return fail(QSV_ERR_HIP, "init launch: %s", hipGetErrorString(e));
@@ -887,6 +900,8 @@ qsv_status qsv_apply_gate(void* psi, int n, qsv_dtype dt, const int* targets, in
         return fail(QSV_ERR_ARG, "G is NULL");
     if (k + c > kMaxIns)
         return fail(QSV_ERR_UNSUPPORTED, "k + c = %d exceeds %d", k + c, kMaxIns);
+    if ((st = enqueue_gate()))
+        return st;
     int ct[QSV_MAX_TARGETS];
     std::vector<double> Gc;
     canonicalize(targets, k, G, ct, Gc);
@@ -919,6 +934,8 @@ qsv_status qsv_apply_fused(void* psi, int n, qsv_dtype dt, const qsv_block* bloc
         if (!blocks[j].M)
             return fail(QSV_ERR_ARG, "block %d has a NULL matrix", j);
     }
+    if ((st = enqueue_gate()))
+        return st;
     hipStream_t s = (hipStream_t)stream;
     for (int j = 0; j < nblocks; ++j) {
         int ct[QSV_MAX_TARGETS];
@@ -946,6 +963,8 @@ qsv_status qsv_norm2(const void* psi, int n, qsv_dtype dt, double* out_dev, void
         return st;
     if (!out_dev || !work)
         return fail(QSV_ERR_ARG, "out_dev or work is NULL");
+    if ((st = enqueue_gate()))
+        return st;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_norm2(psi, n, dt, static_cast<double*>(work), 0, s);
     if (e == hipSuccess)
@@ -965,6 +984,8 @@ qsv_status qsv_expectation(const void* psi, int n, qsv_dtype dt, const qsv_pauli
         return st;
     if (!out_dev || !work)
         return fail(QSV_ERR_ARG, "out_dev or work is NULL");
+    if ((st = enqueue_gate()))
+        return st;
     if ((st = enqueue_expectation(psi, n, dt, H, out_dev, static_cast<double*>(work), 2,
                                   (hipStream_t)stream)))
         return st;
@@ -981,6 +1002,8 @@ qsv_status qsv_inner(const void* a, const void* b, int n, qsv_dtype dt, double* 
         return st;
     if (!out_dev || !work)
         return fail(QSV_ERR_ARG, "out_dev or work is NULL");
+    if ((st = enqueue_gate()))
+        return st;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_inner(a, b, n, dt, static_cast<double*>(work), 0, s);
     if (e == hipSuccess)
@@ -1001,6 +1024,8 @@ qsv_status qsv_apply_pauli_sum(const void* psi, void* out, int n, qsv_dtype dt,
     if (psi == out)
         return fail(QSV_ERR_ARG, "psi and out must be distinct");
     if ((st = check_hamiltonian(H, n)))
+        return st;
+    if ((st = enqueue_gate()))
         return st;
     if ((st = enqueue_hpsi(psi, out, n, dt, H, (hipStream_t)stream)))
         return st;
@@ -1033,6 +1058,8 @@ qsv_status qsv_probabilities(const void* psi, int n, qsv_dtype dt, const int* qu
         return st;
     if (!out_dev || !work)
         return fail(QSV_ERR_ARG, "out_dev or work is NULL");
+    if ((st = enqueue_gate()))
+        return st;
     hipError_t e = launch_marginal(psi, n, dt, qubits, m, out_dev, static_cast<double*>(work),
                                    (hipStream_t)stream);
     if (e != hipSuccess)
@@ -1052,6 +1079,8 @@ qsv_status qsv_sample(const void* psi, int n, qsv_dtype dt, const double* u_dev,
         return ok();
     if (!u_dev || !out_dev || !work)
         return fail(QSV_ERR_ARG, "u_dev, out_dev or work is NULL");
+    if ((st = enqueue_gate()))
+        return st;
     hipError_t e = launch_sample(psi, n, dt, u_dev, 0, 0, nshots, out_dev, static_cast<double*>(work),
                                  (hipStream_t)stream);
     if (e != hipSuccess)
@@ -1073,6 +1102,8 @@ qsv_status qsv_frequencies(const int64_t* samples_dev, int64_t nshots, int n, co
         return fail(QSV_ERR_ARG, "nshots = %lld is negative", (long long)nshots);
     if (!counts_dev || (nshots > 0 && !samples_dev))
         return fail(QSV_ERR_ARG, "samples_dev or counts_dev is NULL");
+    if ((st = enqueue_gate()))
+        return st;
     hipError_t e = launch_frequencies(samples_dev, nshots, n, qubits, m, counts_dev, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail(QSV_ERR_HIP, "frequencies launch: %s", hipGetErrorString(e));
@@ -1091,6 +1122,8 @@ qsv_status qsv_collapse(void* psi, int n, qsv_dtype dt, const int* qubits, int m
         return fail(QSV_ERR_ARG, "outcome %llu needs more than m = %d bits", (unsigned long long)outcome, m);
     if (!prob_dev)
         return fail(QSV_ERR_ARG, "prob_dev is NULL");
+    if ((st = enqueue_gate()))
+        return st;
     hipError_t e = launch_collapse(psi, n, dt, qubits, m, outcome, prob_dev, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail(QSV_ERR_HIP, "collapse launch: %s", hipGetErrorString(e));
@@ -1109,6 +1142,8 @@ qsv_status qsv_sample_seeded(const void* psi, int n, qsv_dtype dt, uint64_t seed
         return ok();
     if (!out_dev || !work)
         return fail(QSV_ERR_ARG, "out_dev or work is NULL");
+    if ((st = enqueue_gate()))
+        return st;
     hipError_t e = launch_sample(psi, n, dt, nullptr, seed, 1, nshots, out_dev, static_cast<double*>(work),
                                  (hipStream_t)stream);
     if (e != hipSuccess)

@@ -450,7 +450,10 @@ qsv_status qsv_batch_run(qsv_batch_plan* plan, const double* params_dev, void* w
         return fail(QSV_ERR_ARG, "NULL plan, work, energies, gradients or parameters");
     if (reinterpret_cast<uintptr_t>(work) % 256)
         return fail(QSV_ERR_ARG, "work is not 256-byte aligned");
-    qsv_status st = configure(plan, plan->m, plan->threads, plan->split);
+    qsv_status st = enqueue_gate();
+    if (st)
+        return st;
+    st = configure(plan, plan->m, plan->threads, plan->split);
     if (st) {
         // the requested tile does not fit this device: take the first candidate that does
         for (auto c : candidates(plan->dt))
@@ -485,6 +488,8 @@ qsv_status qsv_batch_tune(qsv_batch_plan* plan, const double* params_dev, void* 
 {
     if (!plan || !work || !energies_dev)
         return fail(QSV_ERR_ARG, "NULL plan, work or energies");
+    if (qsv_status gst = enqueue_gate())
+        return gst;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

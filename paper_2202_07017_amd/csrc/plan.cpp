@@ -564,6 +564,8 @@ qsv_status qsv_plan_run(qsv_plan* plan, void* psi, const double* params_dev, voi
         return fail(QSV_ERR_ARG, "plan has unbound rotations but params_dev is NULL");
     if (plan->launches.empty())
         return ok();  // nothing to enqueue (empty or all-identity circuit)
+    if ((st = enqueue_gate()))
+        return st;
     hipStream_t s = (hipStream_t)stream;
     std::vector<const void*> key = {psi, params_dev};
     if ((st = run_graph(plan->graph, key, s, [&](hipStream_t cs) {
@@ -877,6 +879,8 @@ qsv_status qsv_adjoint_run(qsv_adjoint_plan* plan, const double* params_dev, voi
         return fail(QSV_ERR_ARG, "NULL work, energy, gradient or parameter pointer");
     if (reinterpret_cast<uintptr_t>(work) % 256)
         return fail(QSV_ERR_ARG, "work is not 256-byte aligned");
+    if (qsv_status gst = enqueue_gate())
+        return gst;
     hipStream_t s = (hipStream_t)stream;
     std::vector<const void*> key = {params_dev, work, energy_dev, grad_dev};
     qsv_status st = run_graph(plan->graph, key, s, [&](hipStream_t cs) {
@@ -896,6 +900,8 @@ qsv_status qsv_adjoint_energy(qsv_adjoint_plan* plan, const double* params_dev, 
         return fail(QSV_ERR_ARG, "NULL work, energy or parameter pointer");
     if (reinterpret_cast<uintptr_t>(work) % 256)
         return fail(QSV_ERR_ARG, "work is not 256-byte aligned");
+    if (qsv_status gst = enqueue_gate())
+        return gst;
     hipStream_t s = (hipStream_t)stream;
     std::vector<const void*> key = {params_dev, work, energy_dev};
     qsv_status st = run_graph(plan->egraph, key, s, [&](hipStream_t cs) {
@@ -921,24 +927,41 @@ qsv_status qsv_adjoint_plan_destroy(qsv_adjoint_plan* plan)
 }
 
 qsv_status qsv_adjoint_gradient(const qsv_circuit* circ, const double* params_dev,
-                                const qsv_pauli_sum* H, qsv_dtype dt, void* work,
-                                double* energy_dev, double* grad_dev, void* stream)
+                                const qsv_pauli_sum* H, qsv_dtype dt, int fuse_k, void* work,
+                                size_t work_bytes, double* energy_dev, double* grad_dev,
+                                void* stream)
 {
     qsv_adjoint_plan* P = nullptr;
     size_t wb = 0;
-    qsv_status st = qsv_adjoint_plan_create(circ, H, dt, 5, &P, &wb);
+    qsv_status st = qsv_adjoint_plan_create(circ, H, dt, fuse_k, &P, &wb);
     if (st)
         return st;
     if (!work || !energy_dev || (P->nparams > 0 && (!grad_dev || !params_dev))) {
         delete P;
         return fail(QSV_ERR_ARG, "NULL work, energy, gradient or parameter pointer");
     }
+    if (reinterpret_cast<uintptr_t>(work) % 256) {
+        delete P;
+        return fail(QSV_ERR_ARG, "work is not 256-byte aligned");
+    }
+    if (work_bytes < wb) {
+        delete P;
+        return fail(QSV_ERR_ARG, "work holds %zu bytes, this circuit needs %zu", work_bytes, wb);
+    }
+    if ((st = enqueue_gate())) {
+        delete P;
+        return st;
+    }
     hipStream_t s = (hipStream_t)stream;
     st = adjoint_enqueue(P, params_dev, work, energy_dev, grad_dev, true, s);
-    hipStreamSynchronize(s);
+    // the plan's device memory is read by the enqueued kernels: wait for
+    // them before releasing it, whatever the enqueue returned
+    const hipError_t e = hipStreamSynchronize(s);
     delete P;
     if (st)
         return st;
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "stream synchronisation: %s", hipGetErrorString(e));
     return ok();
 }
 

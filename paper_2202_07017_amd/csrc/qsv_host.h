@@ -22,6 +22,10 @@ struct Built {
 
 qsv_status fail(qsv_status st, const char* fmt, ...);
 qsv_status ok();
+// Test hook of the launch error path: QSV_OK, or -- with QSV_TEST_FAIL_LAUNCH=1
+// in the environment -- QSV_ERR_HIP with the message a failed launch gives.
+// Every entry point calls it after validation and before its first enqueue.
+qsv_status enqueue_gate();
 size_t amp_bytes(int dt);
 qsv_status check_n_dt(int n, int dt);
 qsv_status check_state(const void* psi, int n, int dt, const char* what);

@@ -102,7 +102,8 @@ _SIGS = {
     "qsv_adjoint_state": ([_vp, _vp, ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
     "qsv_adjoint_plan_destroy": ([_vp], ctypes.c_int),
     "qsv_adjoint_gradient": ([ctypes.POINTER(qsv_circuit), _vp, ctypes.POINTER(qsv_pauli_sum),
-                              ctypes.c_int, _vp, _vp, _vp, _vp], ctypes.c_int),
+                              ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp, _vp, _vp],
+                             ctypes.c_int),
     "qsv_batch_plan_create": ([ctypes.POINTER(qsv_circuit), ctypes.POINTER(qsv_pauli_sum),
                                ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp),
                                ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -515,6 +516,9 @@ def _autograd_function():
         @staticmethod
         def forward(ctx, params, plan):
             p = params.detach().to(torch.float64).contiguous()
+            if not ctx.needs_input_grad[0]:
+                # no gradient wanted: the forward sweep and the energy only
+                return plan.energy(p)[0].clone()
             e, g = plan.run(p)
             ctx.save_for_backward(g.clone())
             return e[0].clone()
@@ -531,11 +535,41 @@ _AE = None
 
 
 def adjoint_energy(params, plan):
-    """Differentiable energy: torch.autograd sees dE/dtheta from the adjoint."""
+    """Differentiable energy: torch.autograd sees dE/dtheta from the adjoint.
+    Without a gradient to record (torch.no_grad() or params not requiring
+    grad) only the forward sweep and the energy run."""
+    import torch
     global _AE
     if _AE is None:
         _AE = _autograd_function()
+    if not (torch.is_grad_enabled() and params.requires_grad):
+        return plan.energy(params.detach().to(torch.float64).contiguous())[0].clone()
     return _AE.apply(params, plan)
+
+
+def adjoint_gradient(circ, params_dev, H, dtype_code_: int, fuse_k: int, work, energy, grad,
+                     stream=None, order="little"):
+    """One-shot qsv_adjoint_gradient: plan, run and release in one call (it
+    host-synchronises the stream).  work: a device tensor of at least
+    adjoint_work_bytes(...) bytes."""
+    c = circ if isinstance(circ, CircuitC) else CircuitC(circ, order)
+    h = H if isinstance(H, PauliSum) else PauliSum(H, order)
+    _check(lib().qsv_adjoint_gradient(ctypes.byref(c.s), _ptr(params_dev), ctypes.byref(h.s),
+                                      dtype_code_, fuse_k, _ptr(work),
+                                      work.numel() * work.element_size(), _ptr(energy),
+                                      _ptr(grad), _stream(stream)))
+    return energy, grad
+
+
+def adjoint_work_bytes(circ, H, dtype_code_: int, fuse_k: int, order="little") -> int:
+    """Workspace size the adjoint needs for (circ, H, dtype, fuse_k)."""
+    c = circ if isinstance(circ, CircuitC) else CircuitC(circ, order)
+    h = H if isinstance(H, PauliSum) else PauliSum(H, order)
+    hp, wb = _vp(), ctypes.c_size_t()
+    _check(lib().qsv_adjoint_plan_create(ctypes.byref(c.s), ctypes.byref(h.s), dtype_code_, fuse_k,
+                                         ctypes.byref(hp), ctypes.byref(wb)))
+    lib().qsv_adjoint_plan_destroy(hp)
+    return wb.value
 
 
 class BatchPlan:

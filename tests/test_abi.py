@@ -117,3 +117,47 @@ def test_binding_refuses_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(qsv, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no fallback"):
         qsv.lib()
+
+
+@pytest.fixture
+def forced_failure(monkeypatch):
+    monkeypatch.setenv("QSV_TEST_FAIL_LAUNCH", "1")
+    yield
+
+
+def test_forced_launch_failure_reports_hip_error(q, forced_failure):
+    """With QSV_TEST_FAIL_LAUNCH=1 every call that passes validation reports
+    QSV_ERR_HIP with the launch-failure message before it enqueues anything;
+    validation errors still come first.  The pointers are fake and never
+    reached (the hook returns first), so this runs only where no GPU is."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("fake device pointers: the GPU variant of this test covers a real state")
+    L = q.lib()
+    P = ctypes.c_void_p(FAKE)
+    assert call_gate(q, FAKE, 4, 1, (0,), (), np.array([[0, 1], [1, 0]], np.complex128)) == q.ERR_HIP
+    assert "QSV_TEST_FAIL_LAUNCH" in L.qsv_last_error().decode()
+    assert call_gate(q, FAKE, 4, 1, (4,), ()) == q.ERR_QUBIT  # validation first
+    x = np.array([1], np.uint64)
+    z = np.array([2], np.uint64)
+    cf = np.array([1.0])
+    H = q.qsv_pauli_sum(1, x.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                        z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                        cf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    qs = (ctypes.c_int * 2)(0, 1)
+    calls = [
+        lambda: L.qsv_init_basis(P, 4, 1, 3, None),
+        lambda: L.qsv_init_random(P, 4, 2, 7, P, None),
+        lambda: L.qsv_norm2(P, 4, 1, P, P, None),
+        lambda: L.qsv_expectation(P, 4, 1, ctypes.byref(H), P, P, None),
+        lambda: L.qsv_inner(P, P, 4, 2, P, P, None),
+        lambda: L.qsv_apply_pauli_sum(P, ctypes.c_void_p(FAKE * 2), 4, 1, ctypes.byref(H), None),
+        lambda: L.qsv_probabilities(P, 4, 1, qs, 2, P, P, None),
+        lambda: L.qsv_sample(P, 4, 1, P, 5, P, P, None),
+        lambda: L.qsv_sample_seeded(P, 4, 1, 9, 5, P, P, None),
+        lambda: L.qsv_frequencies(P, 5, 4, qs, 2, P, None),
+        lambda: L.qsv_collapse(P, 4, 1, qs, 2, 1, P, None),
+    ]
+    for j, call in enumerate(calls):
+        assert call() == q.ERR_HIP, j
+        assert "QSV_TEST_FAIL_LAUNCH" in L.qsv_last_error().decode(), j

@@ -1,6 +1,8 @@
 """Batched energies and adjoint gradients (one persistent launch) against the
 oracle's adjoint, instance by instance, for every tile shape the autotuner may
-pick; plus the tuner itself and a sample of the full 1024-instance workload."""
+pick; plus the tuner itself.  The full 1024-instance workload is checked in
+test_gpu_configs.py.  Complex64 bounds: 1e-7 per unit of sum|c| (complex64
+sweeps with FP64 accumulation against the complex128 oracle)."""
 import os
 
 import numpy as np
@@ -58,6 +60,7 @@ def mixed_instances(seed, count, nmin, nmax):
 
 
 def check_batch(q, orc, insts, code, shape, tol_e, tol_g, refs=None):
+    """tol_e, tol_g: bounds per unit of sum|c| of the instance's Hamiltonian."""
     import torch
     if shape:
         os.environ["QSV_BATCH_SHAPE"] = shape
@@ -68,12 +71,17 @@ def check_batch(q, orc, insts, code, shape, tol_e, tol_g, refs=None):
     params = torch.from_numpy(np.concatenate([i.params for i in insts])).cuda()
     e, g = plan.run(params)
     e, g = e.cpu().numpy(), g.cpu().numpy()
+    worst = [0.0, 0.0]
     for j, inst in enumerate(insts):
         E_ref, g_ref = refs[j] if refs else orc.adjoint(inst.circuit, inst.params, inst.hamiltonian)
         gj = g[plan.offsets[j]:plan.offsets[j + 1]]
-        assert abs(e[j] - E_ref) <= tol_e, (j, inst.circuit.n, e[j], E_ref)
+        scale = float(np.sum(np.abs(inst.hamiltonian.coeff)))
+        worst[0] = max(worst[0], abs(e[j] - E_ref) / scale)
+        assert abs(e[j] - E_ref) <= tol_e * scale, (j, inst.circuit.n, e[j], E_ref)
         if len(gj):
-            assert np.max(np.abs(gj - g_ref)) <= tol_g, (j, inst.circuit.n, np.max(np.abs(gj - g_ref)))
+            worst[1] = max(worst[1], np.max(np.abs(gj - g_ref)) / scale)
+            assert np.max(np.abs(gj - g_ref)) <= tol_g * scale, (j, inst.circuit.n, np.max(np.abs(gj - g_ref)))
+    say("  worst |dE|/sum|c| %.3e  max|dgrad|/sum|c| %.3e" % tuple(worst))
     return plan, params, e, g
 
 
@@ -84,14 +92,14 @@ def test_batch_every_shape(q, orc, code):
     for shape in SHAPES[code]:
         for split in SPLITS:
             say("batch", code, shape, split)
-            check_batch(q, orc, insts, code, shape + "," + split, 1e-10 if code == 2 else 2e-4,
-                        1e-9 if code == 2 else 2e-4, refs)
+            check_batch(q, orc, insts, code, shape + "," + split, 1e-11 if code == 2 else 1e-7,
+                        1e-10 if code == 2 else 1e-7, refs)
 
 
 def test_batch_tune_and_replay(q, orc):
     import torch
     insts = mixed_instances(5, 20, 4, 15)
-    plan, params, e, g = check_batch(q, orc, insts, 2, None, 1e-10, 1e-9)
+    plan, params, e, g = check_batch(q, orc, insts, 2, None, 1e-11, 1e-10)
     en = torch.empty(plan.ninst, dtype=torch.float64, device="cuda")
     gr = torch.empty(max(int(plan.offsets[-1]), 1), dtype=torch.float64, device="cuda")
     say("batch tune")
@@ -106,35 +114,13 @@ def test_batch_tune_and_replay(q, orc):
         assert np.array_equal(e2.cpu().numpy(), e1) and np.array_equal(g2.cpu().numpy(), g1)
 
 
-def test_batch_full_workload_sample(q, orc):
-    """The 1024-instance workload (n ~ U{12..22}, L ~ U{2..10}, complex64): all
-    instances with n <= 13 and three larger ones checked against the oracle."""
-    import torch
-    insts = W.batched_hea()
-    say("batch full")
-    plan = q.BatchPlan(insts, 1)
-    params = torch.from_numpy(np.concatenate([i.params for i in insts])).cuda()
-    e, g = plan.run(params)
-    e, g = e.cpu().numpy(), g.cpu().numpy()
-    assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
-    picks = [j for j, i in enumerate(insts) if i.circuit.n <= 13]
-    picks += [j for j, i in enumerate(insts) if i.circuit.n in (16, 18)][:2]
-    picks += [j for j, i in enumerate(insts) if i.circuit.n == 20][:1]
-    for j in picks:
-        inst = insts[j]
-        E_ref, g_ref = orc.adjoint(inst.circuit, inst.params, inst.hamiltonian)
-        gj = g[plan.offsets[j]:plan.offsets[j + 1]]
-        assert abs(e[j] - E_ref) <= 2e-4 * inst.circuit.n, (j, inst.circuit.n)
-        assert np.max(np.abs(gj - g_ref)) <= 2e-4 * inst.circuit.n, (j, inst.circuit.n)
-
-
 def test_batch_edge_cases(q, orc):
     """A batch whose instances all take the large tier, a circuit with no
     gates, and a circuit of rotations only (no fixed matrices)."""
     rng = np.random.default_rng(3)
     only_big = [W.BatchInstance(W.hea(17, 1), rng.uniform(0, 6.28, 34), W.tfim_chain(17))]
     say("batch only large tier")
-    check_batch(q, orc, only_big, 1, "12,512,16", 2e-4 * 17, 2e-4 * 17)
+    check_batch(q, orc, only_big, 1, "12,512,16", 1e-7, 1e-7)
     empty = W.Circuit(5, [], 0)
     rot = W.Circuit(4, [W.Op("ry", (j,), param=j) for j in range(4)] +
                     [W.Op("rz", (j,), param=4 + j) for j in range(4)], 8)
@@ -142,5 +128,5 @@ def test_batch_edge_cases(q, orc):
              W.BatchInstance(rot, rng.uniform(0, 6.28, 8), W.tfim_chain(4))]
     for code in [1, 2]:
         say("batch empty/rotations", code)
-        check_batch(q, orc, insts, code, None, 1e-10 if code == 2 else 2e-4,
-                    1e-9 if code == 2 else 2e-4)
+        check_batch(q, orc, insts, code, None, 1e-11 if code == 2 else 1e-7,
+                    1e-10 if code == 2 else 1e-7)

@@ -397,7 +397,8 @@ def test_adjoint_tiled_every_form(q, orc, n):
         e, g = plan.run(torch.from_numpy(p).cuda())
         e, g = e.cpu().numpy()[0], g.cpu().numpy()
         scale = float(np.sum(np.abs(H.coeff)))
-        tol = (1e-10 * scale, 1e-9 * scale) if name == "c128" else (2e-6 * n * scale, 2e-6 * n * scale)
+        tol = (1e-10 * scale, 1e-9 * scale) if name == "c128" else (2e-7 * scale, 2e-7 * scale)
+        say("  |dE| %.3e  max|dgrad| %.3e  (sum|c| %.2f)" % (abs(e - E_ref), np.max(np.abs(g - g_ref)), scale))
         assert abs(e - E_ref) < tol[0], (e, E_ref)
         assert np.max(np.abs(g - g_ref)) < tol[1], np.max(np.abs(g - g_ref))
 
@@ -421,7 +422,10 @@ def test_adjoint_tiled_multi_tile(q, orc, n):
                 os.environ.pop("QSV_NO_TILES", None)
             e, g = plan.run(torch.from_numpy(p).cuda())
             e, g = e.cpu().numpy()[0], g.cpu().numpy()
-            tol = (1e-10, 1e-9) if name == "c128" else (2e-4 * n, 2e-4 * n)
+            scale = float(np.sum(np.abs(H.coeff)))
+            # complex64 sweeps with FP64 accumulation: 1e-7 per unit of sum|c|
+            tol = (1e-10, 1e-9) if name == "c128" else (1e-7 * scale, 1e-7 * scale)
+            say("  |dE| %.3e  max|dgrad| %.3e" % (abs(e - E_ref), np.max(np.abs(g - g_ref))))
             assert abs(e - E_ref) < tol[0], (e, E_ref)
             assert np.max(np.abs(g - g_ref)) < tol[1], np.max(np.abs(g - g_ref))
 
@@ -437,42 +441,6 @@ def test_adjoint_autograd(q, orc):
     (2.0 * E).backward()
     _, g_ref = orc.adjoint(circ, p, H)
     assert np.max(np.abs(theta.grad.cpu().numpy() - 2.0 * g_ref)) < 1e-10
-
-
-def test_adjoint_large_vs_finite_differences(q):
-    """HEA n = 22, L = 8 (352 parameters, TFIM): the complex128 adjoint
-    gradient against complex128 central finite differences (h = 1e-6) on a
-    seeded sample of parameters, within 1e-6; the complex64 adjoint (complex64
-    sweeps, FP64 accumulation) against the complex128 one within 1e-4 of the
-    largest gradient entry."""
-    import torch
-    n, L = 22, 8
-    circ, H = W.hea(n, L), W.tfim_chain(n)
-    p = torch.from_numpy(W.random_params(circ.nparams, 22)).cuda()
-    sub = np.sort(np.random.default_rng(22).choice(circ.nparams, size=6, replace=False))
-    say("adjoint n22 c128")
-    plan = q.AdjointPlan(circ, H, 2, 5)
-    e, g = plan.run(p)
-    g = g.cpu().numpy().copy()
-    pe = p.clone()
-    en = torch.empty(1, dtype=torch.float64, device="cuda")
-    h = 1e-6
-    for j in sub:
-        vals = []
-        for sign in (1.0, -1.0):
-            pe.copy_(p)
-            pe[int(j)] += sign * h
-            plan.energy(pe, en)
-            vals.append(float(en.cpu()[0]))
-        fd = (vals[0] - vals[1]) / (2 * h)
-        assert abs(fd - g[j]) <= 1e-6, (int(j), fd, g[j])
-    del plan
-    say("adjoint n22 c64")
-    plan64 = q.AdjointPlan(circ, H, 1, 5)
-    e64, g64 = plan64.run(p)
-    g64 = g64.cpu().numpy()
-    assert np.max(np.abs(g64 - g)) <= 1e-4 * np.max(np.abs(g)), np.max(np.abs(g64 - g))
-    assert abs(float(e64.cpu()[0]) - float(e.cpu()[0])) <= 1e-4 * n
 
 
 def test_full_size_sampled(q, orc):

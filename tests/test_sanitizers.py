@@ -1,0 +1,67 @@
+"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
+
+The oracle (oracle/oracle.c) is driven through every entry point by
+tests/oracle_sanitize_check.c, and the tile-program compiler of the library
+(paper_2202_07017_amd/csrc/tileprog.cpp) through tests/tileprog_check.cpp on
+random gate lists; both are built with g++/gcc and
+-fsanitize=address,undefined -fno-sanitize-recover=all, so any out-of-bounds
+access, use after free, leak or undefined behaviour aborts the run.  The
+GPU code is not built here (GPU sanitizers are not available)."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+from test_tileprog import hea_gates, random_gates, run_checker
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2202_07017_amd", "csrc")
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+           UBSAN_OPTIONS="print_stacktrace=1", OMP_NUM_THREADS="2")
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    exe = str(tmp_path / "oracle_check")
+    subprocess.run(["gcc", "-O1", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off"] + SAN +
+                   [os.path.join(ROOT, "tests", "oracle_sanitize_check.c"),
+                    os.path.join(ROOT, "oracle", "oracle.c"), "-o", exe, "-lm"], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, env=ENV, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "ok" in r.stdout
+    assert "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, r.stderr
+
+
+@pytest.fixture(scope="module")
+def san_checker(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("tileprog_san") / "tileprog_check")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I" + CSRC] + SAN +
+                   [os.path.join(ROOT, "tests", "tileprog_check.cpp"),
+                    os.path.join(CSRC, "tileprog.cpp"), "-o", exe], check=True)
+    return exe
+
+
+@pytest.mark.parametrize("n,m,cap,count,seed", [(9, 6, 512, 160, 1), (12, 7, 40, 200, 3),
+                                                (7, 12, 512, 60, 5), (10, 4, 512, 150, 6)])
+def test_tile_programs_under_sanitizers(orc, san_checker, n, m, cap, count, seed):
+    gates = random_gates(n, count, seed)
+    rng = np.random.default_rng(100 + seed)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi /= np.linalg.norm(psi)
+    got = run_checker(san_checker, n, m, cap, gates, psi)
+    circ = W.Circuit(n, [W.Op("matrix", (t,), controls=tuple(cs), matrix=np.asarray(M, complex))
+                         for _, t, cs, _, M in gates])
+    assert np.max(np.abs(got - orc.run(circ, psi0=psi))) < 1e-12
+
+
+def test_tile_program_ladder_under_sanitizers(orc, san_checker):
+    gates = hea_gates(11, 3, 18)
+    rng = np.random.default_rng(3)
+    psi = rng.normal(size=1 << 11) + 1j * rng.normal(size=1 << 11)
+    psi /= np.linalg.norm(psi)
+    got = run_checker(san_checker, 11, 8, 512, gates, psi)
+    circ = W.Circuit(11, [W.Op("matrix", (t,), controls=tuple(cs), matrix=np.asarray(M, complex))
+                          for _, t, cs, _, M in gates])
+    assert np.max(np.abs(got - orc.run(circ, psi0=psi))) < 1e-12
