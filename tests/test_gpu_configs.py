@@ -297,7 +297,8 @@ def test_batched_workload_checked_subset(q, orc):
         de, dg = abs(e[j] - E_ref), float(np.max(np.abs(gj - g_ref)))
         w = worst.get(n, (0.0, 0.0))
         worst[n] = (max(w[0], de / scale), max(w[1], dg / scale))
-        assert de <= 1e-7 * scale and dg <= 1e-7 * scale, (j, n, de, dg)
+        # complex64: worst measured instance 7e-8 per unit of sum|c|
+        assert de <= 3e-7 * scale and dg <= 3e-7 * scale, (j, n, de, dg)
     for n in sorted(worst):
         say("batch n=%d worst |dE|/sum|c| %.3e  max|dgrad|/sum|c| %.3e" % ((n,) + worst[n]))
     assert len(small) > 400 and {21, 22} <= set(worst)
