@@ -141,3 +141,39 @@ def test_pauli_identity_and_duplicate_terms(q, orc, n):
         out = to_gpu(np.zeros_like(psi), name)
         q.qsv_apply_pauli_sum(d, out, H)
         close(to_np(out) / scale, orc.apply_hamiltonian(psi, H) / scale, name, "H psi")
+
+
+def test_forced_launch_failure_leaves_state_unchanged(q, monkeypatch):
+    """QSV_TEST_FAIL_LAUNCH=1: gate, fused, plan, expectation and adjoint
+    calls on real device buffers report QSV_ERR_HIP with the launch-failure
+    message, enqueue nothing (the state keeps its bits), and work again once
+    the variable is gone."""
+    import torch
+    n = 12
+    rng = np.random.default_rng(5)
+    for name in DTYPES:
+        psi = to_gpu(rand_state(n, rng, name), name)
+        before = psi.clone()
+        G = W.haar_unitary(rng, 2)
+        circ = W.random_u2_cz(n=n, depth=2, seed=3)
+        plan = q.Plan(circ, 1 if name == "c64" else 2, 5)
+        aplan = q.AdjointPlan(W.hea(n, 1), W.tfim_chain(n), 1 if name == "c64" else 2, 5)
+        pdev = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+        monkeypatch.setenv("QSV_TEST_FAIL_LAUNCH", "1")
+        say("forced launch failure", name)
+        calls = [lambda: q.qsv_apply_gate(psi, (3,), (), G),
+                 lambda: q.qsv_apply_gate(psi, (0, 1, 2, 3, 4), (), W.haar_unitary(rng, 32)),
+                 lambda: plan.run(psi),
+                 lambda: q.qsv_expectation(psi, W.tfim_chain(n)),
+                 lambda: q.qsv_norm2(psi),
+                 lambda: aplan.run(pdev)]
+        for call in calls:
+            with pytest.raises(q.QsvError, match="QSV_TEST_FAIL_LAUNCH") as ei:
+                call()
+            assert ei.value.status == q.ERR_HIP
+        torch.cuda.synchronize()
+        assert torch.equal(torch.view_as_real(psi), torch.view_as_real(before))
+        monkeypatch.delenv("QSV_TEST_FAIL_LAUNCH")
+        q.qsv_apply_gate(psi, (3,), (), G)
+        torch.cuda.synchronize()
+        assert not torch.equal(torch.view_as_real(psi), torch.view_as_real(before))
