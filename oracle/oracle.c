@@ -338,15 +338,27 @@ static ocx raw_amp(uint64_t seed, uint64_t i)
     return a;
 }
 
+/* sum_i |raw_i|^2 in a fixed order: 64 equal chunks (fewer for tiny n), each
+ * summed in index order, then the chunk sums in chunk order -- so every call
+ * returns the same bits whatever the thread timing. */
 int orc_random_norm2(int n, uint64_t seed, double* out)
 {
     const uint64_t N = 1ULL << n;
-    double s = 0.0;
-#pragma omp parallel for reduction(+ : s) schedule(static)
-    for (long long ii = 0; ii < (long long)N; ++ii) {
-        ocx a = raw_amp(seed, (uint64_t)ii);
-        s += a.re * a.re + a.im * a.im;
+    const int nch = n >= 6 ? 64 : 1;
+    const uint64_t len = N / (uint64_t)nch;
+    double part[64];
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < nch; ++c) {
+        double s = 0.0;
+        for (uint64_t i = (uint64_t)c * len; i < (uint64_t)(c + 1) * len; ++i) {
+            ocx a = raw_amp(seed, i);
+            s += a.re * a.re + a.im * a.im;
+        }
+        part[c] = s;
     }
+    double s = 0.0;
+    for (int c = 0; c < nch; ++c)
+        s += part[c];
     out[0] = s;
     return 0;
 }
