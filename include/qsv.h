@@ -171,6 +171,20 @@ qsv_status qsv_norm2(const void* psi, int n, qsv_dtype dt, double* out_dev, void
 qsv_status qsv_expectation(const void* psi, int n, qsv_dtype dt, const qsv_pauli_sum* H,
                            double* out_dev, void* work, void* stream);
 
+/* qsv_expectation without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * qsv_expectation minus `work`: the partial sums live in a static device
+ * array of 32 KiB that each GPU holds from the library's first call on it
+ * until the process ends; the call allocates nothing and enqueues no memset
+ * (the first pass overwrites the slots it needs).  Every call on one GPU
+ * shares that array: calls that overlap in time on one GPU (different
+ * streams, or host threads) race and must be serialised by the caller.
+ * Every n up to QSV_MAX_QUBITS fits (at most 2 x 1024 partial sums);
+ * QSV_ERR_UNSUPPORTED would report a state needing more. */
+qsv_status qsv_expectation_noalloc(const void* psi, int n, qsv_dtype dt, const qsv_pauli_sum* H,
+                                   double* out_dev, void* stream);
+
 /* out_dev[0..1] = <a|b> (re, im) in FP64. */
 qsv_status qsv_inner(const void* a, const void* b, int n, qsv_dtype dt, double* out_dev,
                      void* work, void* stream);

@@ -992,6 +992,32 @@ qsv_status qsv_expectation(const void* psi, int n, qsv_dtype dt, const qsv_pauli
     return ok();
 }
 
+qsv_status qsv_expectation_noalloc(const void* psi, int n, qsv_dtype dt, const qsv_pauli_sum* H,
+                                   double* out_dev, void* stream)
+{
+    qsv_status st = check_state(psi, n, dt, "psi");
+    if (st)
+        return st;
+    if ((st = check_hamiltonian(H, n)))
+        return st;
+    if (!out_dev)
+        return fail(QSV_ERR_ARG, "out_dev is NULL");
+    // partial sums: re and im per reduction slot
+    const size_t need = 2 * sizeof(double) * (size_t)reduce_blocks(n, dt);
+    if (need > kStaticScratchBytes)
+        return fail(QSV_ERR_UNSUPPORTED, "n = %d needs %zu bytes of partial sums, the static "
+                    "scratch holds %zu", n, need, kStaticScratchBytes);
+    if ((st = enqueue_gate()))
+        return st;
+    double* scr = nullptr;
+    const hipError_t e = static_scratch(&scr);
+    if (e != hipSuccess)
+        return fail(QSV_ERR_HIP, "static scratch address: %s", hipGetErrorString(e));
+    if ((st = enqueue_expectation(psi, n, dt, H, out_dev, scr, 2, (hipStream_t)stream)))
+        return st;
+    return ok();
+}
+
 qsv_status qsv_inner(const void* a, const void* b, int n, qsv_dtype dt, double* out_dev, void* work,
                      void* stream)
 {

@@ -10,9 +10,39 @@
 // a fixed per-thread visiting order, a fixed in-block tree, per-block FP64
 // partials in device memory, and a one-block finalize that adds them in
 // index order.  Amplitudes are widened to FP64 before any product.
+#include <mutex>
+
 #include "qsv_internal.h"
 
+// Partial sums of qsv_expectation_noalloc.  Each GPU holds its own copy
+// until the process ends; every call on a GPU shares it (calls that overlap
+// in time on one GPU race on it).
+static __device__ __align__(256) double scratch[qsv::kStaticScratchBytes / sizeof(double)];
+
 namespace qsv {
+
+hipError_t static_scratch(double** ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {nullptr};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        addr[dev] = p;
+    }
+    *ptr = static_cast<double*>(addr[dev]);
+    return hipSuccess;
+}
 
 int reduce_blocks(int n, int dt)
 {

@@ -120,6 +120,13 @@ hipError_t launch_expect_pair(const void* psi, int n, int dt, uint64_t x, const 
 hipError_t launch_inner(const void* a, const void* b, int n, int dt, double* partials2,
                         int accumulate, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int nblocks, int ncomp, double* out, hipStream_t s);
+
+// Device scratch of the allocation-free expectation (kernels_reduce.hip): a
+// file-scope __device__ array of kStaticScratchBytes per GPU.  static_scratch
+// returns the current device's address of it (looked up once per device with
+// hipGetSymbolAddress; the array's name is not a device address on the host).
+constexpr size_t kStaticScratchBytes = 32768;
+hipError_t static_scratch(double** ptr);
 hipError_t launch_hpsi_diag(const void* psi, void* lam, int n, int dt, const TermChunk& t,
                             int accumulate, hipStream_t s);
 hipError_t launch_hpsi_pair(const void* psi, void* lam, int n, int dt, uint64_t x,

@@ -71,6 +71,8 @@ _SIGS = {
     "qsv_norm2": ([_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
     "qsv_expectation": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsv_pauli_sum), _vp, _vp,
                          _vp], ctypes.c_int),
+    "qsv_expectation_noalloc": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsv_pauli_sum),
+                                 _vp, _vp], ctypes.c_int),
     "qsv_inner": ([_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
     "qsv_apply_pauli_sum": ([_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsv_pauli_sum),
                              _vp], ctypes.c_int),
@@ -288,6 +290,17 @@ def qsv_expectation(psi, H, out=None, stream=None):
     out = out if out is not None else torch.empty(2, dtype=torch.float64, device=psi.device)
     _check(lib().qsv_expectation(_ptr(psi), _nqubits(psi), dtype_code(psi), ctypes.byref(P.s),
                                  _ptr(out), _ptr(reduce_workspace(psi.device)), _stream(stream)))
+    return out
+
+
+def qsv_expectation_noalloc(psi, H, out=None, stream=None):
+    """qsv_expectation with the library's static per-GPU scratch (no
+    workspace; calls overlapping on one GPU race)."""
+    import torch
+    P = H if isinstance(H, PauliSum) else PauliSum(H)
+    out = out if out is not None else torch.empty(2, dtype=torch.float64, device=psi.device)
+    _check(lib().qsv_expectation_noalloc(_ptr(psi), _nqubits(psi), dtype_code(psi), ctypes.byref(P.s),
+                                         _ptr(out), _stream(stream)))
     return out
 
 
