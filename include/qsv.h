@@ -52,6 +52,9 @@
  *    QSV_BATCH_SHAPE=m,t[,s]    batch tile qubits, threads, split (skips the cache)
  *    QSV_NO_GRAPH=1             plans enqueue their launches instead of replaying a graph
  *    QSV_NO_MFMA=1              4- and 5-qubit blocks on the vector units
+ *    QSV_MFMA_FORM=3m|real      matrix-core blocks as three real products (Gauss)
+ *                               or one real-embedded product (default: three
+ *                               products, except complex128 5-qubit blocks)
  *    QSV_NO_DIAG_RUN=1          plans keep consecutive diagonal gates as separate launches
  *    QSV_NO_TILES=1             per-gate adjoint instead of cache-blocked tile programs
  *    QSV_NO_LANE_SWEEP=1        no cross-lane exchange for low single-qubit targets
@@ -170,6 +173,11 @@ qsv_status qsv_norm2(const void* psi, int n, qsv_dtype dt, double* out_dev, void
  * distinct x_mask.  out_dev: 2 doubles, device. */
 qsv_status qsv_expectation(const void* psi, int n, qsv_dtype dt, const qsv_pauli_sum* H,
                            double* out_dev, void* work, void* stream);
+
+/* Number of kernel launches qsv_expectation (and qsv_expectation_noalloc)
+ * enqueue for H on an n-qubit state: one per pass over the state (each pass
+ * reads it once) plus the final reduction.  Host only; nothing is enqueued. */
+qsv_status qsv_expectation_launches(const qsv_pauli_sum* H, int n, qsv_dtype dt, int* nlaunches);
 
 /* qsv_expectation without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,

@@ -358,7 +358,19 @@ Built build_launch(int n, int dt, const int* ct, int k, const int* ctl, int c, c
         L.ins = make_ins(B, 0);
         L.ntiles = 1ull << (n - k - 6);
         L.ngroups = L.ntiles;
-        mfma_fragments(Gc, k, dt, b.upload);
+        // Three-product kernel by default; the real-embedding one for
+        // complex128 k = 5, where the three-product form needs more registers
+        // than four waves per SIMD allow and ran 6-10% slower (measured).
+        const char* form = std::getenv("QSV_MFMA_FORM");
+        L.mfma3 = (dt == QSV_C64 || k == 4) ? 1 : 0;
+        if (form && std::strcmp(form, "real") == 0)
+            L.mfma3 = 0;
+        else if (form && std::strcmp(form, "3m") == 0)
+            L.mfma3 = 1;
+        if (L.mfma3)
+            mfma3_fragments(Gc, k, dt, b.upload);
+        else
+            mfma_fragments(Gc, k, dt, b.upload);
         return b;
     }
     L.type = L_DENSE;
@@ -653,7 +665,9 @@ void plan_tiles(const qsv_pauli_sum* H, int n, std::vector<TileExpK>& out,
         int L = 0;
         while (L < (int)pos.size() && pos[L] == L)
             ++L;
-        std::vector<XTerm> str, tab, pairs;
+        // diagonal classes (see TileExpK): 0 static straddler, 1 tile-signed
+        // with a local mask, 2 wholly outside, 3 static table term
+        std::vector<XTerm> dcls[4], pairs;
         for (const T& t : pr.second) {
             XTerm x{};
             x.z = t.z;
@@ -664,18 +678,24 @@ void plan_tiles(const qsv_pauli_sum* H, int n, std::vector<TileExpK>& out,
                 x.kind = 0;
                 const bool lo = (x.zloc & 63) != 0, hi = (x.zloc >> 6) != 0;
                 x.dpart = (lo && hi ? 3 : (hi ? 2 : 1));
-                (x.dpart == 3 ? str : tab).push_back(x);
+                const bool inside = (t.z & ~B) == 0;
+                const int cls = inside ? (x.dpart == 3 ? 0 : 3) : (x.zloc ? 1 : 2);
+                dcls[cls].push_back(x);
             } else {
                 x.xloc = compress(t.x);
                 x.kind = (t.z == 0 && t.ylo == 0) ? 2 : 1;
                 pairs.push_back(x);
             }
         }
-        // launches of <= kMaxTileTerms terms: straddlers and table terms ride
-        // with the first launch(es), pair terms fill the rest
-        std::vector<XTerm> diag = str;
-        const int nstr_total = (int)str.size();
-        diag.insert(diag.end(), tab.begin(), tab.end());
+        // launches of <= kMaxTileTerms terms: diagonal terms ride with the
+        // first launch(es), pair terms fill the rest
+        std::vector<XTerm> diag;
+        std::vector<int> dclass;
+        for (int cls = 0; cls < 4; ++cls)
+            for (const XTerm& x : dcls[cls]) {
+                diag.push_back(x);
+                dclass.push_back(cls);
+            }
         size_t di = 0, pi = 0;
         bool first = true;
         while (first || di < diag.size() || pi < pairs.size()) {
@@ -693,13 +713,14 @@ void plan_tiles(const qsv_pauli_sum* H, int n, std::vector<TileExpK>& out,
                 k.choff[c] = o;
             }
             int nt = 0;
-            int nstr = 0;
+            int cnt[4] = {0, 0, 0, 0};
             while (di < diag.size() && nt < kMaxTileTerms) {
-                if ((int)di < nstr_total)
-                    ++nstr;
+                ++cnt[dclass[di]];
                 k.t[nt++] = diag[di++];
             }
-            k.nstr = nstr;
+            k.nx = cnt[0];
+            k.nd = k.nx + cnt[1];
+            k.no = k.nd + cnt[2];
             k.pstart = nt;
             k.ndiag = nt;
             while (pi < pairs.size() && nt < kMaxTileTerms)
@@ -989,6 +1010,31 @@ qsv_status qsv_expectation(const void* psi, int n, qsv_dtype dt, const qsv_pauli
     if ((st = enqueue_expectation(psi, n, dt, H, out_dev, static_cast<double*>(work), 2,
                                   (hipStream_t)stream)))
         return st;
+    return ok();
+}
+
+qsv_status qsv_expectation_launches(const qsv_pauli_sum* H, int n, qsv_dtype dt, int* nlaunches)
+{
+    qsv_status st = check_n_dt(n, dt);
+    if (st)
+        return st;
+    if ((st = check_hamiltonian(H, n)))
+        return st;
+    if (!nlaunches)
+        return fail(QSV_ERR_ARG, "nlaunches is NULL");
+    int count = 1;  // the finalize
+    if (n >= kTileQubits) {
+        std::vector<TileExpK> tiles;
+        std::vector<std::pair<uint64_t, TermChunk>> leftover;
+        plan_tiles(H, n, tiles, leftover);
+        count += (int)(tiles.size() + leftover.size());
+    } else {
+        std::vector<TermChunk> diag;
+        std::vector<std::pair<uint64_t, TermChunk>> pairs;
+        group_terms(H, diag, pairs);
+        count += (int)(diag.size() + pairs.size());
+    }
+    *nlaunches = count;
     return ok();
 }
 

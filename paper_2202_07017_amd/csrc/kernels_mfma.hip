@@ -246,6 +246,163 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma_w
     }
 }
 
+// Gauss's three-product form of the same complex product (3M): with
+// G = Gr + i Gi and In = Xr + i Xi,
+//     P1 = Gr Xr,  P2 = Gi Xi,  P3 = (Gr + Gi)(Xr + Xi),
+//     Out = (P1 - P2) + i (P3 - P1 - P2),
+// three real 2^k x 2^k products instead of one 2^(k+1) x 2^(k+1) one: 3/4 of
+// the matrix-core work (the k = 5 block is bound by it at ~57% of the f32 /
+// f64 matrix peak for 70% of HBM).  The A operands Gr, Gi and Gr + Gi are
+// formed on the host in FP64 and rounded once; Xr + Xi is one VALU add per
+// B value.  The tile layout in LDS is the same [tau'][group] as above, and
+// every B value is one complex LDS read.  Work split: the 2^k / 16 row blocks
+// of complex rows take 4 / RB waves each, each wave 4 / WPR of the four
+// 16-column group blocks.
+// Waves per SIMD the three-product kernel's register allocation must allow:
+// complex64 k = 4 fits 8 (60 VGPRs); the others take what they need
+// (complex128 k = 5 would spill under a 128-register cap).
+template <typename R, int K>
+constexpr int mfma3_wpe()
+{
+    return (sizeof(R) == 4 && K == 4) ? 8 : 1;
+}
+
+template <typename R, int K>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_wpe<R, K>()))) k_mfma3(R* __restrict__ psi0, R* __restrict__ psi1,
+                                               const MfmaK<K> a, const R* __restrict__ frag)
+{
+    using T = MfmaT<R>;
+    using NV = typename T::NV;
+    using P2 = typename Pair2<R>::T;
+    constexpr int D = 1 << K;           // complex rows (amplitudes per group)
+    constexpr int TA = D * 64;          // amplitudes per tile
+    constexpr int APV = T::APV;
+    constexpr int VPT = TA / APV / 256; // vectors per thread
+    constexpr int KS = D / 4;           // k-steps of 4 complex rows
+    constexpr int RB = D / 16;          // 16-row output blocks (2 for k = 5, 1 for k = 4)
+    constexpr int WPR = 4 / RB;         // waves per row block
+    constexpr int CBW = 4 / WPR;        // 16-column blocks per wave
+    static_assert(RB == 1 || RB == 2, "tile split");
+
+    __shared__ __align__(16) R lds[D * kRow * 2];
+
+    R* psi = blockIdx.y ? psi1 : psi0;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int rb = wave % RB;
+    const int cb0 = (wave / RB) * CBW;
+
+    const uint64_t tile = xcd_block();
+    if (tile >= a.ntiles)
+        return;
+    const uint64_t base = insert_bits(tile, a.ins);
+
+    uint64_t goff[VPT];
+    NV in[VPT];
+#pragma unroll
+    for (int r = 0; r < VPT; ++r) {
+        const int loc = (tid + 256 * r) * APV;
+        goff[r] = a.choff[loc >> a.L] + (uint64_t)(loc & ((1 << a.L) - 1));
+        in[r] = __builtin_nontemporal_load(reinterpret_cast<const NV*>(psi + 2 * (base + goff[r])));
+    }
+    // A operands of this wave's row block: Gr, Gi, Gr + Gi, KS values each
+    // per lane, contiguous in the table ([rb][product][lane][kk]).
+    R afr[3][KS];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk)
+            afr[p][kk] = frag[(((size_t)rb * 3 + p) * 64 + lane) * KS + kk];
+    int pos[VPT][APV];
+#pragma unroll
+    for (int r = 0; r < VPT; ++r) {
+        const int loc = (tid + 256 * r) * APV;
+#pragma unroll
+        for (int h = 0; h < APV; ++h) {
+            const int l = loc + h;
+            int tau = 0, j = 0;
+#pragma unroll
+            for (int b = 0; b < K; ++b)
+                tau |= ((l >> a.tloc[b]) & 1) << b;
+#pragma unroll
+            for (int b = 0; b < 6; ++b)
+                j |= ((l >> a.floc[b]) & 1) << b;
+            pos[r][h] = (tau * kRow + j) * 2;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < VPT; ++r)
+#pragma unroll
+        for (int h = 0; h < APV; ++h)
+            *reinterpret_cast<P2*>(&lds[pos[r][h]]) = P2{in[r][2 * h], in[r][2 * h + 1]};
+    __syncthreads();
+
+    // B: lane holds complex row 4 kk + lane / 16 of group (cb0 + c) * 16 +
+    // lane % 16.  Reads in groups of KG k-steps, one group ahead of the
+    // products (scheduling barriers keep the order).
+    typename T::Acc acc[3][CBW];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int c = 0; c < CBW; ++c)
+            acc[p][c] = typename T::Acc{0, 0, 0, 0};
+    const int bofs = ((lane >> 4) * kRow + cb0 * 16 + (lane & 15)) * 2;
+    constexpr int KG = K == 5 ? 2 : 4;  // k = 5: two k-steps per group keeps the registers in bounds
+    P2 bfr[KS][CBW];
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+        for (int c = 0; c < CBW; ++c)
+            bfr[kk][c] = *reinterpret_cast<const P2*>(&lds[bofs + (4 * kk * kRow + 16 * c) * 2]);
+#pragma unroll
+    for (int g = 0; g < KS / KG; ++g) {
+        if (g + 1 < KS / KG) {
+#pragma unroll
+            for (int kk = (g + 1) * KG; kk < (g + 2) * KG; ++kk)
+#pragma unroll
+                for (int c = 0; c < CBW; ++c)
+                    bfr[kk][c] = *reinterpret_cast<const P2*>(&lds[bofs + (4 * kk * kRow + 16 * c) * 2]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int kk = g * KG; kk < (g + 1) * KG; ++kk)
+#pragma unroll
+            for (int c = 0; c < CBW; ++c) {
+                const R xr = bfr[kk][c].x, xi = bfr[kk][c].y;
+                acc[0][c] = T::mfma(afr[0][kk], xr, acc[0][c]);
+                acc[1][c] = T::mfma(afr[1][kk], xi, acc[1][c]);
+                acc[2][c] = T::mfma(afr[2][kk], xr + xi, acc[2][c]);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();  // every wave has read its B operands
+    // register r of each lane holds complex row 16 rb + T::row(lane, r) of
+    // group (cb0 + c) * 16 + lane % 16
+#pragma unroll
+    for (int c = 0; c < CBW; ++c) {
+        const int grp = (cb0 + c) * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int tau = 16 * rb + T::row(lane, r);
+            const R p1 = acc[0][c][r], p2 = acc[1][c][r], p3 = acc[2][c][r];
+            *reinterpret_cast<P2*>(&lds[(tau * kRow + grp) * 2]) = P2{p1 - p2, p3 - p1 - p2};
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < VPT; ++r) {
+        NV o;
+#pragma unroll
+        for (int h = 0; h < APV; ++h) {
+            const P2 w = *reinterpret_cast<const P2*>(&lds[pos[r][h]]);
+            o[2 * h] = w.x;
+            o[2 * h + 1] = w.y;
+        }
+        __builtin_nontemporal_store(o, reinterpret_cast<NV*>(psi + 2 * (base + goff[r])));
+    }
+}
+
 template <typename R, int K>
 hipError_t mfma_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
 {
@@ -262,8 +419,12 @@ hipError_t mfma_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
     if (L.ntiles > (1ull << 31))
         return hipErrorInvalidValue;
     dim3 grid((unsigned)L.ntiles, p1 ? 2 : 1);
-    hipLaunchKernelGGL((k_mfma<R, K>), grid, dim3(256), 0, s, static_cast<R*>(p0),
-                       static_cast<R*>(p1 ? p1 : p0), a, static_cast<const R*>(L.gdev));
+    if (L.mfma3)
+        hipLaunchKernelGGL((k_mfma3<R, K>), grid, dim3(256), 0, s, static_cast<R*>(p0),
+                           static_cast<R*>(p1 ? p1 : p0), a, static_cast<const R*>(L.gdev));
+    else
+        hipLaunchKernelGGL((k_mfma<R, K>), grid, dim3(256), 0, s, static_cast<R*>(p0),
+                           static_cast<R*>(p1 ? p1 : p0), a, static_cast<const R*>(L.gdev));
     return hipGetLastError();
 }
 
@@ -276,6 +437,30 @@ hipError_t launch_mfma(const GateLaunch& L, void* psi, void* psi2, hipStream_t s
     if (L.dt == C64)
         return L.K == 4 ? mfma_go<float, 4>(L, psi, psi2, s) : mfma_go<float, 5>(L, psi, psi2, s);
     return L.K == 4 ? mfma_go<double, 4>(L, psi, psi2, s) : mfma_go<double, 5>(L, psi, psi2, s);
+}
+
+// A operands of the three-product kernel: [rb][product][lane][kk] with
+// lane holding row 16 rb + lane % 16, column 4 kk + lane / 16 of Gr, Gi and
+// Gr + Gi (the sum formed in FP64, then rounded once).
+void mfma3_fragments(const double* Gc, int K, int dt, std::vector<unsigned char>& out)
+{
+    const int D = 1 << K, KS = D / 4, RB = D / 16;
+    const size_t count = (size_t)RB * 3 * 64 * KS;
+    out.assign(count * (dt == C64 ? 4 : 8), 0);
+    for (int rb = 0; rb < RB; ++rb)
+        for (int p = 0; p < 3; ++p)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int kk = 0; kk < KS; ++kk) {
+                    const int row = 16 * rb + (lane & 15), col = 4 * kk + (lane >> 4);
+                    const double gre = Gc[((size_t)row * D + col) * 2];
+                    const double gim = Gc[((size_t)row * D + col) * 2 + 1];
+                    const double v = p == 0 ? gre : (p == 1 ? gim : gre + gim);
+                    const size_t idx = (((size_t)rb * 3 + p) * 64 + lane) * KS + kk;
+                    if (dt == C64)
+                        reinterpret_cast<float*>(out.data())[idx] = (float)v;
+                    else
+                        reinterpret_cast<double*>(out.data())[idx] = v;
+                }
 }
 
 void mfma_fragments(const double* Gc, int K, int dt, std::vector<unsigned char>& out)

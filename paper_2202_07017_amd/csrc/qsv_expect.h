@@ -10,7 +10,7 @@ constexpr int kMaxTileTerms = 48;
 
 // One Pauli term inside a tile pass.  kind: 0 diagonal, 1 general pair term,
 // 2 pure X string (z = 0, no Y).  dpart (diagonal terms): 1 = local mask in
-// the low 6 tile bits, 2 = in the high 6, 3 = straddles both.
+// the low 6 tile bits (or none), 2 = in the high 6, 3 = straddles both.
 struct XTerm {
     uint64_t z;
     double c;
@@ -18,15 +18,25 @@ struct XTerm {
     uint32_t xloc;  // x compressed to local bits (x lies inside the tile)
     int32_t kind;
     int32_t dpart;
-    int32_t ylo;    // number of Y factors mod 4 (32-bit fields: scalar loads)
+    int32_t ylo;    // number of Y factors mod 4
 };
 
+// Terms of a pass, in this order:
+//   [0, nx)        diagonal, z inside the tile, local mask in both table halves
+//   [nx, nd)       diagonal, z partly outside the tile, local mask not empty
+//   [nd, no)       diagonal, z wholly outside the tile (a constant per tile)
+//   [no, pstart)   diagonal, z inside the tile, local mask in one table half
+//   [pstart, pxend) pure X strings;  [pxend, nt) other pair terms.
+// Terms whose sign depends on the tile ([nx, no) and the pair terms) get it
+// once per tile; the others are folded into per-block tables.
 struct TileExpK {
     uint64_t ntiles;
-    InsertSpec ins;  // tile qubits, ascending (zeros inserted into the tile index)
+    InsertSpec ins;  // the kTileQubits tile qubits, ascending (zeros inserted into the tile index)
     int L;           // contiguous low run of tile qubits
-    int nt;          // terms [0, nstr): straddling diagonal; [nstr, pstart): table diagonal;
-    int nstr;        //       [pstart, pxend): pure X strings; [pxend, nt): other pair terms
+    int nt;
+    int nx;
+    int nd;
+    int no;
     int pstart;
     int pxend;
     int ndiag;       // number of diagonal terms (0: no diagonal part in this pass)

@@ -66,6 +66,7 @@ struct GateLaunch {
     uint64_t choff[32] = {};
     int tloc[5] = {};
     int floc[6] = {};
+    int mfma3 = 1;           // mfma: three-product kernel (0: real-embedding kernel)
     // diagonal run: amplitude i is multiplied by entry tau_f(i) of factor f's
     // table for every factor f with (i & run_fix[f]) == run_val[f]; tau_f bit j
     // = bit run_tpos[f][j] of i (run_nt[f] <= 5 varying bits).  The tables
@@ -103,6 +104,7 @@ hipError_t launch_mfma(const GateLaunch& L, void* psi, void* psi2, hipStream_t s
 // Fill the MFMA A-operand fragments of the real embedding of a canonical
 // k-qubit complex128 matrix, in state precision (host side).
 void mfma_fragments(const double* Gc, int K, int dt, std::vector<unsigned char>& out);
+void mfma3_fragments(const double* Gc, int K, int dt, std::vector<unsigned char>& out);
 
 // kernels_reduce.hip
 int reduce_blocks(int n, int dt);

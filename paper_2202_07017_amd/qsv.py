@@ -71,6 +71,8 @@ _SIGS = {
     "qsv_norm2": ([_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
     "qsv_expectation": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsv_pauli_sum), _vp, _vp,
                          _vp], ctypes.c_int),
+    "qsv_expectation_launches": ([ctypes.POINTER(qsv_pauli_sum), ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "qsv_expectation_noalloc": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsv_pauli_sum),
                                  _vp, _vp], ctypes.c_int),
     "qsv_inner": ([_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
@@ -291,6 +293,14 @@ def qsv_expectation(psi, H, out=None, stream=None):
     _check(lib().qsv_expectation(_ptr(psi), _nqubits(psi), dtype_code(psi), ctypes.byref(P.s),
                                  _ptr(out), _ptr(reduce_workspace(psi.device)), _stream(stream)))
     return out
+
+
+def expectation_launches(H, n: int, dtype_code_: int) -> int:
+    """Kernel launches one qsv_expectation of H on an n-qubit state enqueues."""
+    P = H if isinstance(H, PauliSum) else PauliSum(H)
+    c = ctypes.c_int()
+    _check(lib().qsv_expectation_launches(ctypes.byref(P.s), n, dtype_code_, ctypes.byref(c)))
+    return c.value
 
 
 def qsv_expectation_noalloc(psi, H, out=None, stream=None):

@@ -161,3 +161,14 @@ def test_forced_launch_failure_reports_hip_error(q, forced_failure):
     for j, call in enumerate(calls):
         assert call() == q.ERR_HIP, j
         assert "QSV_TEST_FAIL_LAUNCH" in L.qsv_last_error().decode(), j
+
+
+def test_expectation_launch_count(q):
+    """Host-only query: one launch per pass over the state plus the final
+    reduction; a diagonal-only sum at n >= 12 is one tile pass."""
+    import workloads as W
+    assert q.expectation_launches(W.tfim_chain(30), 30, q.C64) == 5
+    assert q.expectation_launches(W.pauli_sum(20, [("ZZ", (0, 19), 1.0), ("Z", (3,), 0.5)]), 20, q.C128) == 2
+    assert q.expectation_launches(W.pauli_sum(5, [("Z", (0,), 1.0)]), 5, q.C64) == 2
+    with pytest.raises(q.QsvError):
+        q.expectation_launches(W.tfim_chain(30), 29, q.C64)

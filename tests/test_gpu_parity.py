@@ -159,7 +159,9 @@ def test_diagonal_gates(q, orc):
 
 @pytest.mark.parametrize("n", [10, 11, 12, 14])
 def test_four_and_five_qubit_gates(q, orc, n):
-    """k = 4, 5: matrix cores (uncontrolled, n >= k + 6) and the VALU path."""
+    """k = 4, 5: matrix cores (uncontrolled, n >= k + 6) in both product
+    forms (three real products and one real-embedded product), and the VALU
+    path."""
     rng = np.random.default_rng(200 + n)
     for name in DTYPES:
         psi = rand_state(n, rng, name)
@@ -169,14 +171,17 @@ def test_four_and_five_qubit_gates(q, orc, n):
                       tuple(int(v) for v in rng.choice(n, k, replace=False))]
             for t in places:
                 G = W.haar_unitary(rng, 2 ** k)
-                for mfma in ["1", "0"]:
-                    os.environ["QSV_NO_MFMA"] = "0" if mfma == "1" else "1"
-                    say("k45", name, n, t, "mfma" if mfma == "1" else "valu")
+                for path in ["3m", "real", "valu"]:
+                    os.environ["QSV_NO_MFMA"] = "1" if path == "valu" else "0"
+                    os.environ["QSV_MFMA_FORM"] = path
+                    say("k45", name, n, t, path)
                     gate_case(q, orc, psi, name, t, (), G)
+                os.environ.pop("QSV_MFMA_FORM", None)
                 ctl = [v for v in range(n) if v not in t][:1]
                 say("k45 controlled", name, n, t, ctl)
                 gate_case(q, orc, psi, name, t, tuple(ctl), G)
     os.environ.pop("QSV_NO_MFMA", None)
+    os.environ.pop("QSV_MFMA_FORM", None)
 
 
 @pytest.mark.parametrize("n", [10, 13])
@@ -193,11 +198,13 @@ def test_low_dense_gates_as_four_qubit_blocks(q, orc, n):
         for base in sets:
             for t in itertools.permutations(base):
                 G = W.haar_unitary(rng, 2 ** len(t))
-                for mfma in ["1", "0"]:
-                    os.environ["QSV_NO_MFMA"] = "0" if mfma == "1" else "1"
-                    say("low dense", name, n, t, "mfma" if mfma == "1" else "valu")
+                for path in ["3m", "real", "valu"]:
+                    os.environ["QSV_NO_MFMA"] = "1" if path == "valu" else "0"
+                    os.environ["QSV_MFMA_FORM"] = path
+                    say("low dense", name, n, t, path)
                     gate_case(q, orc, psi, name, t, (), G)
     os.environ.pop("QSV_NO_MFMA", None)
+    os.environ.pop("QSV_MFMA_FORM", None)
 
 
 def test_apply_fused(q, orc):
