@@ -26,6 +26,7 @@
  * Compile with -ffp-contract=off so no product is fused into an FMA.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -159,6 +160,12 @@ int orc_apply(int n, const double* in, double* out, const int* t, int k, const i
     }
     free(src);
     return 0;
+}
+
+/* Threads the OpenMP loops of this library use (for reports). */
+int orc_threads(void)
+{
+    return omp_get_max_threads();
 }
 
 /* --------------------------------------------------------- pairwise sums */
