@@ -18,6 +18,7 @@
 #include "qsv_internal.h"
 #include "qsv_expect.h"
 #include "qsv_host.h"
+#include "qsv_rpass.h"
 
 using namespace qsv;
 
@@ -736,15 +737,189 @@ void plan_tiles(const qsv_pauli_sum* H, int n, std::vector<TileExpK>& out,
     }
 }
 
+// Register-tile passes for the terms they can take (n >= kTileQubits):
+// diagonal terms, single-qubit X on qubits >= 5 (grouped, in term order,
+// into register sets of kRegQubits qubits) and single-qubit X on qubits 0..4
+// (after the transpose of the first pass).  Every other term index goes to
+// `rest` (LDS-tile passes).
+void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, std::vector<int>& rest)
+{
+    const uint64_t lowq = (1ull << (kRegLanes - 1)) - 1;  // qubits 0..4
+    std::vector<int> diag, low, high;
+    for (int j = 0; j < H->nterms; ++j) {
+        const uint64_t x = H->x_mask[j];
+        const bool xone = x != 0 && (x & (x - 1)) == 0 && H->z_mask[j] == 0;  // a single-qubit X
+        if (x == 0)
+            diag.push_back(j);
+        else if (xone && (x & lowq))
+            low.push_back(j);
+        else if (xone)
+            high.push_back(j);
+        else
+            rest.push_back(j);
+    }
+    // register sets
+    std::vector<std::pair<uint64_t, std::vector<int>>> sets;
+    std::vector<bool> used(high.size(), false);
+    for (size_t i = 0; i < high.size(); ++i) {
+        if (used[i])
+            continue;
+        uint64_t Q = 0;
+        std::vector<int> take;
+        for (size_t k = i; k < high.size(); ++k) {
+            if (used[k])
+                continue;
+            const uint64_t x = H->x_mask[high[k]];
+            if (__builtin_popcountll(Q | x) <= kRegQubits) {
+                Q |= x;
+                take.push_back(high[k]);
+                used[k] = true;
+            }
+        }
+        sets.push_back({Q, take});
+    }
+    if (sets.empty() && (!diag.empty() || !low.empty()))
+        sets.push_back({0, {}});
+    for (size_t si = 0; si < sets.size(); ++si) {
+        uint64_t Q = sets[si].first;
+        // fill the register set up to kRegQubits qubits with the lowest free ones >= 5
+        for (int q = kRegLanes - 1; q < n && __builtin_popcountll(Q) < kRegQubits; ++q)
+            Q |= 1ull << q;
+        std::vector<int> qreg;
+        for (int q = 0; q < n; ++q)
+            if ((Q >> q) & 1)
+                qreg.push_back(q);
+        int h = kRegLanes - 1;
+        while ((Q >> h) & 1)
+            ++h;
+        std::vector<int> tileq = qreg;
+        for (int b = 0; b < kRegLanes - 1; ++b)
+            tileq.push_back(b);
+        tileq.push_back(h);
+        std::sort(tileq.begin(), tileq.end());
+        RegPassK k{};
+        k.ntiles = 1ull << (n - kRegTileQubits);
+        for (int j = 0; j < kRegTileQubits; ++j)
+            k.low[j] = (1ull << tileq[j]) - 1;
+        for (int j = 0; j < kRegQubits; ++j)
+            k.qstride[j] = 1ull << qreg[j];
+        for (int b = 0; b < kRegLanes - 1; ++b)
+            k.lanepos[b] = b;
+        k.lanepos[kRegLanes - 1] = h;
+        auto comp_reg = [&](uint64_t v) {
+            uint32_t o = 0;
+            for (int j = 0; j < kRegQubits; ++j)
+                if ((v >> qreg[j]) & 1)
+                    o |= 1u << j;
+            return o;
+        };
+        auto comp_lane = [&](uint64_t v) {
+            uint32_t o = 0;
+            for (int b = 0; b < kRegLanes; ++b)
+                if ((v >> k.lanepos[b]) & 1)
+                    o |= 1u << b;
+            return o;
+        };
+        auto comp_lane2 = [&](uint64_t v) {  // transposed lane roles
+            uint32_t o = (uint32_t)((v >> h) & 1);
+            for (int j = 0; j < kRegQubits; ++j)
+                if ((v >> qreg[j]) & 1)
+                    o |= 1u << (1 + j);
+            return o;
+        };
+        auto term = [&](int j, int phase) {
+            RTerm t{};
+            const uint64_t x = H->x_mask[j], z = H->z_mask[j];
+            t.z = z;
+            t.c = H->coeff[j];
+            t.ylo = __builtin_popcountll(x & z) & 3;
+            if (phase == 2) {
+                t.xr = (uint32_t)(x & lowq);
+                t.zr = (uint32_t)(z & lowq);
+                t.zl = comp_lane2(z);
+            } else {
+                t.xr = comp_reg(x);
+                t.zr = comp_reg(z);
+                t.zl = comp_lane(z);
+            }
+            return t;
+        };
+        // launches of <= kMaxRegTerms terms with this geometry: the first
+        // register set also takes the diagonal and low-qubit strings
+        std::vector<std::pair<int, int>> items;  // (term, phase 0 diag / 1 register / 2 low)
+        // the diagonal terms ride with the second register set when there is
+        // one and the first also takes the transposed low-qubit strings
+        // (measured: TFIM at n = 30, complex64 7.55 -> 7.15 ms, complex128
+        // 14.5 -> 13.1 ms)
+        const size_t dset = (sets.size() > 1 && !low.empty()) ? 1 : 0;
+        if (si == dset) {
+            for (int j : diag)
+                items.push_back({j, 0});
+        }
+        for (int j : sets[si].second)
+            items.push_back({j, 1});
+        if (si == 0) {
+            for (int j : low)
+                items.push_back({j, 2});
+        }
+        size_t pos = 0;
+        do {
+            RegPassK L = k;
+            int nt = 0, cnt[3] = {0, 0, 0};
+            std::vector<RTerm> byphase[3];
+            while (pos < items.size() && nt < kMaxRegTerms) {
+                byphase[items[pos].second].push_back(term(items[pos].first, items[pos].second));
+                ++cnt[items[pos].second];
+                ++nt;
+                ++pos;
+            }
+            // diagonal terms sorted by register mask, with group offsets
+            std::stable_sort(byphase[0].begin(), byphase[0].end(),
+                             [](const RTerm& x, const RTerm& y) { return x.zr < y.zr; });
+            for (int m = 0, q = 0; m <= (1 << kRegQubits); ++m) {
+                while (q < (int)byphase[0].size() && (int)byphase[0][q].zr < m)
+                    ++q;
+                L.mofs[m] = q;
+            }
+            int w = 0;
+            for (int ph = 0; ph < 3; ++ph)
+                for (const RTerm& t : byphase[ph])
+                    L.t[w++] = t;
+            L.nd = cnt[0];
+            L.n1 = cnt[0] + cnt[1];
+            L.nt = nt;
+            out.push_back(L);
+        } while (pos < items.size());
+    }
+}
+
 qsv_status enqueue_expectation(const void* psi, int n, int dt, const qsv_pauli_sum* H, double* out,
                                double* work, int ncomp, hipStream_t s)
 {
     int acc = 0;
     const int nb = reduce_blocks(n, dt);
     if (n >= kTileQubits) {
+        std::vector<RegPassK> regs;
+        std::vector<int> rest;
+        plan_reg_passes(H, n, regs, rest);
+        for (const RegPassK& k : regs) {
+            hipError_t e = launch_reg_pass(k, psi, dt, work, nb, acc, s);
+            if (e != hipSuccess)
+                return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
+            acc = 1;
+        }
+        std::vector<uint64_t> rx, rz;
+        std::vector<double> rc;
+        for (int j : rest) {
+            rx.push_back(H->x_mask[j]);
+            rz.push_back(H->z_mask[j]);
+            rc.push_back(H->coeff[j]);
+        }
+        const qsv_pauli_sum Hr{(int)rest.size(), rx.data(), rz.data(), rc.data()};
         std::vector<TileExpK> tiles;
         std::vector<std::pair<uint64_t, TermChunk>> leftover;
-        plan_tiles(H, n, tiles, leftover);
+        if (!rest.empty())
+            plan_tiles(&Hr, n, tiles, leftover);
         for (const TileExpK& k : tiles) {
             hipError_t e = launch_tile_pass(k, psi, nullptr, dt, false, work, nb, acc, s);
             if (e != hipSuccess)
@@ -755,6 +930,7 @@ qsv_status enqueue_expectation(const void* psi, int n, int dt, const qsv_pauli_s
             hipError_t e = launch_expect_pair(psi, n, dt, pr.first, pr.second, work, acc, s);
             if (e != hipSuccess)
                 return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
+            acc = 1;
         }
     } else {
         std::vector<TermChunk> diag;
@@ -1024,10 +1200,24 @@ qsv_status qsv_expectation_launches(const qsv_pauli_sum* H, int n, qsv_dtype dt,
         return fail(QSV_ERR_ARG, "nlaunches is NULL");
     int count = 1;  // the finalize
     if (n >= kTileQubits) {
-        std::vector<TileExpK> tiles;
-        std::vector<std::pair<uint64_t, TermChunk>> leftover;
-        plan_tiles(H, n, tiles, leftover);
-        count += (int)(tiles.size() + leftover.size());
+        std::vector<RegPassK> regs;
+        std::vector<int> rest;
+        plan_reg_passes(H, n, regs, rest);
+        count += (int)regs.size();
+        if (!rest.empty()) {
+            std::vector<uint64_t> rx, rz;
+            std::vector<double> rc;
+            for (int j : rest) {
+                rx.push_back(H->x_mask[j]);
+                rz.push_back(H->z_mask[j]);
+                rc.push_back(H->coeff[j]);
+            }
+            const qsv_pauli_sum Hr{(int)rest.size(), rx.data(), rz.data(), rc.data()};
+            std::vector<TileExpK> tiles;
+            std::vector<std::pair<uint64_t, TermChunk>> leftover;
+            plan_tiles(&Hr, n, tiles, leftover);
+            count += (int)(tiles.size() + leftover.size());
+        }
     } else {
         std::vector<TermChunk> diag;
         std::vector<std::pair<uint64_t, TermChunk>> pairs;

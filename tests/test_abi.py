@@ -165,9 +165,11 @@ def test_forced_launch_failure_reports_hip_error(q, forced_failure):
 
 def test_expectation_launch_count(q):
     """Host-only query: one launch per pass over the state plus the final
-    reduction; a diagonal-only sum at n >= 12 is one tile pass."""
+    reduction; TFIM at n = 30 is five register passes (X on five qubits each,
+    the first also the ZZ terms and, after its transpose, X on qubits 0..4); a
+    diagonal-only sum at n >= 12 is one register pass."""
     import workloads as W
-    assert q.expectation_launches(W.tfim_chain(30), 30, q.C64) == 5
+    assert q.expectation_launches(W.tfim_chain(30), 30, q.C64) == 6
     assert q.expectation_launches(W.pauli_sum(20, [("ZZ", (0, 19), 1.0), ("Z", (3,), 0.5)]), 20, q.C128) == 2
     assert q.expectation_launches(W.pauli_sum(5, [("Z", (0,), 1.0)]), 5, q.C64) == 2
     with pytest.raises(q.QsvError):

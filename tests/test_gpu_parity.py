@@ -277,6 +277,53 @@ def test_observables_tiled(q, orc, n):
             check_close(to_np(out) / scale, orc.apply_hamiltonian(psi, H) / scale, name, "H psi")
 
 
+def register_pass_sum(n, seed):
+    """Pauli sums shaped for the register passes: diagonal strings anywhere,
+    X/Y strings on one or two qubits >= 5 or on one or two of qubits 0..4 with
+    random Z/Y factors elsewhere, plus terms the passes leave to the LDS tiles
+    (three-qubit x masks, masks straddling qubits 4 and 5)."""
+    rng = np.random.default_rng(seed)
+    terms = [("", (), 0.3)]
+    for _ in range(12):
+        qs = [int(v) for v in rng.choice(n, int(rng.integers(1, 4)), replace=False)]
+        terms.append(("Z" * len(qs), qs, float(rng.normal())))
+    for lo in (False, True):
+        for _ in range(10):
+            pool = list(range(5)) if lo else list(range(5, n))
+            xq = [int(v) for v in rng.choice(pool, int(rng.integers(1, 3)), replace=False)]
+            letters = "".join(rng.choice(["X", "Y"]) for _ in xq)
+            others = [v for v in range(n) if v not in xq]
+            zq = [int(v) for v in rng.choice(others, int(rng.integers(0, 3)), replace=False)]
+            terms.append((letters + "Z" * len(zq), xq + zq, float(rng.normal())))
+    terms.append(("XXX", (1, 7, n - 1), 0.7))
+    terms.append(("XY", (4, 5), -0.4))
+    terms.append(("YZX", (0, 6, 9), 0.25))
+    return W.pauli_sum(n, terms)
+
+
+@pytest.mark.parametrize("n", [12, 15, 19])
+def test_observables_register_passes(q, orc, n):
+    """Expectation values through the register-tile passes (diagonal terms
+    via the per-lane Walsh-Hadamard sums, strings on register qubits, strings
+    on qubits 0..4 after the LDS transpose) and the LDS-tile fallback for the
+    other terms, against the oracle; the imaginary part stays at rounding
+    level (exactly 0 from the register passes)."""
+    rng = np.random.default_rng(400 + n)
+    for name in DTYPES:
+        psi = rand_state(n, rng, name)
+        d = to_gpu(psi, name)
+        for seed in (1, 2, 3):
+            H = register_pass_sum(n, 50 * n + seed)
+            say("register-pass expectation", name, n, seed, len(H.coeff))
+            e = q.qsv_expectation(d, H).cpu().numpy()
+            ref = orc.expect(psi, H)
+            scale = np.sum(np.abs(H.coeff))
+            assert abs(e[0] - ref.real) <= 1e-10 * scale, (e, ref)
+            assert abs(e[1]) <= 1e-10 * scale
+            e2 = q.qsv_expectation_noalloc(d, H).cpu().numpy()
+            assert np.array_equal(e, e2)
+
+
 def test_plan_random_circuit(q, orc):
     """Random U(2) layers with CZ pairs (n = 20, depth 10): every fusion width
     and graph replay against the oracle, plus <Z_0>."""
