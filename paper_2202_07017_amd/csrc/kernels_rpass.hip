@@ -35,6 +35,14 @@ namespace {
 constexpr int kNR = 1 << kRegQubits;  // 32 amplitudes per lane
 constexpr int kWaves = 4;             // waves per block
 constexpr int kRow = 64 + 3;          // transpose row: 64 lanes + padding; lanes 32..63 skewed by one
+// Diagonal terms of one register mask are taken in chunks of up to kChunk
+// consecutive terms; a chunk's 2^g signed coefficient sums (one per sign
+// pattern of its g terms) sit in an LDS table, so a lane's weight for the
+// chunk is one table read indexed by its g sign bits.  Since 2^g <= 32 g / 5
+// for 1 <= g <= 5, the tables of kMaxRegTerms terms need at most
+// 32 * kMaxRegTerms / 5 entries.
+constexpr int kChunk = 5;
+constexpr int kDiagTab = (32 * kMaxRegTerms) / kChunk + 1;
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -99,15 +107,31 @@ __device__ __forceinline__ double pair_dispatch(uint32_t xr, const double (&re)[
     }
 }
 
+// Term data held across the wave: lane k keeps term k's coefficient, z mask
+// and register x mask in registers, and the tile loop fetches them with
+// readlane (a register read) instead of a scalar memory load per term.
+struct LaneTerms {
+    double c;
+    uint64_t z;
+    uint32_t xr;
+};
+
+__device__ __forceinline__ double term_coef(const LaneTerms& L, int k)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(L.c), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(L.c), k);
+    return __hiloint2double(hi, lo);
+}
+
 // Terms [k0, k1): single-qubit X on a register qubit of the current roles.
 // For Hermitian X the pairs (i, i ^ x) add 2 Re(conj(psi_i) psi_(i ^ x)).
-__device__ __forceinline__ double pair_terms(const RegPassK& a, int k0, int k1, const double (&re)[kNR],
+__device__ __forceinline__ double pair_terms(const LaneTerms& L, int k0, int k1, const double (&re)[kNR],
                                              const double (&im)[kNR])
 {
     double s = 0.0;
     for (int k = k0; k < k1; ++k) {
-        const RTerm& T = a.t[k];
-        s += 2.0 * T.c * pair_dispatch(T.xr, re, im);
+        const uint32_t xr = (uint32_t)__builtin_amdgcn_readlane((int)L.xr, k);
+        s += 2.0 * term_coef(L, k) * pair_dispatch(xr, re, im);
     }
     return s;
 }
@@ -119,6 +143,7 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
     using A = typename RV<R>::A;
     __shared__ A xt[TR ? kWaves * kNR * kRow : 1];
     __shared__ double red[kWaves];
+    __shared__ double dtab[kDiagTab];
     const int lane = threadIdx.x & 63;
     const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint64_t w0 = (uint64_t)blockIdx.x * kWaves + wv;
@@ -131,11 +156,39 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
     uint64_t lsg = 0;
     for (int k = 0; k < a.nd; ++k)
         lsg |= (uint64_t)(__popc((uint32_t)lane & a.t[k].zl) & 1) << k;
+    // signed coefficient sums of every chunk: entry p of a chunk starting at
+    // term k0 with g terms = sum_i (-1)^(bit i of p) c_(k0+i)
+    if (a.nd > 0) {
+        int off = 0;
+        for (int m = 0; m < kNR; ++m) {
+            const int k1 = a.mofs[m + 1];
+            for (int k0 = a.mofs[m]; k0 < k1; k0 += kChunk) {
+                const int g = min(kChunk, k1 - k0);
+                for (int q = threadIdx.x; q < (1 << g); q += blockDim.x) {
+                    double w = 0.0;
+                    for (int i = 0; i < g; ++i)
+                        w += ((q >> i) & 1) ? -a.t[k0 + i].c : a.t[k0 + i].c;
+                    dtab[off + q] = w;
+                }
+                off += 1 << g;
+            }
+        }
+        __syncthreads();
+    }
+    LaneTerms LT{0.0, 0, 0};
+    if (lane < a.nt) {
+        LT.c = a.t[lane].c;
+        LT.z = a.t[lane].z;
+        LT.xr = a.t[lane].xr;
+    }
     double acc = 0.0;
-    for (uint64_t tl = w0; tl < a.ntiles; tl += nw) {
-        const uint64_t base = insert_tile(tl, a);
-        const A* p = reinterpret_cast<const A*>(psi) + base;
-        A v[kNR];
+    // Software pipeline: the loads of the wave's next tile are issued as soon
+    // as the current tile has been widened to FP64, so every term below runs
+    // while they are in flight.
+    A v[kNR];
+    const A* const p0 = reinterpret_cast<const A*>(psi) + loff;
+    auto load_tile = [&](uint64_t b) {
+        const A* p = p0 + b;
 #pragma unroll
         for (int r = 0; r < kNR; ++r) {
             uint64_t o = 0;
@@ -143,8 +196,13 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
             for (int k = 0; k < kRegQubits; ++k)
                 if ((r >> k) & 1)
                     o += a.qstride[k];
-            v[r] = __builtin_nontemporal_load(p + o + loff);
+            v[r] = __builtin_nontemporal_load(p + o);
         }
+    };
+    if (w0 < a.ntiles)
+        load_tile(insert_tile(w0, a));
+    for (uint64_t tl = w0; tl < a.ntiles; tl += nw) {
+        const uint64_t base = insert_tile(tl, a);
         A* rows = TR ? xt + wv * (kNR * kRow) : nullptr;
         if (TR && a.nt > a.n1) {
             // transpose through this wave's LDS rows: element (lane l,
@@ -155,49 +213,49 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
             for (int r = 0; r < kNR; ++r)
                 rows[r * kRow + lane + (lane >> 5)] = v[r];
         }
-        double s = 0.0;
-        if (a.nd > 0) {
-            double N[kNR];
+        double re[kNR], im[kNR];
 #pragma unroll
-            for (int r = 0; r < kNR; ++r) {
-                const double x = (double)v[r].x, y = (double)v[r].y;
-                N[r] = x * x + y * y;
-            }
+        for (int r = 0; r < kNR; ++r) {
+            re[r] = (double)v[r].x;
+            im[r] = (double)v[r].y;
+        }
+        if (tl + nw < a.ntiles)
+            load_tile(insert_tile(tl + nw, a));
+        double s = 0.0;
+        if (a.n1 > a.nd)
+            s += pair_terms(LT, a.nd, a.n1, re, im);
+        if (a.nd > 0) {
+            // N(m) = sum_r (-1)^popcount(r & m) |psi_(lane,r)|^2, built in
+            // place of re (the pair terms are done with it)
+#pragma unroll
+            for (int r = 0; r < kNR; ++r)
+                re[r] = re[r] * re[r] + im[r] * im[r];
 #pragma unroll
             for (int h = 1; h < kNR; h <<= 1)
 #pragma unroll
                 for (int r = 0; r < kNR; ++r)
                     if (!(r & h)) {
-                        const double u = N[r], w = N[r + h];
-                        N[r] = u + w;
-                        N[r + h] = u - w;
+                        const double u = re[r], w = re[r + h];
+                        re[r] = u + w;
+                        re[r + h] = u - w;
                     }
-            // tile part of the signs (uniform), then the terms grouped by
-            // their register mask: each group adds (sum of signed
-            // coefficients) * N(m) with m known at compile time
-            uint64_t bsg = 0;
-            for (int k = 0; k < a.nd; ++k)
-                bsg |= (uint64_t)(__popcll(base & a.t[k].z) & 1) << k;
+            // tile part of the signs (uniform: lane k evaluates term k's
+            // parity and a ballot gathers them), then per register mask m
+            // (known at compile time) its chunks: the lane's sign bits of a
+            // chunk index its table of signed coefficient sums
+            const uint64_t bsg = __ballot(lane < a.nd && (__popcll(base & LT.z) & 1));
             const uint64_t sg = lsg ^ bsg;
+            int off = 0;
 #pragma unroll
             for (int m = 0; m < kNR; ++m) {
-                const int k0 = a.mofs[m], k1 = a.mofs[m + 1];
-                if (k0 == k1)
-                    continue;
-                double w = 0.0;
-                for (int k = k0; k < k1; ++k)
-                    w += ((sg >> k) & 1) ? -a.t[k].c : a.t[k].c;
-                s += w * N[m];
+                const int k1 = a.mofs[m + 1];
+                for (int k0 = a.mofs[m]; k0 < k1; k0 += kChunk) {
+                    const int g = min(kChunk, k1 - k0);
+                    const int q = (int)(sg >> k0) & ((1 << g) - 1);
+                    s += dtab[off + q] * re[m];
+                    off += 1 << g;
+                }
             }
-        }
-        double re[kNR], im[kNR];
-        if (a.n1 > a.nd) {
-#pragma unroll
-            for (int r = 0; r < kNR; ++r) {
-                re[r] = (double)v[r].x;
-                im[r] = (double)v[r].y;
-            }
-            s += pair_terms(a, a.nd, a.n1, re, im);
         }
         if (TR && a.nt > a.n1) {
             __builtin_amdgcn_wave_barrier();
@@ -209,7 +267,7 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
                 im[r] = (double)w.y;
             }
             __builtin_amdgcn_wave_barrier();
-            s += pair_terms(a, a.n1, a.nt, re, im);
+            s += pair_terms(LT, a.n1, a.nt, re, im);
         }
         acc += s;
     }
@@ -279,6 +337,14 @@ hipError_t launch_reg_pass(const RegPassK& a, const void* psi, int dt, double* p
 {
     if (a.ntiles == 0)
         return hipSuccess;
+    // the term tables assume nd <= nt <= kMaxRegTerms and mofs ascending from
+    // 0 to nd (the chunk tables then fit in kDiagTab entries)
+    if (a.nt > kMaxRegTerms || a.nd < 0 || a.nd > a.n1 || a.n1 > a.nt || a.mofs[0] != 0 ||
+        a.mofs[1 << kRegQubits] != a.nd)
+        return hipErrorInvalidValue;
+    for (int m = 0; m < (1 << kRegQubits); ++m)
+        if (a.mofs[m + 1] < a.mofs[m])
+            return hipErrorInvalidValue;
     const bool tr = a.nt > a.n1;
     if (dt == C64)
         return tr ? go<float, true>(a, psi, partials, nslots, accumulate, s)
