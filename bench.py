@@ -119,13 +119,15 @@ def oracle_gate_rates(n, targets, reps=1):
 
 def cpu_baseline():
     """The CPU oracle (never tuned) on a bounded sample of the headline sweep:
-    one Haar U(2) gate at targets 0, 15 and 29 of a seeded 30-qubit complex128
-    state on every host thread, and at targets 0, 15 and 27 of a 28-qubit
-    state on one thread (a child process with OMP_NUM_THREADS=1; one thread at
-    30 qubits would take ~10 s per gate).  value = mean all-thread GB/s."""
+    one Haar U(2) gate at every target 0..29 of a seeded 30-qubit complex128
+    state on every host thread (the GPU's per-target sweep, one gate each),
+    and at targets 0, 15 and 27 of a 28-qubit state on one thread (a child
+    process with OMP_NUM_THREADS=1; one thread at 30 qubits would take ~10 s
+    per gate).  value = mean all-thread GB/s over the 30 targets."""
     import subprocess
+    n = 30
     t0 = time.perf_counter()
-    rates, threads = oracle_gate_rates(30, (0, 15, 29))
+    rates, threads = oracle_gate_rates(n, tuple(range(n)))
     t_all = time.perf_counter() - t0
     env = dict(os.environ, OMP_NUM_THREADS="1")
     code = ("import json, sys; sys.path.insert(0, %r); import bench; r, th = bench.oracle_gate_rates(28, (0, 15, 27)); "
@@ -141,10 +143,11 @@ def cpu_baseline():
     t_one = time.perf_counter() - t1
     value = sum(rates.values()) / len(rates)
     res = {"value": round(value, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-           "sample": "oracle eq.(1), complex128, out of place: one Haar U(2) gate at targets 0, 15, 29 of "
-                     "a seeded 30-qubit state (16 GiB in + 16 GiB out) on %d threads (%.1f s incl. state "
-                     "set-up); GB/s counts 2 x 16 B per amplitude like the GPU figure" % (threads, t_all),
-           "per_target_gbs": {str(k): round(v, 3) for k, v in rates.items()},
+           "sample": "oracle eq.(1), complex128, out of place: one Haar U(2) gate at each target 0..29 of "
+                     "a seeded 30-qubit state (16 GiB in + 16 GiB out per gate) on %d threads (%.1f s incl. "
+                     "state set-up); GB/s counts 2 x 16 B per amplitude like the GPU figure" % (threads, t_all),
+           "seconds": round(t_all, 1),
+           "per_target_gbs": [round(rates[t], 2) for t in range(n)],
            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
            "affinity_cpus": len(os.sched_getaffinity(0)),
            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
@@ -219,7 +222,7 @@ def main():
     ap.add_argument("--profile-mfma", action="store_true",
                     help="only fused k = 4, 5 blocks (matrix-core counter runs)")
     ap.add_argument("--legs", default="",
-                    help="comma list of side legs to run alone (adjoint, adjoint26, batched, configs, measure, circuits): profiling runs")
+                    help="comma list of side legs to run alone (adjoint, adjoint26, batched, configs, expect, measure, circuits): profiling runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X and this build has no "
@@ -249,6 +252,8 @@ def main():
             out["batched"] = batched_leg(qsv, W, torch, np, dev)
         if "configs" in legs:
             out["configs"] = configs_leg(qsv, W, torch, np, dev, torch.cuda.current_stream())
+        if "expect" in legs:
+            out["expectation"] = expectation_leg(qsv, W, torch, np, dev, torch.cuda.current_stream())
         if "measure" in legs:
             out["measure"] = measure_leg(qsv, W, torch, np, dev, torch.cuda.current_stream())
         if "circuits" in legs:
@@ -338,10 +343,35 @@ def main():
         out["adjoint_n26"] = adjoint_leg_large(qsv, W, torch, np, dev)
         out["batched"] = batched_leg(qsv, W, torch, np, dev)
         out["configs"] = configs_leg(qsv, W, torch, np, dev, stream)
+        out["expectation"] = expectation_leg(qsv, W, torch, np, dev, stream)
         out["measure"] = measure_leg(qsv, W, torch, np, dev, stream)
         out["qft_trotter"] = qft_trotter_leg(qsv, W, torch, np, dev, stream)
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+
+
+def expectation_leg(qsv, W, torch, np, dev, stream, n=30):
+    """<psi|H|psi> on a seeded 30-qubit state for the open-chain TFIM (h = 1),
+    the XXZ chain (Delta = 0.5) and 64 random Pauli strings: ms per
+    evaluation, kernel launches, and GB/s counting one read of the state (the
+    least any implementation needs)."""
+    res = {}
+    hams = (("tfim", W.tfim_chain(n)), ("xxz", W.xxz_chain(n, 0.5)), ("random64", W.random_pauli_sum(n, 64, 77)))
+    for name, dt, code, S in (("c64", torch.complex64, qsv.C64, 8), ("c128", torch.complex128, qsv.C128, 16)):
+        psi = torch.empty(1 << n, dtype=dt, device=dev)
+        qsv.qsv_init_random(psi, 4004)
+        out = torch.empty(2, dtype=torch.float64, device=dev)
+        for tag, h in hams:
+            H = qsv.PauliSum(h)
+            qsv.qsv_expectation(psi, H, out)
+            a = event_time(lambda: qsv.qsv_expectation(psi, H, out), 5, stream)
+            res["%s_n%d_%s" % (tag, n, name)] = {
+                "ms": round(a * 1e3, 3), "launches": qsv.expectation_launches(H, n, code),
+                "terms": int(len(h.coeff)),
+                "gbs_one_read": round(S * (1 << n) / a / 1e9, 1)}
+        del psi
+        torch.cuda.empty_cache()
+    return res
 
 
 def measure_leg(qsv, W, torch, np, dev, stream, n=30, shots=1 << 20):
