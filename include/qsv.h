@@ -127,7 +127,11 @@ qsv_status qsv_init_random(void* psi, int n, qsv_dtype dt, uint64_t seed, void* 
  * bits are 1 (Sec. 2).  G need not be unitary.  The library recognises exact
  * 0/1 permutation matrices (moved bit-exactly, no arithmetic) and diagonal
  * matrices (only entries != 1 are touched), and uses MFMA matrix cores for
- * uncontrolled k = 4, 5.  k <= 5; c any (k + c <= n). */
+ * uncontrolled k = 4, 5.  k <= 5; c any (k + c <= n).  For k >= 4 the
+ * matrix (or its matrix-core fragments) is staged into a small per-stream
+ * device ring by a kernel on `stream` whose arguments carry the bytes: the
+ * host never waits for the device, and the ring slot is reused in stream
+ * order.  The first such call on a stream allocates the ring (256 KiB). */
 qsv_status qsv_apply_gate(void* psi, int n, qsv_dtype dt, const int* targets, int k,
                           const int* controls, int c, const double* G, void* stream);
 
@@ -140,8 +144,9 @@ typedef struct {
 } qsv_block;
 
 /* Apply nblocks blocks in order.  Block matrices are staged to device memory
- * with an asynchronous copy on `stream` before the kernels that use them.
- * Not capturable into a HIP graph (use a plan instead). */
+ * as for qsv_apply_gate (stream-ordered staging kernels, no host wait) before
+ * the kernels that use them.  Not capturable into a HIP graph (use a plan
+ * instead). */
 qsv_status qsv_apply_fused(void* psi, int n, qsv_dtype dt, const qsv_block* blocks, int nblocks,
                            void* stream);
 
@@ -168,9 +173,14 @@ qsv_status qsv_norm2(const void* psi, int n, qsv_dtype dt, double* out_dev, void
                      void* stream);
 
 /* out_dev[0] = Re <psi|H|psi>, out_dev[1] = Im (a rounding diagnostic; 0 in
- * exact arithmetic for real coefficients), accumulated in FP64 in a fixed
- * order.  Diagonal terms share one pass; other terms share a pass per
- * distinct x_mask.  out_dev: 2 doubles, device. */
+ * exact arithmetic for real coefficients; terms taken by the register passes
+ * below visit each Hermitian pair once and add exactly 0 to it), accumulated
+ * in FP64 in a fixed order.  For n >= 12: diagonal strings and single-qubit X
+ * strings go to register passes (one read of psi per set of up to five X
+ * qubits above qubit 4); other strings to 12-qubit tile passes grouped by x
+ * mask; a string no tile holds to a pass of its own x mask.
+ * qsv_expectation_launches reports the launch count.  out_dev: 2 doubles,
+ * device. */
 qsv_status qsv_expectation(const void* psi, int n, qsv_dtype dt, const qsv_pauli_sum* H,
                            double* out_dev, void* work, void* stream);
 

@@ -487,64 +487,54 @@ GateLaunch rotation_launch(int n, int dt, int rot, int target, const int* ctl, i
 // -------------------------------------------------------- device staging
 
 namespace {
-// Per (device, stream) double-buffered staging of small host arrays: a pinned
-// host slot is refilled only after the copy that last used it has finished,
-// and the device slot is reused in stream order.
-struct Slot {
-    void* host = nullptr;
-    void* dev = nullptr;
-    size_t cap = 0;
-    hipEvent_t ev = nullptr;
-    bool used = false;
-};
-struct StageEntry {
-    Slot slot[2];
+// Per (device, stream) ring of device slots for the tables of single calls
+// (qsv_apply_gate / qsv_apply_fused with k >= 4).  A slot is filled by a
+// staging kernel on the stream, so its reuse is ordered after the kernel that
+// read it, and no host thread ever waits for the device.
+constexpr int kStageSlots = 8;
+constexpr size_t kStageSlotBytes = 32768;  // the largest table: k = 5 complex128 matrix-core fragments
+struct StageRing {
+    unsigned char* dev = nullptr;
     int next = 0;
 };
 std::mutex g_stage_mu;
-std::map<std::pair<int, hipStream_t>, StageEntry> g_stage;
+std::map<std::pair<int, hipStream_t>, StageRing> g_stage;
 }  // namespace
 
 qsv_status stage_upload(const void* host, size_t bytes, hipStream_t s, const void** dev_out)
 {
+    if (bytes > kStageSlotBytes)
+        return fail(QSV_ERR_UNSUPPORTED, "staged table of %zu bytes exceeds the %zu-byte slot", bytes,
+                    kStageSlotBytes);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess)
         return fail(QSV_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
-    std::lock_guard<std::mutex> lk(g_stage_mu);
-    StageEntry& ent = g_stage[{dev, s}];
-    Slot& sl = ent.slot[ent.next];
-    ent.next ^= 1;
-    if (sl.used) {
-        e = hipEventSynchronize(sl.ev);
-        if (e != hipSuccess)
-            return fail(QSV_ERR_HIP, "staging event: %s", hipGetErrorString(e));
-    }
-    if (sl.cap < bytes) {
-        if (sl.dev) {
-            hipStreamSynchronize(s);
-            hipFree(sl.dev);
-            hipHostFree(sl.host);
+    unsigned char* slot = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        StageRing& r = g_stage[{dev, s}];
+        if (!r.dev) {
+            void* p = nullptr;
+            if (hipMalloc(&p, kStageSlots * kStageSlotBytes) != hipSuccess)
+                return fail(QSV_ERR_NOMEM, "staging ring of %zu bytes", kStageSlots * kStageSlotBytes);
+            r.dev = static_cast<unsigned char*>(p);
         }
-        size_t cap = bytes < (1u << 16) ? (1u << 16) : bytes;
-        if (hipMalloc(&sl.dev, cap) != hipSuccess || hipHostMalloc(&sl.host, cap, 0) != hipSuccess) {
-            sl.dev = sl.host = nullptr;
-            sl.cap = 0;
-            return fail(QSV_ERR_NOMEM, "staging allocation of %zu bytes failed", cap);
-        }
-        sl.cap = cap;
-        if (!sl.ev && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess)
-            return fail(QSV_ERR_HIP, "hipEventCreate failed");
+        slot = r.dev + (size_t)r.next * kStageSlotBytes;
+        r.next = (r.next + 1) % kStageSlots;
     }
-    std::memcpy(sl.host, host, bytes);
-    e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s);
+    // pad to a whole number of 16-byte words
+    const size_t padded = (bytes + 15) & ~(size_t)15;
+    if (padded != bytes) {
+        std::vector<unsigned char> tmp(padded, 0);
+        std::memcpy(tmp.data(), host, bytes);
+        e = launch_stage(slot, tmp.data(), padded, s);
+    } else {
+        e = launch_stage(slot, host, bytes, s);
+    }
     if (e != hipSuccess)
-        return fail(QSV_ERR_HIP, "staging copy: %s", hipGetErrorString(e));
-    e = hipEventRecord(sl.ev, s);
-    if (e != hipSuccess)
-        return fail(QSV_ERR_HIP, "staging event record: %s", hipGetErrorString(e));
-    sl.used = true;
-    *dev_out = sl.dev;
+        return fail(QSV_ERR_HIP, "staging launch: %s", hipGetErrorString(e));
+    *dev_out = slot;
     return QSV_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <vector>
 
 namespace qsv {
@@ -128,6 +129,12 @@ hipError_t launch_finalize(const double* partials, int nblocks, int ncomp, doubl
 // returns the current device's address of it (looked up once per device with
 // hipGetSymbolAddress; the array's name is not a device address on the host).
 constexpr size_t kStaticScratchBytes = 32768;
+
+// Staging of small host tables into device memory in stream order (a kernel
+// whose arguments carry the bytes, kStageChunkBytes per launch); bytes and
+// dst must be multiples of 16.
+constexpr int kStageChunkBytes = 2048;
+hipError_t launch_stage(void* dst, const void* host, size_t bytes, hipStream_t s);
 hipError_t static_scratch(double** ptr);
 hipError_t launch_hpsi_diag(const void* psi, void* lam, int n, int dt, const TermChunk& t,
                             int accumulate, hipStream_t s);
