@@ -324,6 +324,34 @@ def test_observables_register_passes(q, orc, n):
             assert np.array_equal(e, e2)
 
 
+@pytest.mark.parametrize("n", [13, 19])
+def test_observables_register_many_terms(q, orc, n):
+    """A single X on every qubit (several register sets, the transposed set
+    for qubits 0..4) with more diagonal strings than one register launch
+    holds (48): Z on every qubit, every neighbouring ZZ, 30 random Z triples
+    and the identity, so the diagonal terms split over launches and several
+    register masks carry more than one five-term sign-table chunk."""
+    rng = np.random.default_rng(900 + n)
+    terms = [("", (), 0.5)]
+    terms += [("X", (j,), float(rng.normal())) for j in range(n)]
+    terms += [("Z", (j,), float(rng.normal())) for j in range(n)]
+    terms += [("ZZ", (j, j + 1), float(rng.normal())) for j in range(n - 1)]
+    for _ in range(30):
+        qs = [int(v) for v in rng.choice(n, 3, replace=False)]
+        terms.append(("ZZZ", qs, float(rng.normal())))
+    H = W.pauli_sum(n, terms)
+    assert q.expectation_launches(H, n, q.C64) >= 3
+    for name in DTYPES:
+        psi = rand_state(n, rng, name)
+        d = to_gpu(psi, name)
+        say("register-pass expectation, many terms", name, n, len(H.coeff))
+        e = q.qsv_expectation(d, H).cpu().numpy()
+        ref = orc.expect(psi, H)
+        scale = np.sum(np.abs(H.coeff))
+        assert abs(e[0] - ref.real) <= 1e-10 * scale, (e, ref)
+        assert abs(e[1]) <= 1e-10 * scale
+
+
 def test_plan_random_circuit(q, orc):
     """Random U(2) layers with CZ pairs (n = 20, depth 10): every fusion width
     and graph replay against the oracle, plus <Z_0>."""
