@@ -736,14 +736,18 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
 {
     const uint64_t lowq = (1ull << (kRegLanes - 1)) - 1;  // qubits 0..4
     std::vector<int> diag, low, high;
+    // diagonal strings; strings whose x mask is one or two of qubits 0..4;
+    // strings whose x mask is one or two qubits above 4 (both with a z check
+    // once the register qubits are known, below); the rest go to the
+    // LDS-tile passes
     for (int j = 0; j < H->nterms; ++j) {
         const uint64_t x = H->x_mask[j];
-        const bool xone = x != 0 && (x & (x - 1)) == 0 && H->z_mask[j] == 0;  // a single-qubit X
+        const int px = __builtin_popcountll(x);
         if (x == 0)
             diag.push_back(j);
-        else if (xone && (x & lowq))
+        else if (px <= 2 && (x & ~lowq) == 0)
             low.push_back(j);
-        else if (xone)
+        else if (px <= 2 && (x & lowq) == 0)
             high.push_back(j);
         else
             rest.push_back(j);
@@ -817,6 +821,9 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
                     o |= 1u << (1 + j);
             return o;
         };
+        uint64_t tilemask = 0;
+        for (int q : tileq)
+            tilemask |= 1ull << q;
         auto term = [&](int j, int phase) {
             RTerm t{};
             const uint64_t x = H->x_mask[j], z = H->z_mask[j];
@@ -832,7 +839,37 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
                 t.zr = comp_reg(z);
                 t.zl = comp_lane(z);
             }
+            if (phase != 0) {
+                // 2 Re w times i^ylo's sign (ylo 0: +, 2: -), or 2 Im w (ylo 1:
+                // -, 3: +); the half sum s1 (lower x bit of the pair's first
+                // member set) also takes the register part of the z sign
+                const double cf = (t.ylo == 1 || t.ylo == 2) ? -2.0 * t.c : 2.0 * t.c;
+                const bool two = (t.xr & (t.xr - 1)) != 0;
+                const bool slb = two && (t.zr & t.xr & (0u - t.xr)) != 0;
+                t.c = cf;
+                t.c2 = slb ? -cf : cf;
+            }
             return t;
+        };
+        // strings of one phase with the same x mask, Re/Im kind, lane z bits
+        // and z bits outside the tile share every sign but the register one
+        // (already in c2): one term with the summed coefficients
+        auto merge = [&](std::vector<RTerm>& v) {
+            std::vector<RTerm> out;
+            for (const RTerm& t : v) {
+                bool done = false;
+                for (RTerm& u : out)
+                    if (u.xr == t.xr && ((u.ylo ^ t.ylo) & 1) == 0 && u.zl == t.zl &&
+                        (u.z & ~tilemask) == (t.z & ~tilemask)) {
+                        u.c += t.c;
+                        u.c2 += t.c2;
+                        done = true;
+                        break;
+                    }
+                if (!done)
+                    out.push_back(t);
+            }
+            v.swap(out);
         };
         // launches of <= kMaxRegTerms terms with this geometry: the first
         // register set also takes the diagonal and low-qubit strings
@@ -846,11 +883,26 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
             for (int j : diag)
                 items.push_back({j, 0});
         }
-        for (int j : sets[si].second)
-            items.push_back({j, 1});
+        // a string's x mask must be one register bit of its phase or two
+        // neighbouring ones, and its z bits on those register qubits must lie
+        // in the x mask (the pass signs pairs by the lower x bit only); other
+        // strings go to the LDS-tile passes
+        auto reg_ok = [](uint32_t xr) {
+            return xr != 0 && ((xr & (xr - 1)) == 0 || (xr >> __builtin_ctz(xr)) == 3u);
+        };
+        for (int j : sets[si].second) {
+            if (reg_ok(comp_reg(H->x_mask[j])) && (H->z_mask[j] & Q & ~H->x_mask[j]) == 0)
+                items.push_back({j, 1});
+            else
+                rest.push_back(j);
+        }
         if (si == 0) {
-            for (int j : low)
-                items.push_back({j, 2});
+            for (int j : low) {
+                if (reg_ok((uint32_t)(H->x_mask[j] & lowq)) && (H->z_mask[j] & lowq & ~H->x_mask[j]) == 0)
+                    items.push_back({j, 2});
+                else
+                    rest.push_back(j);
+            }
         }
         size_t pos = 0;
         do {
@@ -863,9 +915,19 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
                 ++nt;
                 ++pos;
             }
-            // diagonal terms sorted by register mask, with group offsets
+            // diagonal terms sorted by register mask, with group offsets;
+            // in the other phases single-qubit X strings without Z or Y
+            // factors (the short pair sums) come first
             std::stable_sort(byphase[0].begin(), byphase[0].end(),
                              [](const RTerm& x, const RTerm& y) { return x.zr < y.zr; });
+            auto plain = [](const RTerm& t) { return t.z == 0 && __builtin_popcount(t.xr) == 1; };
+            int nplain[3] = {0, 0, 0};
+            for (int ph = 1; ph < 3; ++ph) {
+                merge(byphase[ph]);
+                cnt[ph] = (int)byphase[ph].size();
+                std::stable_partition(byphase[ph].begin(), byphase[ph].end(), plain);
+                nplain[ph] = (int)std::count_if(byphase[ph].begin(), byphase[ph].end(), plain);
+            }
             for (int m = 0, q = 0; m <= (1 << kRegQubits); ++m) {
                 while (q < (int)byphase[0].size() && (int)byphase[0][q].zr < m)
                     ++q;
@@ -876,8 +938,10 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
                 for (const RTerm& t : byphase[ph])
                     L.t[w++] = t;
             L.nd = cnt[0];
+            L.ns1 = cnt[0] + nplain[1];
             L.n1 = cnt[0] + cnt[1];
-            L.nt = nt;
+            L.ns2 = L.n1 + nplain[2];
+            L.nt = cnt[0] + cnt[1] + cnt[2];
             out.push_back(L);
         } while (pos < items.size());
     }

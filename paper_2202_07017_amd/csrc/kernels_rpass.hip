@@ -3,21 +3,27 @@
 // A wave takes a tile of 2^11 amplitudes: its 64 lanes run over 6 lane
 // qubits (qubits 0..4 and one more, so every load instruction reads runs of
 // 32 consecutive amplitudes) and each lane holds the 32 amplitudes of 5
-// register qubits.  The pass evaluates, from registers only, the two kinds
-// of terms that dominate the transverse-field and Ising-type Hamiltonians:
+// register qubits.  The pass evaluates, from registers only, the kinds of
+// terms that make up Ising- and Heisenberg-type Hamiltonians:
 //
 //  * a single-qubit X on a register qubit pairs amplitude i = (lane, r) with
 //    j = (lane, r ^ 2^k); the two contributions conj(psi_i) psi_j and
 //    conj(psi_j) psi_i are complex conjugates, so each pair is visited once
 //    and adds 2 Re(conj(psi_i) psi_j);
+//  * any string whose x mask is one or two register qubits (XX, YY, XY, Y,
+//    with Z factors anywhere except on the other register qubits) the same
+//    way, with 2 Re or 2 Im of the pair product by its number of Y factors
+//    and the sign of its z mask on the pair's first member (register part:
+//    that member's lower x bit; lane part fixed per lane; tile part per
+//    tile);
 //  * diagonal terms sum (-1)^popcount(i & z) |psi_i|^2.  With the per-lane
 //    Walsh-Hadamard transform N(m) = sum_r (-1)^popcount(r & m) |psi_(lane,r)|^2
 //    (five butterfly stages), a term costs its two signs (lane part, fixed
 //    per lane, and tile part) however many amplitudes the tile holds; terms
 //    come grouped by their register mask m, so N(m) is read at a
 //    compile-time index;
-//  * a single-qubit X on qubits 0..4 (lane bits) is evaluated after an LDS
-//    transpose of the wave's tile that makes qubits 0..4 the register
+//  * strings whose x mask lies on qubits 0..4 (lane bits) are evaluated after
+//    an LDS transpose of the wave's tile that makes qubits 0..4 the register
 //    qubits.
 //
 // Every other Pauli string goes to the LDS-tile passes (kernels_expect.hip).
@@ -112,31 +118,107 @@ __device__ __forceinline__ double pair_dispatch(uint32_t xr, const double (&re)[
 // readlane (a register read) instead of a scalar memory load per term.
 struct LaneTerms {
     double c;
+    double c2;
     uint64_t z;
     uint32_t xr;
+    int32_t ylo;
 };
 
-__device__ __forceinline__ double term_coef(const LaneTerms& L, int k)
+__device__ __forceinline__ double lane_double(double v, int k)
 {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(L.c), k);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(L.c), k);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
     return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ double term_coef(const LaneTerms& L, int k) { return lane_double(L.c, k); }
+
 // Terms [k0, k1): single-qubit X on a register qubit of the current roles.
-// For Hermitian X the pairs (i, i ^ x) add 2 Re(conj(psi_i) psi_(i ^ x)).
+// For Hermitian X the pairs (i, i ^ x) add 2 Re(conj(psi_i) psi_(i ^ x)); the
+// factor 2 is in the term's coefficient.
 __device__ __forceinline__ double pair_terms(const LaneTerms& L, int k0, int k1, const double (&re)[kNR],
                                              const double (&im)[kNR])
 {
     double s = 0.0;
     for (int k = k0; k < k1; ++k) {
         const uint32_t xr = (uint32_t)__builtin_amdgcn_readlane((int)L.xr, k);
-        s += 2.0 * term_coef(L, k) * pair_dispatch(xr, re, im);
+        s += term_coef(L, k) * pair_dispatch(xr, re, im);
     }
     return s;
 }
 
-template <typename R, bool TR>
+// A string P with x mask on register bits XR (one bit or two neighbouring
+// ones) and a z mask whose register bits lie inside XR: over the pairs
+// (a, b = a ^ x) with a the member whose highest x bit (HB) is 0,
+//   <psi|P|psi> = sum_pairs c i^ylo (-1)^(z.a) [w + (-1)^ylo conj(w)],
+// w = conj(psi_b) psi_a, i.e. 2 Re w (ylo even) or 2 Im w (ylo odd) times
+// (+-1) and (-1)^(z.a).  The register part of (-1)^(z.a) is (-1)^(a_LB) when
+// z has the lowest x bit LB (a_HB = 0), so the pairs are summed in two
+// halves by a_LB (s0: a_LB = 0, s1: a_LB = 1; for a single x bit the halves
+// simply alternate) and the host folds that sign into the coefficient of s1.
+struct Halves {
+    double s0, s1;
+};
+
+template <int XR, bool IM>
+__device__ __forceinline__ Halves gen_sum(const double (&re)[kNR], const double (&im)[kNR])
+{
+    constexpr int HB = (XR & 16) ? 4 : (XR & 8) ? 3 : (XR & 4) ? 2 : (XR & 2) ? 1 : 0;
+    constexpr int LB = (XR & 1) ? 0 : (XR & 2) ? 1 : (XR & 4) ? 2 : (XR & 8) ? 3 : 4;
+    double s0 = 0.0, s1 = 0.0;
+    int m = 0;
+#pragma unroll
+    for (int r = 0; r < kNR; ++r) {
+        if ((r >> HB) & 1)
+            continue;
+        const int j = r ^ XR;
+        const double d = IM ? im[r] * re[j] - re[r] * im[j] : re[r] * re[j] + im[r] * im[j];
+        if (LB != HB ? ((r >> LB) & 1) : (m++ & 1))
+            s1 += d;
+        else
+            s0 += d;
+    }
+    return Halves{s0, s1};
+}
+
+// x masks of one register bit or two neighbouring ones (each further case
+// costs registers: with all ten two-bit masks a complex64 pass no longer fits
+// two waves per SIMD); the host sends other masks to the LDS-tile passes
+template <bool IM>
+__device__ __forceinline__ Halves gen_dispatch(uint32_t xr, const double (&re)[kNR], const double (&im)[kNR])
+{
+    switch (xr) {
+    case 1: return gen_sum<1, IM>(re, im);
+    case 2: return gen_sum<2, IM>(re, im);
+    case 4: return gen_sum<4, IM>(re, im);
+    case 8: return gen_sum<8, IM>(re, im);
+    case 16: return gen_sum<16, IM>(re, im);
+    case 3: return gen_sum<3, IM>(re, im);
+    case 6: return gen_sum<6, IM>(re, im);
+    case 12: return gen_sum<12, IM>(re, im);
+    case 24: return gen_sum<24, IM>(re, im);
+    default: return Halves{0.0, 0.0};
+    }
+}
+
+// Terms [k0, k1): strings with an x mask of one register bit or two
+// neighbouring ones of the current roles (merged as described at RTerm).  sg
+// bit k set: the lane and tile parts of the z sign are negative for term k.
+__device__ __forceinline__ double gen_terms(const LaneTerms& L, uint64_t sg, int k0, int k1,
+                                            const double (&re)[kNR], const double (&im)[kNR])
+{
+    double s = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const uint32_t xr = (uint32_t)__builtin_amdgcn_readlane((int)L.xr, k);
+        const int ylo = __builtin_amdgcn_readlane(L.ylo, k);
+        const Halves h = (ylo & 1) ? gen_dispatch<true>(xr, re, im) : gen_dispatch<false>(xr, re, im);
+        const double v = lane_double(L.c, k) * h.s0 + lane_double(L.c2, k) * h.s1;
+        s += ((sg >> k) & 1) ? -v : v;
+    }
+    return s;
+}
+
+template <typename R, bool TR, bool GEN>
 __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, const RegPassK a,
                                                   double* __restrict__ partials, int pstride, int accumulate)
 {
@@ -152,9 +234,9 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
 #pragma unroll
     for (int b = 0; b < kRegLanes; ++b)
         loff |= (uint64_t)((lane >> b) & 1) << a.lanepos[b];
-    // lane part of every diagonal term's sign, once: bit k = parity(lane & zl_k)
+    // lane part of every term's sign, once: bit k = parity(lane & zl_k)
     uint64_t lsg = 0;
-    for (int k = 0; k < a.nd; ++k)
+    for (int k = 0; k < a.nt; ++k)
         lsg |= (uint64_t)(__popc((uint32_t)lane & a.t[k].zl) & 1) << k;
     // signed coefficient sums of every chunk: entry p of a chunk starting at
     // term k0 with g terms = sum_i (-1)^(bit i of p) c_(k0+i)
@@ -175,16 +257,20 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
         }
         __syncthreads();
     }
-    LaneTerms LT{0.0, 0, 0};
+    LaneTerms LT{0.0, 0.0, 0, 0, 0};
     if (lane < a.nt) {
         LT.c = a.t[lane].c;
+        LT.c2 = a.t[lane].c2;
         LT.z = a.t[lane].z;
         LT.xr = a.t[lane].xr;
+        LT.ylo = a.t[lane].ylo;
     }
     double acc = 0.0;
-    // Software pipeline: the loads of the wave's next tile are issued as soon
-    // as the current tile has been widened to FP64, so every term below runs
-    // while they are in flight.
+    // Software pipeline (passes without the general string sums): the loads
+    // of the wave's next tile are issued as soon as the current tile has been
+    // widened to FP64, so every term below runs while they are in flight.
+    // The general sums need the registers of that second tile.
+    constexpr bool kPrefetch = !GEN;
     A v[kNR];
     const A* const p0 = reinterpret_cast<const A*>(psi) + loff;
     auto load_tile = [&](uint64_t b) {
@@ -199,10 +285,12 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
             v[r] = __builtin_nontemporal_load(p + o);
         }
     };
-    if (w0 < a.ntiles)
+    if (kPrefetch && w0 < a.ntiles)
         load_tile(insert_tile(w0, a));
     for (uint64_t tl = w0; tl < a.ntiles; tl += nw) {
         const uint64_t base = insert_tile(tl, a);
+        if (!kPrefetch)
+            load_tile(base);
         A* rows = TR ? xt + wv * (kNR * kRow) : nullptr;
         if (TR && a.nt > a.n1) {
             // transpose through this wave's LDS rows: element (lane l,
@@ -219,11 +307,13 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
             re[r] = (double)v[r].x;
             im[r] = (double)v[r].y;
         }
-        if (tl + nw < a.ntiles)
+        if (kPrefetch && tl + nw < a.ntiles)
             load_tile(insert_tile(tl + nw, a));
+        // tile part of every term's sign (uniform: lane k evaluates term k's
+        // parity with the tile base and a ballot gathers them)
+        const uint64_t sg = lsg ^ __ballot(lane < a.nt && (__popcll(base & LT.z) & 1));
         double s = 0.0;
-        if (a.n1 > a.nd)
-            s += pair_terms(LT, a.nd, a.n1, re, im);
+        s += GEN ? gen_terms(LT, sg, a.nd, a.n1, re, im) : pair_terms(LT, a.nd, a.n1, re, im);
         if (a.nd > 0) {
             // N(m) = sum_r (-1)^popcount(r & m) |psi_(lane,r)|^2, built in
             // place of re (the pair terms are done with it)
@@ -239,12 +329,9 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
                         re[r] = u + w;
                         re[r + h] = u - w;
                     }
-            // tile part of the signs (uniform: lane k evaluates term k's
-            // parity and a ballot gathers them), then per register mask m
-            // (known at compile time) its chunks: the lane's sign bits of a
-            // chunk index its table of signed coefficient sums
-            const uint64_t bsg = __ballot(lane < a.nd && (__popcll(base & LT.z) & 1));
-            const uint64_t sg = lsg ^ bsg;
+            // per register mask m (known at compile time) its chunks: the
+            // lane's sign bits of a chunk index its table of signed
+            // coefficient sums
             int off = 0;
 #pragma unroll
             for (int m = 0; m < kNR; ++m) {
@@ -258,6 +345,7 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
             }
         }
         if (TR && a.nt > a.n1) {
+            // the transposed roles
             __builtin_amdgcn_wave_barrier();
             const A* src = rows + (lane >> 1) * kRow + ((lane & 1) ? 33 : 0);
 #pragma unroll
@@ -267,7 +355,7 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
                 im[r] = (double)w.y;
             }
             __builtin_amdgcn_wave_barrier();
-            s += pair_terms(LT, a.n1, a.nt, re, im);
+            s += GEN ? gen_terms(LT, sg, a.n1, a.nt, re, im) : pair_terms(LT, a.n1, a.nt, re, im);
         }
         acc += s;
     }
@@ -293,7 +381,7 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
         }
 }
 
-template <typename R, bool TR>
+template <typename R, bool TR, bool GEN>
 int reg_grid()
 {
     static int cache[64] = {0};
@@ -302,7 +390,7 @@ int reg_grid()
         return 1024;
     if (cache[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_reg_pass<R, TR>, 256, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_reg_pass<R, TR, GEN>, 256, 0) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             per_cu < 1 || cus < 1)
             return 1024;
@@ -311,13 +399,13 @@ int reg_grid()
     return cache[dev];
 }
 
-template <typename R, bool TR>
+template <typename R, bool TR, bool GEN>
 hipError_t go(const RegPassK& a, const void* psi, double* partials, int nslots, int accumulate,
               hipStream_t s)
 {
     // every resident block once (capped by the partial slots), each wave
     // streaming tiles
-    uint64_t g = (uint64_t)reg_grid<R, TR>();
+    uint64_t g = (uint64_t)reg_grid<R, TR, GEN>();
     if (g > (uint64_t)nslots)
         g = (uint64_t)nslots;
     const uint64_t maxg = (a.ntiles + kWaves - 1) / kWaves;
@@ -325,9 +413,26 @@ hipError_t go(const RegPassK& a, const void* psi, double* partials, int nslots, 
         g = maxg;
     if (g < 1)
         g = 1;
-    hipLaunchKernelGGL((k_reg_pass<R, TR>), dim3((unsigned)g), dim3(256), 0, s, static_cast<const R*>(psi), a,
-                       partials, nslots, accumulate);
+    hipLaunchKernelGGL((k_reg_pass<R, TR, GEN>), dim3((unsigned)g), dim3(256), 0, s, static_cast<const R*>(psi),
+                       a, partials, nslots, accumulate);
     return hipGetLastError();
+}
+
+// The variant: complex64 or complex128; with the transpose when strings on
+// qubits 0..4 are present; with the general string sums only when needed
+// (they cost registers, and complex64 passes without them keep two waves
+// per SIMD).
+template <typename R>
+hipError_t pick(const RegPassK& a, const void* psi, double* partials, int nslots, int accumulate,
+                hipStream_t s)
+{
+    const bool tr = a.nt > a.n1;
+    const bool gen = a.n1 > a.ns1 || a.nt > a.ns2;
+    if (tr)
+        return gen ? go<R, true, true>(a, psi, partials, nslots, accumulate, s)
+                   : go<R, true, false>(a, psi, partials, nslots, accumulate, s);
+    return gen ? go<R, false, true>(a, psi, partials, nslots, accumulate, s)
+               : go<R, false, false>(a, psi, partials, nslots, accumulate, s);
 }
 
 }  // namespace
@@ -339,18 +444,14 @@ hipError_t launch_reg_pass(const RegPassK& a, const void* psi, int dt, double* p
         return hipSuccess;
     // the term tables assume nd <= nt <= kMaxRegTerms and mofs ascending from
     // 0 to nd (the chunk tables then fit in kDiagTab entries)
-    if (a.nt > kMaxRegTerms || a.nd < 0 || a.nd > a.n1 || a.n1 > a.nt || a.mofs[0] != 0 ||
-        a.mofs[1 << kRegQubits] != a.nd)
+    if (a.nt > kMaxRegTerms || a.nd < 0 || a.nd > a.ns1 || a.ns1 > a.n1 || a.n1 > a.ns2 || a.ns2 > a.nt ||
+        a.mofs[0] != 0 || a.mofs[1 << kRegQubits] != a.nd)
         return hipErrorInvalidValue;
     for (int m = 0; m < (1 << kRegQubits); ++m)
         if (a.mofs[m + 1] < a.mofs[m])
             return hipErrorInvalidValue;
-    const bool tr = a.nt > a.n1;
-    if (dt == C64)
-        return tr ? go<float, true>(a, psi, partials, nslots, accumulate, s)
-                  : go<float, false>(a, psi, partials, nslots, accumulate, s);
-    return tr ? go<double, true>(a, psi, partials, nslots, accumulate, s)
-              : go<double, false>(a, psi, partials, nslots, accumulate, s);
+    return dt == C64 ? pick<float>(a, psi, partials, nslots, accumulate, s)
+                     : pick<double>(a, psi, partials, nslots, accumulate, s);
 }
 
 }  // namespace qsv
