@@ -23,7 +23,10 @@
 // registers (16 per lane for k = 5).  Results go back to LDS and the tile is
 // stored in place.  One tile per workgroup, blocks in XCD-contiguous order:
 // on MI355X this streams faster than persistent tile loops (measured), and
-// the small register footprint keeps several workgroups per CU.
+// the small register footprint keeps several workgroups per CU.  The one
+// exception is the complex64 k = 5 three-product kernel below: it takes two
+// consecutive tiles per workgroup and issues the loads of the second as soon
+// as the first is in LDS, so they run under the first tile's products.
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -267,7 +270,7 @@ constexpr int mfma3_wpe()
     return (sizeof(R) == 4 && K == 4) ? 8 : 1;
 }
 
-template <typename R, int K>
+template <typename R, int K, int TPB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_wpe<R, K>()))) k_mfma3(R* __restrict__ psi0, R* __restrict__ psi1,
                                                const MfmaK<K> a, const R* __restrict__ frag)
 {
@@ -293,18 +296,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_
     const int rb = wave % RB;
     const int cb0 = (wave / RB) * CBW;
 
-    const uint64_t tile = xcd_block();
-    if (tile >= a.ntiles)
+    // TPB consecutive tiles per workgroup (TPB divides ntiles): the loads of
+    // the next tile are issued right after the current one is in LDS, so
+    // they run under its products
+    const uint64_t tile0 = xcd_block() * TPB;
+    if (tile0 >= a.ntiles)
         return;
-    const uint64_t base = insert_bits(tile, a.ins);
 
     uint64_t goff[VPT];
     NV in[VPT];
+    {
+        const uint64_t base0 = insert_bits(tile0, a.ins);
 #pragma unroll
-    for (int r = 0; r < VPT; ++r) {
-        const int loc = (tid + 256 * r) * APV;
-        goff[r] = a.choff[loc >> a.L] + (uint64_t)(loc & ((1 << a.L) - 1));
-        in[r] = __builtin_nontemporal_load(reinterpret_cast<const NV*>(psi + 2 * (base + goff[r])));
+        for (int r = 0; r < VPT; ++r) {
+            const int loc = (tid + 256 * r) * APV;
+            goff[r] = a.choff[loc >> a.L] + (uint64_t)(loc & ((1 << a.L) - 1));
+            in[r] = __builtin_nontemporal_load(reinterpret_cast<const NV*>(psi + 2 * (base0 + goff[r])));
+        }
     }
     // A operands of this wave's row block: Gr, Gi, Gr + Gi, KS values each
     // per lane, contiguous in the table ([rb][product][lane][kk]).
@@ -331,12 +339,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_
             pos[r][h] = (tau * kRow + j) * 2;
         }
     }
+    for (int it = 0; it < TPB; ++it) {
+    const uint64_t tile = tile0 + it;
+    const uint64_t base = insert_bits(tile, a.ins);
 #pragma unroll
     for (int r = 0; r < VPT; ++r)
 #pragma unroll
         for (int h = 0; h < APV; ++h)
             *reinterpret_cast<P2*>(&lds[pos[r][h]]) = P2{in[r][2 * h], in[r][2 * h + 1]};
     __syncthreads();
+    if (it + 1 < TPB) {
+        const uint64_t nb = insert_bits(tile + 1, a.ins);
+#pragma unroll
+        for (int r = 0; r < VPT; ++r)
+            in[r] = __builtin_nontemporal_load(reinterpret_cast<const NV*>(psi + 2 * (nb + goff[r])));
+    }
 
     // B: lane holds complex row 4 kk + lane / 16 of group (cb0 + c) * 16 +
     // lane % 16.  Reads in groups of KG k-steps, one group ahead of the
@@ -401,6 +418,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_
         }
         __builtin_nontemporal_store(o, reinterpret_cast<NV*>(psi + 2 * (base + goff[r])));
     }
+    if (TPB > 1)
+        __syncthreads();  // the LDS tile is rewritten by the next iteration
+    }
 }
 
 template <typename R, int K>
@@ -418,9 +438,21 @@ hipError_t mfma_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
         a.floc[j] = L.floc[j];
     if (L.ntiles > (1ull << 31))
         return hipErrorInvalidValue;
+    // complex64 k = 5 (three products) takes two tiles per workgroup:
+    // measured at n = 30 over nine target sets, 2-14% faster on eight and 4%
+    // slower on one; complex64 k = 4 and complex128 gained on some target sets
+    // and lost on others and keep one
+    if constexpr (sizeof(R) == 4 && K == 5) {
+        if (L.mfma3 && L.ntiles >= 2) {
+            hipLaunchKernelGGL((k_mfma3<R, K, 2>), dim3((unsigned)(L.ntiles / 2), p1 ? 2 : 1), dim3(256), 0, s,
+                               static_cast<R*>(p0), static_cast<R*>(p1 ? p1 : p0), a,
+                               static_cast<const R*>(L.gdev));
+            return hipGetLastError();
+        }
+    }
     dim3 grid((unsigned)L.ntiles, p1 ? 2 : 1);
     if (L.mfma3)
-        hipLaunchKernelGGL((k_mfma3<R, K>), grid, dim3(256), 0, s, static_cast<R*>(p0),
+        hipLaunchKernelGGL((k_mfma3<R, K, 1>), grid, dim3(256), 0, s, static_cast<R*>(p0),
                            static_cast<R*>(p1 ? p1 : p0), a, static_cast<const R*>(L.gdev));
     else
         hipLaunchKernelGGL((k_mfma<R, K>), grid, dim3(256), 0, s, static_cast<R*>(p0),
