@@ -54,7 +54,7 @@
  *    QSV_NO_MFMA=1              4- and 5-qubit blocks on the vector units
  *    QSV_MFMA_FORM=3m|real      matrix-core blocks as three real products (Gauss)
  *                               or one real-embedded product (default: three
- *                               products, except complex128 5-qubit blocks)
+ *                               products)
  *    QSV_NO_DIAG_RUN=1          plans keep consecutive diagonal gates as separate launches
  *    QSV_NO_TILES=1             per-gate adjoint instead of cache-blocked tile programs
  *    QSV_NO_LANE_SWEEP=1        no cross-lane exchange for low single-qubit targets

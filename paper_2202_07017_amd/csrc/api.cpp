@@ -359,11 +359,12 @@ Built build_launch(int n, int dt, const int* ct, int k, const int* ctl, int c, c
         L.ins = make_ins(B, 0);
         L.ntiles = 1ull << (n - k - 6);
         L.ngroups = L.ntiles;
-        // Three-product kernel by default; the real-embedding one for
-        // complex128 k = 5, where the three-product form needs more registers
-        // than four waves per SIMD allow and ran 6-10% slower (measured).
+        // Three-product kernel by default (complex128 k = 5 with two tiles
+        // per workgroup: with one it ran 6-10% slower than the real
+        // embedding, with two 0-7% faster, measured); QSV_MFMA_FORM=real
+        // selects the embedding.
         const char* form = std::getenv("QSV_MFMA_FORM");
-        L.mfma3 = (dt == QSV_C64 || k == 4) ? 1 : 0;
+        L.mfma3 = 1;
         if (form && std::strcmp(form, "real") == 0)
             L.mfma3 = 0;
         else if (form && std::strcmp(form, "3m") == 0)

@@ -24,7 +24,7 @@
 // stored in place.  One tile per workgroup, blocks in XCD-contiguous order:
 // on MI355X this streams faster than persistent tile loops (measured), and
 // the small register footprint keeps several workgroups per CU.  The one
-// exception is the complex64 k = 5 three-product kernel below: it takes two
+// exception is the k = 5 three-product kernel below: it takes two
 // consecutive tiles per workgroup and issues the loads of the second as soon
 // as the first is in LDS, so they run under the first tile's products.
 #include "qsv_internal.h"
@@ -262,8 +262,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma_w
 // of complex rows take 4 / RB waves each, each wave 4 / WPR of the four
 // 16-column group blocks.
 // Waves per SIMD the three-product kernel's register allocation must allow:
-// complex64 k = 4 fits 8 (60 VGPRs); the others take what they need
-// (complex128 k = 5 would spill under a 128-register cap).
+// complex64 k = 4 fits 8; the others take what they need (complex128 k = 5
+// would spill under a 128-register cap).
 template <typename R, int K>
 constexpr int mfma3_wpe()
 {
@@ -438,11 +438,11 @@ hipError_t mfma_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
         a.floc[j] = L.floc[j];
     if (L.ntiles > (1ull << 31))
         return hipErrorInvalidValue;
-    // complex64 k = 5 (three products) takes two tiles per workgroup:
-    // measured at n = 30 over nine target sets, 2-14% faster on eight and 4%
-    // slower on one; complex64 k = 4 and complex128 gained on some target sets
-    // and lost on others and keep one
-    if constexpr (sizeof(R) == 4 && K == 5) {
+    // k = 5 three-product blocks take two tiles per workgroup: measured at
+    // n = 30, complex64 2-14% faster on eight of nine target sets and 6%
+    // slower on one; complex128 0-7% faster than the real embedding on six of
+    // six; k = 4 gained on some sets and lost on others and keeps one
+    if constexpr (K == 5) {
         if (L.mfma3 && L.ntiles >= 2) {
             hipLaunchKernelGGL((k_mfma3<R, K, 2>), dim3((unsigned)(L.ntiles / 2), p1 ? 2 : 1), dim3(256), 0, s,
                                static_cast<R*>(p0), static_cast<R*>(p1 ? p1 : p0), a,
