@@ -1,9 +1,10 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
 
 The oracle (oracle/oracle.c) is driven through every entry point by
-tests/oracle_sanitize_check.c, and the tile-program compiler of the library
+tests/oracle_sanitize_check.c, the tile-program compiler of the library
 (paper_2202_07017_amd/csrc/tileprog.cpp) through tests/tileprog_check.cpp on
-random gate lists; both are built with g++/gcc and
+random gate lists, and the register-pass planner (csrc/rpass_plan.cpp)
+through tests/rpass_check.cpp on mixed Pauli sums; all are built with g++/gcc and
 -fsanitize=address,undefined -fno-sanitize-recover=all, so any out-of-bounds
 access, use after free, leak or undefined behaviour aborts the run.  The
 GPU code is not built here (GPU sanitizers are not available)."""
@@ -14,6 +15,9 @@ import numpy as np
 import pytest
 
 import workloads as W
+from test_rpass_plan import mixed_sum
+from test_rpass_plan import run as run_rpass
+from test_rpass_plan import sub
 from test_tileprog import hea_gates, random_gates, run_checker
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -65,3 +69,16 @@ def test_tile_program_ladder_under_sanitizers(orc, san_checker):
     circ = W.Circuit(11, [W.Op("matrix", (t,), controls=tuple(cs), matrix=np.asarray(M, complex))
                           for _, t, cs, _, M in gates])
     assert np.max(np.abs(got - orc.run(circ, psi0=psi))) < 1e-12
+
+
+def test_register_pass_planner_under_sanitizers(orc, tmp_path):
+    exe = str(tmp_path / "rpass_check")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I" + CSRC, "-I" + os.path.join(ROOT, "include")] + SAN +
+                   [os.path.join(ROOT, "tests", "rpass_check.cpp"), os.path.join(CSRC, "rpass_plan.cpp"),
+                    "-o", exe], check=True)
+    for n in (12, 14):
+        H = mixed_sum(n, 7 + n)
+        psi = orc.random_state(n, 99 + n)
+        _, rest, e_reg = run_rpass(exe, H, psi, tmp_path, env=ENV)
+        e_rest = orc.expect(psi, sub(H, rest)).real if rest else 0.0
+        assert abs(e_reg + e_rest - orc.expect(psi, H).real) <= 1e-12 * float(np.sum(np.abs(H.coeff)))
