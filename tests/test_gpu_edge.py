@@ -177,3 +177,81 @@ def test_forced_launch_failure_leaves_state_unchanged(q, monkeypatch):
         q.qsv_apply_gate(psi, (3,), (), G)
         torch.cuda.synchronize()
         assert not torch.equal(torch.view_as_real(psi), torch.view_as_real(before))
+
+
+def _device_to_host(ptr, nbytes):
+    """Copy nbytes at a raw device pointer to the host (hipMemcpy, device to
+    host), for buffers the library hands out as plain pointers."""
+    import ctypes
+    import torch
+    torch.cuda.synchronize()
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+    except OSError:
+        hip = ctypes.CDLL("/opt/rocm/lib/libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipMemcpy.restype = ctypes.c_int
+    buf = np.empty(nbytes, dtype=np.uint8)
+    assert hip.hipMemcpy(buf.ctypes.data, ptr, nbytes, 2) == 0
+    return buf
+
+
+def test_state_alloc_and_free(q, orc):
+    """qsv_state_alloc / qsv_state_free (the allocation entry points for C
+    callers): a basis state and a Hadamard on qubit 0 in the allocated
+    buffer, read back and checked against the oracle; argument errors."""
+    import ctypes
+    import torch
+    L = q.lib()
+    n = 12
+    H2 = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2)
+    for name, code, npdt in (("c64", q.C64, np.complex64), ("c128", q.C128, np.complex128)):
+        say("state alloc", name, n)
+        p = ctypes.c_void_p()
+        assert L.qsv_state_alloc(n, code, ctypes.byref(p)) == q.OK and p.value
+        assert L.qsv_init_basis(p, n, code, 5, None) == q.OK
+        tg = (ctypes.c_int * 1)(0)
+        G = np.ascontiguousarray(H2)
+        assert L.qsv_apply_gate(p, n, code, tg, 1, None, 0,
+                                G.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None) == q.OK
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+        ws = q.reduce_workspace(out.device)
+        assert L.qsv_norm2(p, n, code, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                           None) == q.OK
+        got = _device_to_host(p.value, np.dtype(npdt).itemsize << n).view(npdt).astype(np.complex128)
+        basis = np.zeros(1 << n, dtype=np.complex128)
+        basis[5] = 1.0
+        ref = orc.apply(basis, (0,), (), H2)
+        close(got, ref, name, "allocated state")
+        assert abs(float(out.cpu()[0]) - 1.0) < 1e-6
+        assert L.qsv_state_free(p) == q.OK
+    bad = ctypes.c_void_p()
+    assert L.qsv_state_alloc(0, q.C64, ctypes.byref(bad)) == q.ERR_ARG
+    assert L.qsv_state_alloc(12, 7, ctypes.byref(bad)) == q.ERR_ARG
+    assert L.qsv_state_alloc(12, q.C64, None) == q.ERR_ARG
+    assert L.qsv_state_free(None) == q.OK
+
+
+def test_adjoint_state_slot(q, orc):
+    """qsv_adjoint_state: after the forward sweep (qsv_adjoint_energy) slot 0
+    of the workspace holds U(theta)|0>, equal to the oracle's circuit run;
+    slots other than 0 and 1 are refused."""
+    import ctypes
+    import torch
+    n, layers = 10, 3
+    circ = W.hea(n, layers)
+    H = W.tfim_chain(n)
+    for name, code, npdt in (("c64", q.C64, np.complex64), ("c128", q.C128, np.complex128)):
+        say("adjoint state slot", name, n)
+        params = W.random_params(circ.nparams, 77)
+        plan = q.AdjointPlan(circ, H, code, 5)
+        pd = torch.from_numpy(params).to("cuda")
+        e = plan.energy(pd)
+        ptr = plan.state_ptr(0)
+        got = _device_to_host(ptr, np.dtype(npdt).itemsize << n).view(npdt).astype(np.complex128)
+        ref = orc.run(circ, params=params)
+        close(got, ref, name, "adjoint slot 0")
+        assert abs(float(e.cpu()[0]) - orc.expect(ref, H).real) <= 1e-5 * np.sum(np.abs(H.coeff))
+        p = ctypes.c_void_p()
+        assert q.lib().qsv_adjoint_state(plan.h, ctypes.c_void_p(plan.work.data_ptr()), 2,
+                                         ctypes.byref(p)) == q.ERR_ARG
