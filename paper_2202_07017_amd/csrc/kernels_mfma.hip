@@ -270,94 +270,22 @@ constexpr int mfma3_wpe()
     return (sizeof(R) == 4 && K == 4) ? 8 : 1;
 }
 
-template <typename R, int K, int TPB>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_wpe<R, K>()))) k_mfma3(R* __restrict__ psi0, R* __restrict__ psi1,
-                                               const MfmaK<K> a, const R* __restrict__ frag)
+// The products of one tile, between the barrier after the tile is in LDS
+// and the barrier before it is read back: B operands from LDS (lane holds
+// complex row 4 kk + lane / 16 of group (cb0 + c) * 16 + lane % 16, read in
+// groups of KG k-steps one group ahead of the products; scheduling barriers
+// keep the order), the three accumulators, and the complex results written
+// back over the tile in LDS.
+template <typename R, int K>
+__device__ __forceinline__ void mfma3_multiply(R* lds, const R (&afr)[3][(1 << K) / 4], int lane, int rb,
+                                               int cb0)
 {
     using T = MfmaT<R>;
-    using NV = typename T::NV;
     using P2 = typename Pair2<R>::T;
-    constexpr int D = 1 << K;           // complex rows (amplitudes per group)
-    constexpr int TA = D * 64;          // amplitudes per tile
-    constexpr int APV = T::APV;
-    constexpr int VPT = TA / APV / 256; // vectors per thread
-    constexpr int KS = D / 4;           // k-steps of 4 complex rows
-    constexpr int RB = D / 16;          // 16-row output blocks (2 for k = 5, 1 for k = 4)
-    constexpr int WPR = 4 / RB;         // waves per row block
-    constexpr int CBW = 4 / WPR;        // 16-column blocks per wave
-    static_assert(RB == 1 || RB == 2, "tile split");
-
-    __shared__ __align__(16) R lds[D * kRow * 2];
-
-    R* psi = blockIdx.y ? psi1 : psi0;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int rb = wave % RB;
-    const int cb0 = (wave / RB) * CBW;
-
-    // TPB consecutive tiles per workgroup (TPB divides ntiles): the loads of
-    // the next tile are issued right after the current one is in LDS, so
-    // they run under its products
-    const uint64_t tile0 = xcd_block() * TPB;
-    if (tile0 >= a.ntiles)
-        return;
-
-    uint64_t goff[VPT];
-    NV in[VPT];
-    {
-        const uint64_t base0 = insert_bits(tile0, a.ins);
-#pragma unroll
-        for (int r = 0; r < VPT; ++r) {
-            const int loc = (tid + 256 * r) * APV;
-            goff[r] = a.choff[loc >> a.L] + (uint64_t)(loc & ((1 << a.L) - 1));
-            in[r] = __builtin_nontemporal_load(reinterpret_cast<const NV*>(psi + 2 * (base0 + goff[r])));
-        }
-    }
-    // A operands of this wave's row block: Gr, Gi, Gr + Gi, KS values each
-    // per lane, contiguous in the table ([rb][product][lane][kk]).
-    R afr[3][KS];
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk)
-            afr[p][kk] = frag[(((size_t)rb * 3 + p) * 64 + lane) * KS + kk];
-    int pos[VPT][APV];
-#pragma unroll
-    for (int r = 0; r < VPT; ++r) {
-        const int loc = (tid + 256 * r) * APV;
-#pragma unroll
-        for (int h = 0; h < APV; ++h) {
-            const int l = loc + h;
-            int tau = 0, j = 0;
-#pragma unroll
-            for (int b = 0; b < K; ++b)
-                tau |= ((l >> a.tloc[b]) & 1) << b;
-#pragma unroll
-            for (int b = 0; b < 6; ++b)
-                j |= ((l >> a.floc[b]) & 1) << b;
-            pos[r][h] = (tau * kRow + j) * 2;
-        }
-    }
-    for (int it = 0; it < TPB; ++it) {
-    const uint64_t tile = tile0 + it;
-    const uint64_t base = insert_bits(tile, a.ins);
-#pragma unroll
-    for (int r = 0; r < VPT; ++r)
-#pragma unroll
-        for (int h = 0; h < APV; ++h)
-            *reinterpret_cast<P2*>(&lds[pos[r][h]]) = P2{in[r][2 * h], in[r][2 * h + 1]};
-    __syncthreads();
-    if (it + 1 < TPB) {
-        const uint64_t nb = insert_bits(tile + 1, a.ins);
-#pragma unroll
-        for (int r = 0; r < VPT; ++r)
-            in[r] = __builtin_nontemporal_load(reinterpret_cast<const NV*>(psi + 2 * (nb + goff[r])));
-    }
-
-    // B: lane holds complex row 4 kk + lane / 16 of group (cb0 + c) * 16 +
-    // lane % 16.  Reads in groups of KG k-steps, one group ahead of the
-    // products (scheduling barriers keep the order).
+    constexpr int D = 1 << K;
+    constexpr int KS = D / 4;
+    constexpr int RB = D / 16;
+    constexpr int CBW = 4 / (4 / RB);
     typename T::Acc acc[3][CBW];
 #pragma unroll
     for (int p = 0; p < 3; ++p)
@@ -406,20 +334,117 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_
             *reinterpret_cast<P2*>(&lds[(tau * kRow + grp) * 2]) = P2{p1 - p2, p3 - p1 - p2};
         }
     }
-    __syncthreads();
+}
+
+// TPB consecutive tiles per workgroup (TPB divides ntiles; 1 or 2).  With
+// two, the loads of the second tile are issued as soon as the first is in
+// LDS (the load registers are free again), so they run under its products.
+template <typename R, int K, int TPB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_wpe<R, K>()))) k_mfma3(R* __restrict__ psi0, R* __restrict__ psi1,
+                                               const MfmaK<K> a, const R* __restrict__ frag)
+{
+    using T = MfmaT<R>;
+    using NV = typename T::NV;
+    using P2 = typename Pair2<R>::T;
+    constexpr int D = 1 << K;           // complex rows (amplitudes per group)
+    constexpr int TA = D * 64;          // amplitudes per tile
+    constexpr int APV = T::APV;
+    constexpr int VPT = TA / APV / 256; // vectors per thread
+    constexpr int KS = D / 4;           // k-steps of 4 complex rows
+    constexpr int RB = D / 16;          // 16-row output blocks (2 for k = 5, 1 for k = 4)
+    constexpr int WPR = 4 / RB;         // waves per row block
+    constexpr int CBW = 4 / WPR;        // 16-column blocks per wave
+    static_assert(RB == 1 || RB == 2, "tile split");
+    static_assert(TPB == 1 || TPB == 2, "tiles per workgroup");
+
+    __shared__ __align__(16) R lds[D * kRow * 2];
+
+    R* psi = blockIdx.y ? psi1 : psi0;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int rb = wave % RB;
+    const int cb0 = (wave / RB) * CBW;
+
+    const uint64_t tile = xcd_block() * TPB;
+    if (tile >= a.ntiles)
+        return;
+    const uint64_t base = insert_bits(tile, a.ins);
+
+    uint64_t goff[VPT];
+    NV in[VPT];
 #pragma unroll
     for (int r = 0; r < VPT; ++r) {
-        NV o;
+        const int loc = (tid + 256 * r) * APV;
+        goff[r] = a.choff[loc >> a.L] + (uint64_t)(loc & ((1 << a.L) - 1));
+        in[r] = __builtin_nontemporal_load(reinterpret_cast<const NV*>(psi + 2 * (base + goff[r])));
+    }
+    // A operands of this wave's row block: Gr, Gi, Gr + Gi, KS values each
+    // per lane, contiguous in the table ([rb][product][lane][kk]).
+    R afr[3][KS];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk)
+            afr[p][kk] = frag[(((size_t)rb * 3 + p) * 64 + lane) * KS + kk];
+    int pos[VPT][APV];
+#pragma unroll
+    for (int r = 0; r < VPT; ++r) {
+        const int loc = (tid + 256 * r) * APV;
 #pragma unroll
         for (int h = 0; h < APV; ++h) {
-            const P2 w = *reinterpret_cast<const P2*>(&lds[pos[r][h]]);
-            o[2 * h] = w.x;
-            o[2 * h + 1] = w.y;
+            const int l = loc + h;
+            int tau = 0, j = 0;
+#pragma unroll
+            for (int b = 0; b < K; ++b)
+                tau |= ((l >> a.tloc[b]) & 1) << b;
+#pragma unroll
+            for (int b = 0; b < 6; ++b)
+                j |= ((l >> a.floc[b]) & 1) << b;
+            pos[r][h] = (tau * kRow + j) * 2;
         }
-        __builtin_nontemporal_store(o, reinterpret_cast<NV*>(psi + 2 * (base + goff[r])));
     }
-    if (TPB > 1)
-        __syncthreads();  // the LDS tile is rewritten by the next iteration
+    auto to_lds = [&]() {
+#pragma unroll
+        for (int r = 0; r < VPT; ++r)
+#pragma unroll
+            for (int h = 0; h < APV; ++h)
+                *reinterpret_cast<P2*>(&lds[pos[r][h]]) = P2{in[r][2 * h], in[r][2 * h + 1]};
+    };
+    auto store = [&](uint64_t b) {
+#pragma unroll
+        for (int r = 0; r < VPT; ++r) {
+            NV o;
+#pragma unroll
+            for (int h = 0; h < APV; ++h) {
+                const P2 w = *reinterpret_cast<const P2*>(&lds[pos[r][h]]);
+                o[2 * h] = w.x;
+                o[2 * h + 1] = w.y;
+            }
+            __builtin_nontemporal_store(o, reinterpret_cast<NV*>(psi + 2 * (b + goff[r])));
+        }
+    };
+    if constexpr (TPB == 2) {
+        for (int it = 0; it < 2; ++it) {
+            to_lds();
+            __syncthreads();
+            if (it == 0) {
+                const uint64_t b1 = insert_bits(tile + 1, a.ins);
+#pragma unroll
+                for (int r = 0; r < VPT; ++r)
+                    in[r] = __builtin_nontemporal_load(reinterpret_cast<const NV*>(psi + 2 * (b1 + goff[r])));
+            }
+            mfma3_multiply<R, K>(lds, afr, lane, rb, cb0);
+            __syncthreads();
+            store(insert_bits(tile + it, a.ins));
+            __syncthreads();  // every wave has read the tile back before the next one is written
+        }
+    } else {
+        to_lds();
+        __syncthreads();
+        mfma3_multiply<R, K>(lds, afr, lane, rb, cb0);
+        __syncthreads();
+        store(base);
     }
 }
 
