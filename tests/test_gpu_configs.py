@@ -19,6 +19,10 @@ CPU oracle (never against the GPU itself), through the C ABI.
   vector).  Complex64 errors against the oracle are printed and bounded.
 * Batched workload (1024 instances): every instance with n <= 16 and 32
   seeded larger ones (n = 21 and n = 22 included) against the oracle's adjoint.
+* Expectation values at n = 30 (the bench step's size): a product state
+  built on the GPU, TFIM, XXZ, a Heisenberg chain with fields and random
+  1-3-qubit strings, against the product-state closed form (pinned against
+  the oracle in tests/test_product_formula.py).
 
 Floating-point bars: complex128 max|d psi| and ||d psi||_2 <= 1e-12,
 complex64 <= 1e-5 (both against the complex128 oracle); energies and
@@ -302,3 +306,73 @@ def test_batched_workload_checked_subset(q, orc):
     for n in sorted(worst):
         say("batch n=%d worst |dE|/sum|c| %.3e  max|dgrad|/sum|c| %.3e" % ((n,) + worst[n]))
     assert len(small) > 400 and {21, 22} <= set(worst)
+
+
+# ------------------------------------------- n = 30 expectation values
+
+def product_expectation(H, vecs):
+    """<H> on the product state (x)_q (a_q|0> + b_q|1>) (qubit q = bit q):
+    sum_j c_j prod_q <sigma>_q with <X> = 2 Re(conj(a) b), <Y> = 2 Im(conj(a) b),
+    <Z> = |a|^2 - |b|^2 and 1 for the identity factors (Sec. 3 Pauli
+    strings; a closed form that holds at any size)."""
+    one = {}
+    for q, (a, b) in enumerate(vecs):
+        w = np.conj(a) * b
+        one[q] = (2 * w.real, 2 * w.imag, abs(a) ** 2 - abs(b) ** 2)
+    tot = 0.0
+    for x, z, c in zip(H.x_mask, H.z_mask, H.coeff):
+        x, z, v = int(x), int(z), float(c)
+        for q in range(len(vecs)):
+            xb, zb = (x >> q) & 1, (z >> q) & 1
+            if xb and zb:
+                v *= one[q][1]
+            elif xb:
+                v *= one[q][0]
+            elif zb:
+                v *= one[q][2]
+        tot += v
+    return tot
+
+
+def hamiltonians_for(n):
+    rng = np.random.default_rng(3000 + n)
+    heis = [(ab, (q, q + 1), 1.0) for q in range(n - 1) for ab in ("XX", "YY", "ZZ")]
+    heis += [(c, (q,), float(rng.normal())) for q in range(n) for c in "XYZ"]
+    mixed = [("", (), 0.3)]
+    for _ in range(40):
+        k = int(rng.integers(1, 4))
+        qs = [int(v) for v in rng.choice(n, k, replace=False)]
+        mixed.append(("".join(rng.choice(["X", "Y", "Z"]) for _ in range(k)), qs, float(rng.normal())))
+    return [("tfim", W.tfim_chain(n, 0.8)), ("xxz", W.xxz_chain(n, 0.5)), ("heisenberg_fields", W.pauli_sum(n, heis)),
+            ("mixed", W.pauli_sum(n, mixed))]
+
+
+@pytest.mark.parametrize("name", DTYPES)
+def test_expectation_n30_product_state(q, name):
+    """<psi|H|psi> at n = 30 (the bench step's size and launch configuration:
+    register-tile passes, the LDS-tile and per-mask passes for the rest) on a
+    product state built on the GPU by one Haar U(2) per qubit from |0...0>,
+    against the closed form; TFIM, XXZ, a Heisenberg chain with fields and 40
+    random 1-3-qubit strings.  The imaginary part stays at rounding level."""
+    import torch
+    n = 30
+    rng = np.random.default_rng(3030)
+    Us = [W.haar_unitary(rng, 2) for _ in range(n)]
+    psi = torch.empty(1 << n, dtype=torch_dtype(name), device="cuda")
+    q.qsv_init_basis(psi, 0)
+    for t in range(n):
+        q.qsv_apply_gate(psi, (t,), (), Us[t])
+    vecs = [U[:, 0] for U in Us]
+    # measured: complex64 <= 1.8e-9, complex128 <= 1.5e-16 (per sum |c|)
+    tol = 1e-7 if name == "c64" else 1e-13
+    for hname, H in hamiltonians_for(n):
+        ref = product_expectation(H, vecs)
+        e = q.qsv_expectation(psi, H).cpu().numpy()
+        scale = float(np.sum(np.abs(H.coeff)))
+        err = abs(e[0] - ref) / scale
+        say("expectation n = 30 product state", name, hname, "launches", q.expectation_launches(H, n, CODE[name]),
+            "err/sum|c| %.2e" % err)
+        assert err <= tol, (hname, e, ref)
+        assert abs(e[1]) <= tol * scale
+    del psi
+    torch.cuda.empty_cache()
