@@ -122,6 +122,7 @@ struct LaneTerms {
     uint64_t z;
     uint32_t xr;
     int32_t ylo;
+    uint32_t xl;
 };
 
 __device__ __forceinline__ double lane_double(double v, int k)
@@ -218,6 +219,37 @@ __device__ __forceinline__ double gen_terms(const LaneTerms& L, uint64_t sg, int
     return s;
 }
 
+// Terms [k0, k1) of the transposed roles: strings whose x mask is register
+// bit 4 (qubit 4) and one lane bit (mask xl).  The pair of (lane, r), r < 16,
+// is (lane ^ xl, r + 16): the partner's amplitudes come over the cross-lane
+// crossbar, and each lane sums its own 16 pairs (r bit 4 clear), so every
+// pair is visited once.  The z sign has no register part (z on qubits 0..3
+// is excluded and r bit 4 is 0); lane and tile parts come from sg, the
+// factor 2 and the sign of i^ylo from the coefficient.
+__device__ __forceinline__ double cross_terms(const LaneTerms& L, uint64_t sg, int k0, int k1,
+                                              const double (&re)[kNR], const double (&im)[kNR])
+{
+    double s = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const int xl = __builtin_amdgcn_readlane((int)L.xl, k);
+        const int ylo = __builtin_amdgcn_readlane(L.ylo, k);
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < kNR / 2; ++r) {
+            const double br = __shfl_xor(re[r + kNR / 2], xl, 64);
+            const double bi = __shfl_xor(im[r + kNR / 2], xl, 64);
+            const double d = (ylo & 1) ? im[r] * br - re[r] * bi : re[r] * br + im[r] * bi;
+            if (r & 1)
+                s1 += d;
+            else
+                s0 += d;
+        }
+        const double v = term_coef(L, k) * (s0 + s1);
+        s += ((sg >> k) & 1) ? -v : v;
+    }
+    return s;
+}
+
 template <typename R, bool TR, bool GEN>
 __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, const RegPassK a,
                                                   double* __restrict__ partials, int pstride, int accumulate)
@@ -257,13 +289,14 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
         }
         __syncthreads();
     }
-    LaneTerms LT{0.0, 0.0, 0, 0, 0};
+    LaneTerms LT{0.0, 0.0, 0, 0, 0, 0};
     if (lane < a.nt) {
         LT.c = a.t[lane].c;
         LT.c2 = a.t[lane].c2;
         LT.z = a.t[lane].z;
         LT.xr = a.t[lane].xr;
         LT.ylo = a.t[lane].ylo;
+        LT.xl = a.t[lane].xl;
     }
     double acc = 0.0;
     // Software pipeline (passes without the general string sums): the loads
@@ -355,7 +388,9 @@ __global__ void __launch_bounds__(256) k_reg_pass(const R* __restrict__ psi, con
                 im[r] = (double)w.y;
             }
             __builtin_amdgcn_wave_barrier();
-            s += GEN ? gen_terms(LT, sg, a.n1, a.nt, re, im) : pair_terms(LT, a.n1, a.nt, re, im);
+            s += GEN ? gen_terms(LT, sg, a.n1, a.nc, re, im) : pair_terms(LT, a.n1, a.nc, re, im);
+            if (GEN)
+                s += cross_terms(LT, sg, a.nc, a.nt, re, im);
         }
         acc += s;
     }
@@ -427,7 +462,7 @@ hipError_t pick(const RegPassK& a, const void* psi, double* partials, int nslots
                 hipStream_t s)
 {
     const bool tr = a.nt > a.n1;
-    const bool gen = a.n1 > a.ns1 || a.nt > a.ns2;
+    const bool gen = a.n1 > a.ns1 || a.nc > a.ns2 || a.nt > a.nc;
     if (tr)
         return gen ? go<R, true, true>(a, psi, partials, nslots, accumulate, s)
                    : go<R, true, false>(a, psi, partials, nslots, accumulate, s);
@@ -444,8 +479,8 @@ hipError_t launch_reg_pass(const RegPassK& a, const void* psi, int dt, double* p
         return hipSuccess;
     // the term tables assume nd <= nt <= kMaxRegTerms and mofs ascending from
     // 0 to nd (the chunk tables then fit in kDiagTab entries)
-    if (a.nt > kMaxRegTerms || a.nd < 0 || a.nd > a.ns1 || a.ns1 > a.n1 || a.n1 > a.ns2 || a.ns2 > a.nt ||
-        a.mofs[0] != 0 || a.mofs[1 << kRegQubits] != a.nd)
+    if (a.nt > kMaxRegTerms || a.nd < 0 || a.nd > a.ns1 || a.ns1 > a.n1 || a.n1 > a.ns2 || a.ns2 > a.nc ||
+        a.nc > a.nt || a.mofs[0] != 0 || a.mofs[1 << kRegQubits] != a.nd)
         return hipErrorInvalidValue;
     for (int m = 0; m < (1 << kRegQubits); ++m)
         if (a.mofs[m + 1] < a.mofs[m])

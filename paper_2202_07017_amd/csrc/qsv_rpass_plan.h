@@ -37,6 +37,7 @@ struct RTerm {
     uint32_t zr;
     uint32_t zl;
     int32_t ylo;     // number of Y factors mod 4 (its parity picks Re or Im)
+    uint32_t xl;     // cross-lane strings: lane xor mask of the partner (else 0)
 };
 
 // One pass: a wave loads a tile -- lanes on the lane qubits (lane bits 0..4
@@ -45,10 +46,13 @@ struct RTerm {
 //   [0, nd)     diagonal terms,
 //   [nd, ns1)   single-qubit X strings (no Z or Y factors) on a register qubit,
 //   [ns1, n1)   other strings whose x mask is one or two register qubits,
-//   [n1, ns2)   single-qubit X strings on one of qubits 0..4, and
-//   [ns2, nt)   other strings whose x mask is one or two of qubits 0..4,
-// the last two after an LDS transpose that swaps the roles of lane bits 0..4
-// and the register bits.
+//   [n1, ns2)   single-qubit X strings on one of qubits 0..4,
+//   [ns2, nc)   other strings whose x mask is one or two of qubits 0..4, and
+//   [nc, nt)    strings whose x mask is qubit 4 and one qubit that is a lane
+//               qubit of the transposed roles (the pair (4, 5) of a chain):
+//               the partner sits in register r ^ 16 of lane ^ xl,
+// the last three after an LDS transpose that swaps the roles of lane bits
+// 0..4 and the register bits.
 struct RegPassK {
     uint64_t ntiles;
     uint64_t low[kRegTileQubits];   // insertion masks of the tile qubits, ascending
@@ -58,6 +62,7 @@ struct RegPassK {
     int ns1;
     int n1;
     int ns2;
+    int nc;
     int nt;
     int mofs[(1 << kRegQubits) + 1];  // diagonal terms sorted by zr: terms [mofs[m], mofs[m+1]) have zr = m
     RTerm t[kMaxRegTerms];

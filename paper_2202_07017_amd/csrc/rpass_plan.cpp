@@ -1,11 +1,13 @@
 // Host planner of the register-tile Pauli passes (kernels_rpass.hip).
 //
 // Strings are sorted into diagonal ones, ones whose x mask is one or two of
-// qubits 0..4, ones whose x mask is one or two qubits above 4, and the rest
-// (for the LDS-tile passes).  The qubits above 4 are grouped, in term order,
-// into register sets of kRegQubits qubits, each set one pass; the first pass
-// also takes the strings on qubits 0..4 (after an in-wave transpose) and the
-// second (or only) one the diagonal strings.
+// qubits 0..4, ones whose x mask is one or two qubits above 4, ones whose x
+// mask is qubit 4 and one qubit above, and the rest (for the LDS-tile
+// passes).  The qubits above 4 are grouped, in term order, into register
+// sets of kRegQubits qubits, each set one pass; the first pass also takes
+// the strings on qubits 0..4 and those with qubit 4 and one of its lane
+// qubits (after an in-wave transpose), and the second (or only) one the
+// diagonal strings.
 #include <algorithm>
 #include <cstdint>
 #include <vector>
@@ -17,11 +19,12 @@ namespace qsv {
 void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, std::vector<int>& rest)
 {
     const uint64_t lowq = (1ull << (kRegLanes - 1)) - 1;  // qubits 0..4
-    std::vector<int> diag, low, high;
+    std::vector<int> diag, low, high, cross;
     // diagonal strings; strings whose x mask is one or two of qubits 0..4;
     // strings whose x mask is one or two qubits above 4 (both with a z check
-    // once the register qubits are known, below); the rest go to the
-    // LDS-tile passes
+    // once the register qubits are known, below); strings whose x mask is
+    // qubit 4 and one qubit above (cross-lane candidates of the first pass);
+    // the rest go to the LDS-tile passes
     for (int j = 0; j < H->nterms; ++j) {
         const uint64_t x = H->x_mask[j];
         const int px = __builtin_popcountll(x);
@@ -31,6 +34,8 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
             low.push_back(j);
         else if (px <= 2 && (x & lowq) == 0)
             high.push_back(j);
+        else if (px == 2 && (x & lowq) == 16)
+            cross.push_back(j);
         else
             rest.push_back(j);
     }
@@ -54,8 +59,10 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
         }
         sets.push_back({Q, take});
     }
-    if (sets.empty() && (!diag.empty() || !low.empty()))
+    if (sets.empty() && (!diag.empty() || !low.empty() || !cross.empty()))
         sets.push_back({0, {}});
+    if (sets.empty())
+        rest.insert(rest.end(), cross.begin(), cross.end());
     for (size_t si = 0; si < sets.size(); ++si) {
         uint64_t Q = sets[si].first;
         // fill the register set up to kRegQubits qubits with the lowest free ones >= 5
@@ -112,10 +119,12 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
             t.z = z;
             t.c = H->coeff[j];
             t.ylo = __builtin_popcountll(x & z) & 3;
-            if (phase == 2) {
+            if (phase >= 2) {
                 t.xr = (uint32_t)(x & lowq);
                 t.zr = (uint32_t)(z & lowq);
                 t.zl = comp_lane2(z);
+                if (phase == 3)
+                    t.xl = comp_lane2(x & ~lowq);
             } else {
                 t.xr = comp_reg(x);
                 t.zr = comp_reg(z);
@@ -141,7 +150,7 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
             for (const RTerm& t : v) {
                 bool done = false;
                 for (RTerm& u : out)
-                    if (u.xr == t.xr && ((u.ylo ^ t.ylo) & 1) == 0 && u.zl == t.zl &&
+                    if (u.xr == t.xr && u.xl == t.xl && ((u.ylo ^ t.ylo) & 1) == 0 && u.zl == t.zl &&
                         (u.z & ~tilemask) == (t.z & ~tilemask)) {
                         u.c += t.c;
                         u.c2 += t.c2;
@@ -155,7 +164,7 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
         };
         // launches of <= kMaxRegTerms terms with this geometry: the first
         // register set also takes the diagonal and low-qubit strings
-        std::vector<std::pair<int, int>> items;  // (term, phase 0 diag / 1 register / 2 low)
+        std::vector<std::pair<int, int>> items;  // (term, phase 0 diag / 1 register / 2 low / 3 cross-lane)
         // the diagonal terms ride with the second register set when there is
         // one and the first also takes the transposed low-qubit strings
         // (measured: TFIM at n = 30, complex64 7.55 -> 7.15 ms, complex128
@@ -185,12 +194,24 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
                 else
                     rest.push_back(j);
             }
+            // qubit 4 with a qubit that is a lane qubit after the transpose
+            // (h or a register qubit of this set): the partner is register
+            // r ^ 16 of another lane; z on qubits 0..3 would need a register
+            // sign the pass does not apply
+            const uint64_t lanes2 = Q | (1ull << h);
+            for (int j : cross) {
+                const uint64_t x = H->x_mask[j];
+                if ((x & ~lowq & lanes2) != 0 && (H->z_mask[j] & lowq & ~x) == 0)
+                    items.push_back({j, 3});
+                else
+                    rest.push_back(j);
+            }
         }
         size_t pos = 0;
         do {
             RegPassK L = k;
-            int nt = 0, cnt[3] = {0, 0, 0};
-            std::vector<RTerm> byphase[3];
+            int nt = 0, cnt[4] = {0, 0, 0, 0};
+            std::vector<RTerm> byphase[4];
             while (pos < items.size() && nt < kMaxRegTerms) {
                 byphase[items[pos].second].push_back(term(items[pos].first, items[pos].second));
                 ++cnt[items[pos].second];
@@ -204,11 +225,13 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
                              [](const RTerm& x, const RTerm& y) { return x.zr < y.zr; });
             auto plain = [](const RTerm& t) { return t.z == 0 && __builtin_popcount(t.xr) == 1; };
             int nplain[3] = {0, 0, 0};
-            for (int ph = 1; ph < 3; ++ph) {
+            for (int ph = 1; ph < 4; ++ph) {
                 merge(byphase[ph]);
                 cnt[ph] = (int)byphase[ph].size();
-                std::stable_partition(byphase[ph].begin(), byphase[ph].end(), plain);
-                nplain[ph] = (int)std::count_if(byphase[ph].begin(), byphase[ph].end(), plain);
+                if (ph < 3) {
+                    std::stable_partition(byphase[ph].begin(), byphase[ph].end(), plain);
+                    nplain[ph] = (int)std::count_if(byphase[ph].begin(), byphase[ph].end(), plain);
+                }
             }
             for (int m = 0, q = 0; m <= (1 << kRegQubits); ++m) {
                 while (q < (int)byphase[0].size() && (int)byphase[0][q].zr < m)
@@ -216,14 +239,15 @@ void plan_reg_passes(const qsv_pauli_sum* H, int n, std::vector<RegPassK>& out, 
                 L.mofs[m] = q;
             }
             int w = 0;
-            for (int ph = 0; ph < 3; ++ph)
+            for (int ph = 0; ph < 4; ++ph)
                 for (const RTerm& t : byphase[ph])
                     L.t[w++] = t;
             L.nd = cnt[0];
             L.ns1 = cnt[0] + nplain[1];
             L.n1 = cnt[0] + cnt[1];
             L.ns2 = L.n1 + nplain[2];
-            L.nt = cnt[0] + cnt[1] + cnt[2];
+            L.nc = L.n1 + cnt[2];
+            L.nt = L.nc + cnt[3];
             out.push_back(L);
         } while (pos < items.size());
     }

@@ -98,8 +98,8 @@ int main(int argc, char** argv)
         const RegPassK& P = passes[pi];
         // structure
         require(P.ntiles == (1ull << (n - qsv::kRegTileQubits)), "tile count", pi);
-        require(P.nd >= 0 && P.nd <= P.ns1 && P.ns1 <= P.n1 && P.n1 <= P.ns2 && P.ns2 <= P.nt &&
-                    P.nt <= qsv::kMaxRegTerms, "term ranges", pi);
+        require(P.nd >= 0 && P.nd <= P.ns1 && P.ns1 <= P.n1 && P.n1 <= P.ns2 && P.ns2 <= P.nc &&
+                    P.nc <= P.nt && P.nt <= qsv::kMaxRegTerms, "term ranges", pi);
         require(P.mofs[0] == 0 && P.mofs[32] == P.nd, "diagonal offsets", pi);
         uint64_t tmask = 0;
         int prevq = -1;
@@ -128,12 +128,17 @@ int main(int argc, char** argv)
             for (int k = P.mofs[m]; k < P.mofs[m + 1]; ++k)
                 require(P.t[k].xr == 0 && (int)P.t[k].zr == m, "diagonal group", pi);
         }
-        for (int k = P.nd; k < P.nt; ++k) {
+        for (int k = P.nd; k < P.nc; ++k) {
             const RTerm& t = P.t[k];
-            require(reg_ok(t.xr), "register x mask", pi);
+            require(reg_ok(t.xr) && t.xl == 0, "register x mask", pi);
             const bool pl = (k < P.ns1) || (k >= P.n1 && k < P.ns2);
             require(pl == plain(t), "plain / general split", pi);
             require((t.zr & ~t.xr) == 0, "register z bits inside the x mask", pi);
+        }
+        for (int k = P.nc; k < P.nt; ++k) {
+            const RTerm& t = P.t[k];
+            require(t.xr == 16 && t.xl != 0 && t.xl < 64 && (t.xl & (t.xl - 1)) == 0, "cross-lane masks", pi);
+            require((t.zr & ~16u) == 0, "cross-lane z on qubits 0..3", pi);
         }
         // evaluation, tile by tile
         for (uint64_t tl = 0; tl < P.ntiles; ++tl) {
@@ -182,7 +187,7 @@ int main(int argc, char** argv)
                 }
                 for (int ph = 0; ph < 2; ++ph) {
                     const cd* a = ph ? amp2[lane] : amp[lane];
-                    const int k0 = ph ? P.n1 : P.nd, k1 = ph ? P.nt : P.n1;
+                    const int k0 = ph ? P.n1 : P.nd, k1 = ph ? P.nc : P.n1;
                     for (int k = k0; k < k1; ++k) {
                         const RTerm& t = P.t[k];
                         double s0, s1;
@@ -190,6 +195,17 @@ int main(int argc, char** argv)
                         const double v = plain(t) ? t.c * (s0 + s1) : t.c * s0 + t.c2 * s1;
                         s += ((sg >> k) & 1) ? -v : v;
                     }
+                }
+                // cross-lane strings: the pair of (lane, r), r < 16, is (lane ^ xl, r + 16)
+                for (int k = P.nc; k < P.nt; ++k) {
+                    const RTerm& t = P.t[k];
+                    double d = 0.0;
+                    for (int r = 0; r < 16; ++r) {
+                        const cd w = std::conj(amp2[lane ^ t.xl][r + 16]) * amp2[lane][r];
+                        d += (t.ylo & 1) ? w.imag() : w.real();
+                    }
+                    const double v = t.c * d;
+                    s += ((sg >> k) & 1) ? -v : v;
                 }
                 energy += s;
             }

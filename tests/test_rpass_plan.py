@@ -54,8 +54,9 @@ def sub(H, idx):
 def mixed_sum(n, seed):
     """Diagonal strings anywhere (more than one launch holds), single X and
     Y on every qubit, XX / YY / XY / YX on neighbours with and without Z
-    factors elsewhere, non-neighbouring pairs, three-qubit strings and the
-    pair (4, 5) that straddles the lane and register qubits."""
+    factors elsewhere, non-neighbouring pairs, three-qubit strings, and
+    pairs of qubit 4 with qubits above (cross-lane strings of the first
+    pass, or left to the LDS tiles)."""
     rng = np.random.default_rng(seed)
     t = [("", (), 0.4)]
     for _ in range(60):
@@ -77,6 +78,7 @@ def mixed_sum(n, seed):
     t.append(("YY", (6, 9), -0.2))
     t.append(("XXX", (0, 7, n - 1), 0.7))
     t.append(("XX", (4, 5), 0.25))
+    t += [("XX", (4, 7), 0.35), ("XY", (4, 6), -0.15), ("YX", (4, 9), 0.2), ("YYZ", (4, 8, 1), 0.1)]
     return W.pauli_sum(n, t)
 
 
@@ -102,7 +104,6 @@ def test_register_pass_plan_reproduces_expectation(checker, orc, tmp_path, name,
     scale = float(np.sum(np.abs(H.coeff)))
     assert abs(e_reg + e_rest - ref) <= 1e-12 * scale, (e_reg, e_rest, ref)
     if name in ("tfim", "xxz", "heis_fields"):
-        # every string of these models goes to the register passes except the
-        # neighbour pair (4, 5), which straddles the lane and register qubits
-        for j in rest:
-            assert int(H.x_mask[j]) == 0b110000, (j, int(H.x_mask[j]), int(H.z_mask[j]))
+        # every string of these models goes to the register passes (the
+        # neighbour pair (4, 5) as a cross-lane string of the first pass)
+        assert rest == [], [(j, int(H.x_mask[j]), int(H.z_mask[j])) for j in rest]
