@@ -243,6 +243,69 @@ __global__ void __launch_bounds__(kBlock) k_expect_pair(const R* __restrict__ ps
     }
 }
 
+// One string per launch (the usual case for strings that no tile pass
+// holds): its z mask, coefficient and Y count stay in registers, the phase
+// of the partner follows from the phase of i (popcount(j & z) = popcount(i
+// & z) + popcount(x & z) mod 2), and each thread keeps four pairs' loads in
+// flight.  The per-thread order of the sums is that of k_expect_pair.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_expect_pair1(const R* __restrict__ psi, uint64_t npairs,
+                                                         uint64_t x, uint64_t lowmask, uint64_t z,
+                                                         double c, int ylo, double* partials,
+                                                         int accumulate)
+{
+    const int dx = popc64(x & z) & 1;
+    double sr = 0.0, si = 0.0;
+    auto add = [&](uint64_t i, double2 a, double2 b) {
+        const double wr = b.x * a.x + b.y * a.y, wi = b.x * a.y - b.y * a.x;
+        const int p = popc64(i & z) & 1;
+        const int ei = (ylo + 2 * p) & 3, ej = (ylo + 2 * (p ^ dx)) & 3;
+        const double2 fi = make_double2(ei == 0 ? c : (ei == 2 ? -c : 0.0), ei == 1 ? c : (ei == 3 ? -c : 0.0));
+        const double2 fj = make_double2(ej == 0 ? c : (ej == 2 ? -c : 0.0), ej == 1 ? c : (ej == 3 ? -c : 0.0));
+        const double pr = fi.x + fj.x, pi = fi.y - fj.y;
+        const double qr = fi.x - fj.x, qi = fi.y + fj.y;
+        sr += wr * pr - wi * pi;
+        si += wr * qi + wi * qr;
+    };
+    const uint64_t step = (uint64_t)gridDim.x * kBlock;
+    uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; g + 3 * step < npairs; g += 4 * step) {
+        uint64_t i[4];
+        double2 a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t gu = g + (uint64_t)u * step;
+            i[u] = ((gu & ~lowmask) << 1) | (gu & lowmask);
+            a[u] = ld(psi, i[u]);
+            b[u] = ld(psi, i[u] ^ x);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            add(i[u], a[u], b[u]);
+    }
+    for (; g < npairs; g += step) {
+        const uint64_t i = ((g & ~lowmask) << 1) | (g & lowmask);
+        add(i, ld(psi, i), ld(psi, i ^ x));
+    }
+    __shared__ double red[2][kBlock];
+    red[0][threadIdx.x] = sr;
+    red[1][threadIdx.x] = si;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* p = partials + blockIdx.x;
+        double* q = partials + gridDim.x + blockIdx.x;
+        *p = accumulate ? *p + red[0][0] : red[0][0];
+        *q = accumulate ? *q + red[1][0] : red[1][0];
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_inner(const R* __restrict__ a, const R* __restrict__ b,
                                                   uint64_t N, double* partials, int accumulate)
@@ -411,6 +474,16 @@ hipError_t launch_expect_pair(const void* psi, int n, int dt, uint64_t x, const 
     const int nb = reduce_blocks(n, dt);
     const uint64_t np = 1ull << (n - 1);
     const uint64_t lm = top_low_mask(x);
+    if (t.nt == 1) {
+        if (dt == C64)
+            hipLaunchKernelGGL(k_expect_pair1<float>, dim3(nb), dim3(kBlock), 0, s, static_cast<const float*>(psi),
+                               np, x, lm, t.z[0], t.c[0], t.ylo[0], partials, accumulate);
+        else
+            hipLaunchKernelGGL(k_expect_pair1<double>, dim3(nb), dim3(kBlock), 0, s,
+                               static_cast<const double*>(psi), np, x, lm, t.z[0], t.c[0], t.ylo[0], partials,
+                               accumulate);
+        return hipGetLastError();
+    }
     if (dt == C64)
         hipLaunchKernelGGL(k_expect_pair<float>, dim3(nb), dim3(kBlock), 0, s,
                            static_cast<const float*>(psi), np, x, lm, t, partials, accumulate);
