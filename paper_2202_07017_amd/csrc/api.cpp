@@ -19,6 +19,7 @@
 #include "qsv_expect.h"
 #include "qsv_host.h"
 #include "qsv_rpass.h"
+#include "qsv_span.h"
 
 using namespace qsv;
 
@@ -728,40 +729,127 @@ void plan_tiles(const qsv_pauli_sum* H, int n, std::vector<TileExpK>& out,
     }
 }
 
+// The passes of <psi|H|psi> for n >= kTileQubits: register-tile passes for
+// the strings they take; for the rest either LDS-tile passes (12-qubit
+// tiles, many x masks each when they share few qubits above 5) with span
+// passes (five x masks per state read) for what no tile holds, or span
+// passes for every string with an x bit above 5 and LDS tiles for the
+// others, whichever costs less (an LDS-tile pass measured at about 1.7 span
+// passes on n = 30 states).  One pass per x mask only with
+// QSV_NO_SPAN_PASS=1 (comparisons) or for a string no span pass takes.
+struct ExpPlan {
+    std::vector<RegPassK> regs;
+    std::vector<TileExpK> tiles;
+    std::vector<SpanPassK> spans;
+    std::vector<std::pair<uint64_t, TermChunk>> pairs;
+    double cost() const { return 1.7 * (double)tiles.size() + (double)(spans.size() + pairs.size()); }
+};
+
+struct SubSum {  // the strings idx of H as a Pauli sum of their own
+    std::vector<uint64_t> x, z;
+    std::vector<double> c;
+    SubSum() = default;
+    SubSum(const qsv_pauli_sum* H, const std::vector<int>& idx)
+    {
+        for (int j : idx) {
+            x.push_back(H->x_mask[j]);
+            z.push_back(H->z_mask[j]);
+            c.push_back(H->coeff[j]);
+        }
+    }
+    qsv_pauli_sum sum() const { return qsv_pauli_sum{(int)x.size(), x.data(), z.data(), c.data()}; }
+};
+
+// span passes for the strings of S; strings they leave become per-mask passes
+void add_spans(const SubSum& S, int n, ExpPlan& P)
+{
+    const qsv_pauli_sum H = S.sum();
+    std::vector<int> left;
+    plan_span_passes(&H, n, P.spans, left);
+    for (int j : left) {
+        TermChunk tc{};
+        tc.nt = 1;
+        tc.z[0] = S.z[j];
+        tc.c[0] = S.c[j];
+        tc.ylo[0] = __builtin_popcountll(S.x[j] & S.z[j]) & 3;
+        P.pairs.push_back({S.x[j], tc});
+    }
+}
+
+void plan_expectation(const qsv_pauli_sum* H, int n, ExpPlan& P)
+{
+    std::vector<int> rest;
+    plan_reg_passes(H, n, P.regs, rest);
+    if (rest.empty())
+        return;
+    const SubSum R(H, rest);
+    const qsv_pauli_sum Hr = R.sum();
+    // tiles first
+    ExpPlan A;
+    std::vector<std::pair<uint64_t, TermChunk>> leftover;
+    plan_tiles(&Hr, n, A.tiles, leftover);
+    const char* nospan = std::getenv("QSV_NO_SPAN_PASS");
+    const bool span = !(nospan && nospan[0] == '1');
+    if (!span || leftover.empty()) {
+        A.pairs.swap(leftover);
+    } else {
+        SubSum L;
+        for (const auto& pr : leftover)
+            for (int k = 0; k < pr.second.nt; ++k) {
+                L.x.push_back(pr.first);
+                L.z.push_back(pr.second.z[k]);
+                L.c.push_back(pr.second.c[k]);
+            }
+        add_spans(L, n, A);
+    }
+    // span passes first
+    ExpPlan B;
+    if (span) {
+        std::vector<int> hi, lo;
+        for (int j = 0; j < Hr.nterms; ++j)
+            ((Hr.x_mask[j] >> kSpanLaneQubits) != 0 ? hi : lo).push_back(j);
+        add_spans(SubSum(&Hr, hi), n, B);
+        if (!lo.empty()) {
+            const SubSum Lo(&Hr, lo);
+            const qsv_pauli_sum Hlo = Lo.sum();
+            std::vector<std::pair<uint64_t, TermChunk>> left;
+            plan_tiles(&Hlo, n, B.tiles, left);
+            B.pairs.insert(B.pairs.end(), left.begin(), left.end());
+        }
+    }
+    const ExpPlan& W = (span && B.cost() <= A.cost()) ? B : A;
+    P.tiles = W.tiles;
+    P.spans = W.spans;
+    P.pairs = W.pairs;
+}
+
 qsv_status enqueue_expectation(const void* psi, int n, int dt, const qsv_pauli_sum* H, double* out,
                                double* work, int ncomp, hipStream_t s)
 {
     int acc = 0;
     const int nb = reduce_blocks(n, dt);
     if (n >= kTileQubits) {
-        std::vector<RegPassK> regs;
-        std::vector<int> rest;
-        plan_reg_passes(H, n, regs, rest);
-        for (const RegPassK& k : regs) {
+        ExpPlan P;
+        plan_expectation(H, n, P);
+        for (const RegPassK& k : P.regs) {
             hipError_t e = launch_reg_pass(k, psi, dt, work, nb, acc, s);
             if (e != hipSuccess)
                 return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
             acc = 1;
         }
-        std::vector<uint64_t> rx, rz;
-        std::vector<double> rc;
-        for (int j : rest) {
-            rx.push_back(H->x_mask[j]);
-            rz.push_back(H->z_mask[j]);
-            rc.push_back(H->coeff[j]);
-        }
-        const qsv_pauli_sum Hr{(int)rest.size(), rx.data(), rz.data(), rc.data()};
-        std::vector<TileExpK> tiles;
-        std::vector<std::pair<uint64_t, TermChunk>> leftover;
-        if (!rest.empty())
-            plan_tiles(&Hr, n, tiles, leftover);
-        for (const TileExpK& k : tiles) {
+        for (const TileExpK& k : P.tiles) {
             hipError_t e = launch_tile_pass(k, psi, nullptr, dt, false, work, nb, acc, s);
             if (e != hipSuccess)
                 return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
             acc = 1;
         }
-        for (const auto& pr : leftover) {
+        for (const SpanPassK& k : P.spans) {
+            hipError_t e = launch_span_pass(k, psi, dt, work, nb, acc, s);
+            if (e != hipSuccess)
+                return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
+            acc = 1;
+        }
+        for (const auto& pr : P.pairs) {
             hipError_t e = launch_expect_pair(psi, n, dt, pr.first, pr.second, work, acc, s);
             if (e != hipSuccess)
                 return fail(QSV_ERR_HIP, "expectation launch: %s", hipGetErrorString(e));
@@ -1035,24 +1123,9 @@ qsv_status qsv_expectation_launches(const qsv_pauli_sum* H, int n, qsv_dtype dt,
         return fail(QSV_ERR_ARG, "nlaunches is NULL");
     int count = 1;  // the finalize
     if (n >= kTileQubits) {
-        std::vector<RegPassK> regs;
-        std::vector<int> rest;
-        plan_reg_passes(H, n, regs, rest);
-        count += (int)regs.size();
-        if (!rest.empty()) {
-            std::vector<uint64_t> rx, rz;
-            std::vector<double> rc;
-            for (int j : rest) {
-                rx.push_back(H->x_mask[j]);
-                rz.push_back(H->z_mask[j]);
-                rc.push_back(H->coeff[j]);
-            }
-            const qsv_pauli_sum Hr{(int)rest.size(), rx.data(), rz.data(), rc.data()};
-            std::vector<TileExpK> tiles;
-            std::vector<std::pair<uint64_t, TermChunk>> leftover;
-            plan_tiles(&Hr, n, tiles, leftover);
-            count += (int)(tiles.size() + leftover.size());
-        }
+        ExpPlan P;
+        plan_expectation(H, n, P);
+        count += (int)(P.regs.size() + P.tiles.size() + P.spans.size() + P.pairs.size());
     } else {
         std::vector<TermChunk> diag;
         std::vector<std::pair<uint64_t, TermChunk>> pairs;

@@ -343,17 +343,26 @@ def hamiltonians_for(n):
         k = int(rng.integers(1, 4))
         qs = [int(v) for v in rng.choice(n, k, replace=False)]
         mixed.append(("".join(rng.choice(["X", "Y", "Z"]) for _ in range(k)), qs, float(rng.normal())))
+    # strings of 7-10 factors spread over the register (x masks with many
+    # qubits above 5: span passes), values large enough to test on a product
+    # state
+    spread = []
+    for _ in range(48):
+        k = min(n, int(rng.integers(7, 11)))
+        qs = [int(v) for v in rng.choice(n, k, replace=False)]
+        spread.append(("".join(rng.choice(["X", "Y", "X", "Y", "Z"]) for _ in range(k)), qs, float(rng.normal())))
     return [("tfim", W.tfim_chain(n, 0.8)), ("xxz", W.xxz_chain(n, 0.5)), ("heisenberg_fields", W.pauli_sum(n, heis)),
-            ("mixed", W.pauli_sum(n, mixed))]
+            ("mixed", W.pauli_sum(n, mixed)), ("spread", W.pauli_sum(n, spread))]
 
 
 @pytest.mark.parametrize("name", DTYPES)
 def test_expectation_n30_product_state(q, name):
     """<psi|H|psi> at n = 30 (the bench step's size and launch configuration:
-    register-tile passes, the LDS-tile and per-mask passes for the rest) on a
+    register-tile passes, the LDS-tile and span passes for the rest) on a
     product state built on the GPU by one Haar U(2) per qubit from |0...0>,
-    against the closed form; TFIM, XXZ, a Heisenberg chain with fields and 40
-    random 1-3-qubit strings.  The imaginary part stays at rounding level."""
+    against the closed form; TFIM, XXZ, a Heisenberg chain with fields, 40
+    random 1-3-qubit strings and 48 strings of 7-10 factors spread over all
+    qubits.  The imaginary part stays at rounding level."""
     import torch
     n = 30
     rng = np.random.default_rng(3030)

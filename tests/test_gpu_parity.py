@@ -352,6 +352,35 @@ def test_observables_register_many_terms(q, orc, n):
         assert abs(e[1]) <= 1e-10 * scale
 
 
+@pytest.mark.parametrize("n", [16, 20])
+def test_observables_span_passes(q, orc, n, monkeypatch):
+    """Strings with arbitrary x masks (random strings, 40 strings on one
+    mask, XORs of earlier masks, masks on qubits 0..5 only, a Y on the top
+    qubit): span passes of five x masks per state read, against the oracle
+    and against one pass per x mask (QSV_NO_SPAN_PASS=1)."""
+    from test_span_plan import span_sum
+    rng = np.random.default_rng(1500 + n)
+    H = span_sum(n, 700 + n)
+    n_span = q.expectation_launches(H, n, q.C64)
+    monkeypatch.setenv("QSV_NO_SPAN_PASS", "1")
+    n_pair = q.expectation_launches(H, n, q.C64)
+    monkeypatch.delenv("QSV_NO_SPAN_PASS")
+    assert n_span < n_pair, (n_span, n_pair)
+    scale = np.sum(np.abs(H.coeff))
+    for name in DTYPES:
+        psi = rand_state(n, rng, name)
+        d = to_gpu(psi, name)
+        say("span-pass expectation", name, n, len(H.coeff), "launches", n_span, "vs", n_pair)
+        e = q.qsv_expectation(d, H).cpu().numpy()
+        ref = orc.expect(psi, H)
+        assert abs(e[0] - ref.real) <= 1e-10 * scale, (e, ref)
+        assert abs(e[1]) <= 1e-10 * scale
+        monkeypatch.setenv("QSV_NO_SPAN_PASS", "1")
+        e_pair = q.qsv_expectation(d, H).cpu().numpy()
+        monkeypatch.delenv("QSV_NO_SPAN_PASS")
+        assert abs(e_pair[0] - e[0]) <= 1e-10 * scale, (e_pair, e)
+
+
 def test_plan_random_circuit(q, orc):
     """Random U(2) layers with CZ pairs (n = 20, depth 10): every fusion width
     and graph replay against the oracle, plus <Z_0>."""

@@ -12,7 +12,7 @@ from test_gpu_configs import hamiltonians_for, product_expectation
 def test_product_formula_matches_oracle(orc):
     """The closed form above against the oracle on small product states (so
     the n = 30 check below rests on a pinned formula)."""
-    n = 9
+    n = 12
     rng = np.random.default_rng(5)
     vecs = [W.haar_unitary(rng, 2)[:, 0] for _ in range(n)]
     psi = np.array([1.0 + 0j])

@@ -4,7 +4,8 @@ The oracle (oracle/oracle.c) is driven through every entry point by
 tests/oracle_sanitize_check.c, the tile-program compiler of the library
 (paper_2202_07017_amd/csrc/tileprog.cpp) through tests/tileprog_check.cpp on
 random gate lists, and the register-pass planner (csrc/rpass_plan.cpp)
-through tests/rpass_check.cpp on mixed Pauli sums; all are built with g++/gcc and
+through tests/rpass_check.cpp on mixed Pauli sums, the span-pass planner
+(csrc/span_plan.cpp) through tests/span_check.cpp; all are built with g++/gcc and
 -fsanitize=address,undefined -fno-sanitize-recover=all, so any out-of-bounds
 access, use after free, leak or undefined behaviour aborts the run.  The
 GPU code is not built here (GPU sanitizers are not available)."""
@@ -82,3 +83,15 @@ def test_register_pass_planner_under_sanitizers(orc, tmp_path):
         _, rest, e_reg = run_rpass(exe, H, psi, tmp_path, env=ENV)
         e_rest = orc.expect(psi, sub(H, rest)).real if rest else 0.0
         assert abs(e_reg + e_rest - orc.expect(psi, H).real) <= 1e-12 * float(np.sum(np.abs(H.coeff)))
+
+
+def test_span_pass_planner_under_sanitizers(orc, tmp_path):
+    from test_span_plan import build_checker, span_sum
+    from test_span_plan import run as run_span
+    exe = build_checker(str(tmp_path / "span_check"), SAN)
+    for n in (12, 14):
+        H = span_sum(n, 11 + n)
+        psi = orc.random_state(n, 55 + n)
+        _, rest, e_span = run_span(exe, H, psi, tmp_path, env=ENV)
+        e_rest = orc.expect(psi, sub(H, rest)).real if rest else 0.0
+        assert abs(e_span + e_rest - orc.expect(psi, H).real) <= 1e-12 * float(np.sum(np.abs(H.coeff)))
