@@ -729,20 +729,47 @@ void plan_tiles(const qsv_pauli_sum* H, int n, std::vector<TileExpK>& out,
     }
 }
 
-// The passes of <psi|H|psi> for n >= kTileQubits: register-tile passes for
-// the strings they take; for the rest either LDS-tile passes (12-qubit
-// tiles, many x masks each when they share few qubits above 5) with span
-// passes (five x masks per state read) for what no tile holds, or span
-// passes for every string with an x bit above 5 and LDS tiles for the
-// others, whichever costs less (an LDS-tile pass measured at about 1.7 span
-// passes on n = 30 states).  One pass per x mask only with
-// QSV_NO_SPAN_PASS=1 (comparisons) or for a string no span pass takes.
+// The passes of <psi|H|psi> for n >= kTileQubits, the cheapest of three
+// plans:
+//   R1  register-tile passes for the strings they take, LDS-tile passes for
+//       the rest whose x masks fit a 12-qubit tile, span passes for the
+//       others;
+//   R2  register-tile passes, span passes for all the rest;
+//   S   span passes for every string (five x masks with a qubit above 5 per
+//       pass, strings on qubits 0..5 and diagonal strings spread over them).
+// The cost of a pass is its time relative to a register pass of single X
+// strings, measured at n = 30 (ExpPlan::cost).  QSV_EXPECT_PLAN=reg or
+// =span restricts the choice to R1/R2 or S (comparisons); QSV_NO_SPAN_PASS=1
+// leaves R1 with one pass per x mask for what no tile holds.
 struct ExpPlan {
     std::vector<RegPassK> regs;
     std::vector<TileExpK> tiles;
     std::vector<SpanPassK> spans;
     std::vector<std::pair<uint64_t, TermChunk>> pairs;
-    double cost() const { return 1.7 * (double)tiles.size() + (double)(spans.size() + pairs.size()); }
+    // complex64 passes are partly bound by their FP64 arithmetic, complex128
+    // ones by the state read: register passes with transposed roles and
+    // general strings 2.6 (1.7), with general strings 1.2 (1.05), with
+    // transposed roles 1.1 (1.0); LDS-tile passes 1.7 (1.3); per-mask passes
+    // 1.15; a span pass grows with its arithmetic L (direction strings 1,
+    // lane strings 2.5, diagonal strings 0.1 plus 2 for their transform):
+    // complex64 0.78 + 0.1 L ms against 1.3 ms, complex128 2.45 + 0.025 L
+    // ms against 2.6 ms
+    double cost(int dt) const
+    {
+        const bool c64 = dt == C64;
+        double c = (c64 ? 1.7 : 1.3) * (double)tiles.size() + 1.15 * (double)pairs.size();
+        for (const RegPassK& k : regs) {
+            const bool tr = k.nt > k.n1, gen = k.n1 > k.ns1 || k.nc > k.ns2 || k.nt > k.nc;
+            c += (tr && gen) ? (c64 ? 2.6 : 1.7) : gen ? (c64 ? 1.2 : 1.05) : tr ? (c64 ? 1.1 : 1.0) : 1.0;
+        }
+        for (const SpanPassK& k : spans) {
+            const int ndir = k.koff[2 * kSpanDirs], nlane = k.koff[kSpanGroups] - ndir,
+                      ndiag = k.nt - k.koff[kSpanGroups];
+            const double L = ndir + 2.5 * nlane + 0.1 * ndiag + (ndiag ? 2.0 : 0.0);
+            c += c64 ? std::max(0.97, (0.78 + 0.1 * L) / 1.3) : (2.45 + 0.025 * L) / 2.6;
+        }
+        return c;
+    }
 };
 
 struct SubSum {  // the strings idx of H as a Pauli sum of their own
@@ -760,67 +787,57 @@ struct SubSum {  // the strings idx of H as a Pauli sum of their own
     qsv_pauli_sum sum() const { return qsv_pauli_sum{(int)x.size(), x.data(), z.data(), c.data()}; }
 };
 
-// span passes for the strings of S; strings they leave become per-mask passes
-void add_spans(const SubSum& S, int n, ExpPlan& P)
+void plan_expectation(const qsv_pauli_sum* H, int n, int dt, ExpPlan& P)
 {
-    const qsv_pauli_sum H = S.sum();
-    std::vector<int> left;
-    plan_span_passes(&H, n, P.spans, left);
-    for (int j : left) {
-        TermChunk tc{};
-        tc.nt = 1;
-        tc.z[0] = S.z[j];
-        tc.c[0] = S.c[j];
-        tc.ylo[0] = __builtin_popcountll(S.x[j] & S.z[j]) & 3;
-        P.pairs.push_back({S.x[j], tc});
-    }
-}
-
-void plan_expectation(const qsv_pauli_sum* H, int n, ExpPlan& P)
-{
-    std::vector<int> rest;
-    plan_reg_passes(H, n, P.regs, rest);
-    if (rest.empty())
-        return;
-    const SubSum R(H, rest);
-    const qsv_pauli_sum Hr = R.sum();
-    // tiles first
-    ExpPlan A;
-    std::vector<std::pair<uint64_t, TermChunk>> leftover;
-    plan_tiles(&Hr, n, A.tiles, leftover);
     const char* nospan = std::getenv("QSV_NO_SPAN_PASS");
     const bool span = !(nospan && nospan[0] == '1');
-    if (!span || leftover.empty()) {
-        A.pairs.swap(leftover);
-    } else {
-        SubSum L;
-        for (const auto& pr : leftover)
-            for (int k = 0; k < pr.second.nt; ++k) {
-                L.x.push_back(pr.first);
-                L.z.push_back(pr.second.z[k]);
-                L.c.push_back(pr.second.c[k]);
+    const char* force = std::getenv("QSV_EXPECT_PLAN");
+    const bool want_r = span && force && std::strcmp(force, "reg") == 0;
+    const bool want_s = span && force && std::strcmp(force, "span") == 0;
+    std::vector<ExpPlan> plans;
+    if (!want_s) {
+        std::vector<int> rest;
+        std::vector<RegPassK> regs;
+        plan_reg_passes(H, n, regs, rest);
+        const SubSum R(H, rest);
+        const qsv_pauli_sum Hr = R.sum();
+        ExpPlan A;  // R1
+        A.regs = regs;
+        if (!rest.empty()) {
+            std::vector<std::pair<uint64_t, TermChunk>> leftover;
+            plan_tiles(&Hr, n, A.tiles, leftover);
+            if (!span || leftover.empty()) {
+                A.pairs.swap(leftover);
+            } else {
+                SubSum L;
+                for (const auto& pr : leftover)
+                    for (int k = 0; k < pr.second.nt; ++k) {
+                        L.x.push_back(pr.first);
+                        L.z.push_back(pr.second.z[k]);
+                        L.c.push_back(pr.second.c[k]);
+                    }
+                const qsv_pauli_sum Hl = L.sum();
+                plan_span_passes(&Hl, n, A.spans);
             }
-        add_spans(L, n, A);
-    }
-    // span passes first
-    ExpPlan B;
-    if (span) {
-        std::vector<int> hi, lo;
-        for (int j = 0; j < Hr.nterms; ++j)
-            ((Hr.x_mask[j] >> kSpanLaneQubits) != 0 ? hi : lo).push_back(j);
-        add_spans(SubSum(&Hr, hi), n, B);
-        if (!lo.empty()) {
-            const SubSum Lo(&Hr, lo);
-            const qsv_pauli_sum Hlo = Lo.sum();
-            std::vector<std::pair<uint64_t, TermChunk>> left;
-            plan_tiles(&Hlo, n, B.tiles, left);
-            B.pairs.insert(B.pairs.end(), left.begin(), left.end());
+        }
+        plans.push_back(A);
+        if (span && !rest.empty()) {
+            ExpPlan B;  // R2
+            B.regs = regs;
+            plan_span_passes(&Hr, n, B.spans);
+            plans.push_back(B);
         }
     }
-    const ExpPlan& W = (span && B.cost() <= A.cost()) ? B : A;
-    P.tiles = W.tiles;
-    P.spans = W.spans;
-    P.pairs = W.pairs;
+    if (span && !want_r) {
+        ExpPlan S;
+        plan_span_passes(H, n, S.spans);
+        plans.push_back(S);
+    }
+    size_t best = 0;
+    for (size_t i = 1; i < plans.size(); ++i)
+        if (plans[i].cost(dt) < plans[best].cost(dt))
+            best = i;
+    P = plans[best];
 }
 
 qsv_status enqueue_expectation(const void* psi, int n, int dt, const qsv_pauli_sum* H, double* out,
@@ -830,7 +847,7 @@ qsv_status enqueue_expectation(const void* psi, int n, int dt, const qsv_pauli_s
     const int nb = reduce_blocks(n, dt);
     if (n >= kTileQubits) {
         ExpPlan P;
-        plan_expectation(H, n, P);
+        plan_expectation(H, n, dt, P);
         for (const RegPassK& k : P.regs) {
             hipError_t e = launch_reg_pass(k, psi, dt, work, nb, acc, s);
             if (e != hipSuccess)
@@ -1124,7 +1141,7 @@ qsv_status qsv_expectation_launches(const qsv_pauli_sum* H, int n, qsv_dtype dt,
     int count = 1;  // the finalize
     if (n >= kTileQubits) {
         ExpPlan P;
-        plan_expectation(H, n, P);
+        plan_expectation(H, n, dt, P);
         count += (int)(P.regs.size() + P.tiles.size() + P.spans.size() + P.pairs.size());
     } else {
         std::vector<TermChunk> diag;

@@ -1,5 +1,6 @@
 // Span passes: <psi|H|psi> for Pauli strings with arbitrary x masks, up to
-// five x masks per state read.
+// five x masks with a qubit above 5 per state read, plus any number of
+// strings whose x mask lies on qubits 0..5 and of diagonal strings.
 //
 // A string P = i^ylo X^x Z^z pairs every amplitude with the one whose index
 // differs by x; a pass over the state for each x mask reads the state once
@@ -20,6 +21,11 @@
 // (-1)^(z.a).  The sign splits as z.a = z.base + z.L + z.D(r): a tile part
 // (uniform; lane k evaluates it for string k and a ballot gathers the bits),
 // a lane part (fixed per lane) and a register part per pair (host table).
+// A string with x on qubits 0..5 pairs (L, r) with (L ^ x, r), taken over
+// the cross-lane crossbar; each lane sums its own 32 ordered pairs, so every
+// unordered pair is counted from both ends and the factor 2 is not needed.
+// Diagonal strings use the per-lane Walsh-Hadamard transform of |psi|^2
+// over the registers, N(m), with m = the string's register mask.
 // Every product and sum is FP64 (amplitudes widened first), in a fixed order.
 #include <type_traits>
 
@@ -86,6 +92,25 @@ __device__ __forceinline__ double string_sum(const double (&re)[kNR], const doub
     return t;
 }
 
+// sum_r (-1)^(bit r of m) f_r, f_r = Re (IM false) or Im (IM true) of
+// conj(psi_b) psi_a, a = (L, r), b = (L ^ xl, r): the partner amplitudes
+// come over the cross-lane crossbar (complex64 ones as their float values,
+// which the widened doubles hold exactly).
+template <bool IM, typename R>
+__device__ __forceinline__ double lane_sum(const double (&re)[kNR], const double (&im)[kNR], int xl, uint32_t m)
+{
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < kNR; ++r) {
+        const double br = (double)__shfl_xor((R)re[r], xl, 64);
+        const double bi = (double)__shfl_xor((R)im[r], xl, 64);
+        const double f = IM ? im[r] * br - re[r] * bi : re[r] * br + im[r] * bi;
+        const double sgn = __longlong_as_double((long long)(0x3FF0000000000000ull | ((uint64_t)((m >> r) & 1) << 63)));
+        t = __builtin_fma(f, sgn, t);
+    }
+    return t;
+}
+
 __device__ __forceinline__ double lane_double(double v, int k)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
@@ -107,7 +132,7 @@ __global__ void __launch_bounds__(256) k_span_pass(const R* __restrict__ psi, co
     // tile loop; lane part of every string's sign once
     double tc = 0.0;
     uint64_t tz = 0;
-    int tsgn = 0;
+    int tsgn = 0, txl = 0;
     uint64_t lsg = 0;
     for (int k = 0; k < a.nt; ++k)
         lsg |= (uint64_t)(__popcll((uint64_t)lane & a.t[k].z) & 1) << k;
@@ -115,6 +140,7 @@ __global__ void __launch_bounds__(256) k_span_pass(const R* __restrict__ psi, co
         tc = a.t[lane].c;
         tz = a.t[lane].z;
         tsgn = (int)a.t[lane].sgn;
+        txl = (int)a.t[lane].xl;
     }
     const A* const p = reinterpret_cast<const A*>(psi);
     double acc = 0.0;
@@ -135,13 +161,14 @@ __global__ void __launch_bounds__(256) k_span_pass(const R* __restrict__ psi, co
         double s = 0.0;
         // strings grouped by (direction, Re/Im): one loop per group with
         // the pair pattern fixed at compile time
+        auto add = [&](int k, double t) {
+            const double w = lane_double(tc, k) * t;
+            s += ((sg >> k) & 1) ? -w : w;
+        };
         auto group = [&](auto key) {
             constexpr int K = decltype(key)::value;
-            for (int k = a.koff[K]; k < a.koff[K + 1]; ++k) {
-                const uint32_t m = (uint32_t)__builtin_amdgcn_readlane(tsgn, k);
-                const double w = lane_double(tc, k) * string_sum<K / 2, (K & 1) != 0>(re, im, m);
-                s += ((sg >> k) & 1) ? -w : w;
-            }
+            for (int k = a.koff[K]; k < a.koff[K + 1]; ++k)
+                add(k, string_sum<K / 2, (K & 1) != 0>(re, im, (uint32_t)__builtin_amdgcn_readlane(tsgn, k)));
         };
         group(std::integral_constant<int, 0>{});
         group(std::integral_constant<int, 1>{});
@@ -153,6 +180,36 @@ __global__ void __launch_bounds__(256) k_span_pass(const R* __restrict__ psi, co
         group(std::integral_constant<int, 7>{});
         group(std::integral_constant<int, 8>{});
         group(std::integral_constant<int, 9>{});
+        // lane strings: the partner is in lane L ^ xl
+        for (int k = a.koff[2 * kSpanDirs]; k < a.koff[2 * kSpanDirs + 1]; ++k)
+            add(k, lane_sum<false, R>(re, im, __builtin_amdgcn_readlane(txl, k),
+                                      (uint32_t)__builtin_amdgcn_readlane(tsgn, k)));
+        for (int k = a.koff[2 * kSpanDirs + 1]; k < a.koff[kSpanGroups]; ++k)
+            add(k, lane_sum<true, R>(re, im, __builtin_amdgcn_readlane(txl, k),
+                                     (uint32_t)__builtin_amdgcn_readlane(tsgn, k)));
+        if (a.koff[kSpanGroups] < a.nt) {
+            // diagonal strings: N(m) = sum_r (-1)^popcount(r & m) |psi_(L,r)|^2
+            // (five butterfly stages in place of re; the other strings are
+            // done with it), read at compile-time m per group of strings
+#pragma unroll
+            for (int r = 0; r < kNR; ++r)
+                re[r] = re[r] * re[r] + im[r] * im[r];
+#pragma unroll
+            for (int h = 1; h < kNR; h <<= 1)
+#pragma unroll
+                for (int r = 0; r < kNR; ++r)
+                    if (!(r & h)) {
+                        const double x0 = re[r], x1 = re[r + h];
+                        re[r] = x0 + x1;
+                        re[r + h] = x0 - x1;
+                    }
+#pragma unroll
+            for (int m = 0; m < kNR; ++m)
+                for (int k = a.mofs[m]; k < a.mofs[m + 1]; ++k) {
+                    const double w = lane_double(tc, k) * re[m];
+                    s += ((sg >> k) & 1) ? -w : w;
+                }
+        }
         acc += s;
     }
     for (int off = 32; off > 0; off >>= 1)
@@ -222,14 +279,26 @@ hipError_t launch_span_pass(const SpanPassK& a, const void* psi, int dt, double*
         return hipSuccess;
     if (a.nt < 0 || a.nt > kMaxSpanTerms)
         return hipErrorInvalidValue;
-    // strings of group g = 2 dir + im at [koff[g], koff[g + 1])
-    if (a.koff[0] != 0 || a.koff[2 * kSpanDirs] != a.nt)
+    // group offsets ascending from 0 to nt; direction and lane strings in
+    // their groups; diagonal offsets from koff[kSpanGroups] to nt
+    if (a.koff[0] != 0 || a.mofs[0] != a.koff[kSpanGroups] || a.mofs[1 << kSpanDirs] != a.nt)
         return hipErrorInvalidValue;
-    for (int g = 0; g < 2 * kSpanDirs; ++g) {
+    for (int g = 0; g < kSpanGroups; ++g) {
         if (a.koff[g + 1] < a.koff[g])
             return hipErrorInvalidValue;
-        for (int k = a.koff[g]; k < a.koff[g + 1]; ++k)
-            if (2 * a.t[k].dir + a.t[k].im != g)
+        for (int k = a.koff[g]; k < a.koff[g + 1]; ++k) {
+            const STerm& t = a.t[k];
+            const bool ok = g < 2 * kSpanDirs ? (2 * t.dir + t.im == g)
+                                              : (t.dir == -1 && t.im == g - 2 * kSpanDirs && t.xl != 0 && t.xl < 64);
+            if (!ok)
+                return hipErrorInvalidValue;
+        }
+    }
+    for (int m = 0; m < (1 << kSpanDirs); ++m) {
+        if (a.mofs[m + 1] < a.mofs[m])
+            return hipErrorInvalidValue;
+        for (int k = a.mofs[m]; k < a.mofs[m + 1]; ++k)
+            if ((int)a.t[k].zr != m)
                 return hipErrorInvalidValue;
     }
     return dt == C64 ? go<float>(a, psi, partials, nslots, accumulate, s)

@@ -61,8 +61,7 @@ int main(int argc, char** argv)
 
     const qsv_pauli_sum H{nt, X.data(), Z.data(), C.data()};
     std::vector<SpanPassK> passes;
-    std::vector<int> rest;
-    qsv::plan_span_passes(&H, n, passes, rest);
+    qsv::plan_span_passes(&H, n, passes);
 
     double energy = 0.0;
     std::vector<unsigned char> seen(N);
@@ -81,10 +80,24 @@ int main(int argc, char** argv)
             tmask |= 1ull << q;
         }
         require((tmask & 63) == 63, "lanes on qubits 0..5", pi);
-        require(P.koff[0] == 0 && P.koff[2 * qsv::kSpanDirs] == P.nt, "group offsets", pi);
-        for (int g = 0; g < 2 * qsv::kSpanDirs; ++g)
-            for (int k = P.koff[g]; k < P.koff[g + 1]; ++k)
-                require(2 * P.t[k].dir + P.t[k].im == g, "string group", pi);
+        const int G = qsv::kSpanGroups, NM = 1 << qsv::kSpanDirs;
+        require(P.koff[0] == 0 && P.mofs[0] == P.koff[G] && P.mofs[NM] == P.nt, "group offsets", pi);
+        for (int g = 0; g < G; ++g) {
+            require(P.koff[g] <= P.koff[g + 1], "group offsets ascending", pi);
+            for (int k = P.koff[g]; k < P.koff[g + 1]; ++k) {
+                const STerm& t = P.t[k];
+                if (g < 2 * qsv::kSpanDirs)
+                    require(2 * t.dir + t.im == g && t.xl == 0, "direction string group", pi);
+                else
+                    require(t.dir == -1 && t.im == g - 2 * qsv::kSpanDirs && t.xl != 0 && t.xl < 64,
+                            "lane string group", pi);
+            }
+        }
+        for (int m = 0; m < NM; ++m) {
+            require(P.mofs[m] <= P.mofs[m + 1], "diagonal offsets ascending", pi);
+            for (int k = P.mofs[m]; k < P.mofs[m + 1]; ++k)
+                require(P.t[k].dir == -1 && P.t[k].xl == 0 && (int)P.t[k].zr == m, "diagonal group", pi);
+        }
         auto D = [&](int r) {
             uint64_t o = 0;
             for (int j = 0; j < qsv::kSpanDirs; ++j)
@@ -98,36 +111,43 @@ int main(int argc, char** argv)
             for (int j = 0; j < qsv::kSpanTileQubits; ++j)
                 base = ((base & ~P.low[j]) << 1) | (base & P.low[j]);
             require(base < N && (base & tmask) == 0, "tile base", pi);
-            for (int lane = 0; lane < 64; ++lane) {
-                cd a[32];
+            static cd a[64][32];
+            for (int lane = 0; lane < 64; ++lane)
                 for (int r = 0; r < 32; ++r) {
                     const uint64_t i = base ^ (uint64_t)lane ^ D(r);
                     require(i < N, "index in range", pi);
                     require(seen[i] == 0, "index reached twice", pi);
                     seen[i] = 1;
-                    a[r] = psi[i];
+                    a[lane][r] = psi[i];
                 }
+            for (int lane = 0; lane < 64; ++lane)
                 for (int k = 0; k < P.nt; ++k) {
                     const STerm& t = P.t[k];
-                    require(t.dir >= 0 && t.dir < qsv::kSpanDirs && (t.im == 0 || t.im == 1), "string kind", pi);
                     double s = 0.0;
-                    for (int i = 0; i < 16; ++i) {
-                        const int r = ((i >> t.dir) << (t.dir + 1)) | (i & ((1 << t.dir) - 1));
-                        const cd w = std::conj(a[r ^ (1 << t.dir)]) * a[r];
-                        const double fv = t.im ? w.imag() : w.real();
-                        s += ((t.sgn >> i) & 1) ? -fv : fv;
+                    if (k < P.koff[2 * qsv::kSpanDirs]) {  // direction string
+                        for (int i = 0; i < 16; ++i) {
+                            const int r = ((i >> t.dir) << (t.dir + 1)) | (i & ((1 << t.dir) - 1));
+                            const cd w = std::conj(a[lane][r ^ (1 << t.dir)]) * a[lane][r];
+                            const double fv = t.im ? w.imag() : w.real();
+                            s += ((t.sgn >> i) & 1) ? -fv : fv;
+                        }
+                    } else if (k < P.koff[G]) {  // lane string
+                        for (int r = 0; r < 32; ++r) {
+                            const cd w = std::conj(a[lane ^ t.xl][r]) * a[lane][r];
+                            const double fv = t.im ? w.imag() : w.real();
+                            s += ((t.sgn >> r) & 1) ? -fv : fv;
+                        }
+                    } else {  // diagonal string
+                        for (int r = 0; r < 32; ++r)
+                            s += (par((uint64_t)(r & t.zr)) ? -1.0 : 1.0) * std::norm(a[lane][r]);
                     }
                     const int sg = par(t.z & base) ^ par(t.z & (uint64_t)lane);
                     energy += (sg ? -1.0 : 1.0) * t.c * s;
                 }
-            }
         }
         for (uint64_t i = 0; i < N; ++i)
             require(seen[i] == 1, "index not reached", pi);
     }
-    std::printf("passes %d\nrest", (int)passes.size());
-    for (int j : rest)
-        std::printf(" %d", j);
-    std::printf("\nenergy %.17g\n", energy);
+    std::printf("passes %d\nenergy %.17g\n", (int)passes.size(), energy);
     return 0;
 }

@@ -354,31 +354,44 @@ def test_observables_register_many_terms(q, orc, n):
 
 @pytest.mark.parametrize("n", [16, 20])
 def test_observables_span_passes(q, orc, n, monkeypatch):
-    """Strings with arbitrary x masks (random strings, 40 strings on one
-    mask, XORs of earlier masks, masks on qubits 0..5 only, a Y on the top
-    qubit): span passes of five x masks per state read, against the oracle
-    and against one pass per x mask (QSV_NO_SPAN_PASS=1)."""
+    """Strings with arbitrary x masks (random strings, 70 strings on one
+    mask, XORs of earlier masks, strings on qubits 0..5, diagonal strings, a
+    Y on the top qubit), an XXZ chain and a Heisenberg chain with fields:
+    the default plan, the register-pass plans (QSV_EXPECT_PLAN=reg), span
+    passes alone (=span) and one pass per x mask (QSV_NO_SPAN_PASS=1), each
+    against the oracle."""
     from test_span_plan import span_sum
     rng = np.random.default_rng(1500 + n)
-    H = span_sum(n, 700 + n)
-    n_span = q.expectation_launches(H, n, q.C64)
-    monkeypatch.setenv("QSV_NO_SPAN_PASS", "1")
-    n_pair = q.expectation_launches(H, n, q.C64)
-    monkeypatch.delenv("QSV_NO_SPAN_PASS")
-    assert n_span < n_pair, (n_span, n_pair)
-    scale = np.sum(np.abs(H.coeff))
-    for name in DTYPES:
-        psi = rand_state(n, rng, name)
-        d = to_gpu(psi, name)
-        say("span-pass expectation", name, n, len(H.coeff), "launches", n_span, "vs", n_pair)
-        e = q.qsv_expectation(d, H).cpu().numpy()
-        ref = orc.expect(psi, H)
-        assert abs(e[0] - ref.real) <= 1e-10 * scale, (e, ref)
-        assert abs(e[1]) <= 1e-10 * scale
-        monkeypatch.setenv("QSV_NO_SPAN_PASS", "1")
-        e_pair = q.qsv_expectation(d, H).cpu().numpy()
-        monkeypatch.delenv("QSV_NO_SPAN_PASS")
-        assert abs(e_pair[0] - e[0]) <= 1e-10 * scale, (e_pair, e)
+    heis = [(ab, (j, j + 1), 1.0) for j in range(n - 1) for ab in ("XX", "YY", "ZZ")]
+    heis += [(c, (j,), float(rng.normal())) for j in range(n) for c in "XYZ"]
+    models = [("span_sum", span_sum(n, 700 + n)), ("xxz", W.xxz_chain(n, 0.5)),
+              ("heisenberg_fields", W.pauli_sum(n, heis))]
+    variants = [("default", None, None), ("reg", "QSV_EXPECT_PLAN", "reg"), ("span", "QSV_EXPECT_PLAN", "span"),
+                ("per-mask", "QSV_NO_SPAN_PASS", "1")]
+    for mname, H in models:
+        scale = np.sum(np.abs(H.coeff))
+        counts = {}
+        for vname, var, val in variants:
+            if var:
+                monkeypatch.setenv(var, val)
+            counts[vname] = q.expectation_launches(H, n, q.C64)
+            if var:
+                monkeypatch.delenv(var)
+        if mname == "span_sum":
+            assert counts["default"] < counts["per-mask"], counts
+        for name in DTYPES:
+            psi = rand_state(n, rng, name)
+            d = to_gpu(psi, name)
+            ref = orc.expect(psi, H)
+            for vname, var, val in variants:
+                if var:
+                    monkeypatch.setenv(var, val)
+                say("expectation plans", mname, name, n, vname, "launches", counts[vname])
+                e = q.qsv_expectation(d, H).cpu().numpy()
+                if var:
+                    monkeypatch.delenv(var)
+                assert abs(e[0] - ref.real) <= 1e-10 * scale, (mname, vname, e, ref)
+                assert abs(e[1]) <= 1e-10 * scale
 
 
 def test_plan_random_circuit(q, orc):
