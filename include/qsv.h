@@ -173,12 +173,18 @@ qsv_status qsv_norm2(const void* psi, int n, qsv_dtype dt, double* out_dev, void
                      void* stream);
 
 /* out_dev[0] = Re <psi|H|psi>, out_dev[1] = Im (a rounding diagnostic; 0 in
- * exact arithmetic for real coefficients; terms taken by the register passes
- * below visit each Hermitian pair once and add exactly 0 to it), accumulated
- * in FP64 in a fixed order.  For n >= 12: diagonal strings and single-qubit X
- * strings go to register passes (one read of psi per set of up to five X
- * qubits above qubit 4); other strings to 12-qubit tile passes grouped by x
- * mask; a string no tile holds to a pass of its own x mask.
+ * exact arithmetic for real coefficients; terms taken by the register and
+ * span passes below add exactly 0 to it), accumulated in FP64 in a fixed
+ * order (Sec. 3, expectation values of Hamiltonians given as sums of Pauli
+ * strings).  For n >= 12 the strings are read in passes of one state read
+ * each, the cheapest of three plans by a cost measured per dtype:
+ * register-tile passes (diagonal strings and strings whose x mask is one or
+ * two neighbouring qubits of a five-qubit register set, or of qubits 0..4)
+ * with 12-qubit LDS-tile passes or span passes for the rest, or span passes
+ * alone (any x mask: five masks with a qubit above 5 per pass, strings on
+ * qubits 0..5 and diagonal strings spread over them).  The environment
+ * variable QSV_EXPECT_PLAN=reg or =span restricts the choice (comparisons);
+ * QSV_NO_SPAN_PASS=1 replaces span passes by one pass per x mask.
  * qsv_expectation_launches reports the launch count.  out_dev: 2 doubles,
  * device. */
 qsv_status qsv_expectation(const void* psi, int n, qsv_dtype dt, const qsv_pauli_sum* H,
