@@ -73,6 +73,9 @@ __device__ __forceinline__ void block_sum_store(double v, double* out)
     __syncthreads();
 }
 
+typedef float nv4f __attribute__((ext_vector_type(4)));
+typedef double nv2d __attribute__((ext_vector_type(2)));
+
 template <typename R>
 struct W;
 template <>
@@ -113,6 +116,16 @@ __device__ __forceinline__ int popc64(uint64_t v)
     return __popcll(v);
 }
 
+// Block index in XCD-contiguous order (a bijection on [0, gridDim.x)): the
+// hardware deals blocks round-robin to the 8 XCDs, so block b reads the
+// slice of logical block (b mod 8) * G/8 + b / 8 and each XCD streams one
+// contiguous eighth of every round of the grid-stride loop.
+__device__ __forceinline__ uint64_t xcd_block()
+{
+    const uint32_t G = gridDim.x, b = blockIdx.x, per = G >> 3;
+    return b < (per << 3) ? (uint64_t)(b & 7u) * per + (b >> 3) : (uint64_t)b;
+}
+
 // sum_j c_j (-1)^popcount(i & z_j)
 __device__ __forceinline__ double diag_weight(uint64_t i, const TermChunk& t)
 {
@@ -140,23 +153,55 @@ __global__ void __launch_bounds__(kBlock) k_norm2(const R* __restrict__ psi, uin
                                                   double* partials, int accumulate)
 {
     (void)accumulate;
+    // software pipeline: the next round's U loads are issued before this
+    // round's squares are summed (loads streamed past the caches); the sums
+    // keep the thread's index order
+    constexpr int U = 4;
+    using A = typename W<R>::A;
+    const A* p = reinterpret_cast<const A*>(psi);
     double s = 0.0;
     const uint64_t step = (uint64_t)gridDim.x * kBlock;
-    if constexpr (sizeof(R) == 4) {
-        for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < N / 2; v += step) {
-            double2 a, b;
-            ld_pair(psi, v, a, b);
-            s += a.x * a.x + a.y * a.y + (b.x * b.x + b.y * b.y);
+    const uint64_t nu = sizeof(R) == 4 ? N / 2 : N;  // 16-byte units
+    auto unit = [&](uint64_t v) {
+        if constexpr (sizeof(R) == 4) {
+            const nv4f f = __builtin_nontemporal_load(reinterpret_cast<const nv4f*>(p) + v);
+            return make_double4((double)f.x, (double)f.y, (double)f.z, (double)f.w);
+        } else {
+            const nv2d a = __builtin_nontemporal_load(reinterpret_cast<const nv2d*>(p) + v);
+            return make_double4(a.x, a.y, 0.0, 0.0);
         }
-        if (N == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
-            const double2 a = ld(psi, 0);
-            s += a.x * a.x + a.y * a.y;
+    };
+    auto sq = [](const double4& d) { return d.x * d.x + d.y * d.y + (d.z * d.z + d.w * d.w); };
+    uint64_t v = xcd_block() * kBlock + threadIdx.x;
+    if (v + (U - 1) * step < nu) {
+        double4 cur[U], nxt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            cur[u] = unit(v + (uint64_t)u * step);
+        for (;;) {
+            const uint64_t vn = v + U * step;
+            const bool more = vn + (U - 1) * step < nu;
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    nxt[u] = unit(vn + (uint64_t)u * step);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                s += sq(cur[u]);
+            v = vn;
+            if (!more)
+                break;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                cur[u] = nxt[u];
         }
-    } else {
-        for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
-            const double2 a = ld(psi, i);
-            s += a.x * a.x + a.y * a.y;
-        }
+    }
+    for (; v < nu; v += step)
+        s += sq(unit(v));
+    if (sizeof(R) == 4 && N == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+        const double2 a = ld(psi, 0);
+        s += a.x * a.x + a.y * a.y;
     }
     block_sum_store(s, partials + blockIdx.x);
 }
@@ -310,27 +355,65 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_inner(const R* __restrict__ a, const R* __restrict__ b,
                                                   uint64_t N, double* partials, int accumulate)
 {
+    // software pipeline as in k_norm2: the next round's loads of both
+    // vectors are issued before this round's products are summed; the sums
+    // keep the thread's index order
+    constexpr int U = 2;
     double sr = 0.0, si = 0.0;
     const uint64_t step = (uint64_t)gridDim.x * kBlock;
-    if constexpr (sizeof(R) == 4) {
-        for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < N / 2; v += step) {
-            double2 u0, u1, v0, v1;
-            ld_pair(a, v, u0, u1);
-            ld_pair(b, v, v0, v1);
-            sr += (u0.x * v0.x + u0.y * v0.y) + (u1.x * v1.x + u1.y * v1.y);
-            si += (u0.x * v0.y - u0.y * v0.x) + (u1.x * v1.y - u1.y * v1.x);
+    const uint64_t nu = sizeof(R) == 4 ? N / 2 : N;  // 16-byte units
+    auto unit = [&](const R* q, uint64_t v) {
+        if constexpr (sizeof(R) == 4) {
+            const nv4f f = __builtin_nontemporal_load(reinterpret_cast<const nv4f*>(q) + v);
+            return make_double4((double)f.x, (double)f.y, (double)f.z, (double)f.w);
+        } else {
+            const nv2d d = __builtin_nontemporal_load(reinterpret_cast<const nv2d*>(q) + v);
+            return make_double4(d.x, d.y, 0.0, 0.0);
         }
-        if (N == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
-            const double2 u = ld(a, 0), v = ld(b, 0);
-            sr += u.x * v.x + u.y * v.y;
-            si += u.x * v.y - u.y * v.x;
+    };
+    // conj(u) v summed over the unit's amplitudes (complex128: the zero
+    // second half adds exact zeros)
+    auto add = [&](const double4& u, const double4& v) {
+        sr += (u.x * v.x + u.y * v.y) + (u.z * v.z + u.w * v.w);
+        si += (u.x * v.y - u.y * v.x) + (u.z * v.w - u.w * v.z);
+    };
+    uint64_t v = xcd_block() * kBlock + threadIdx.x;
+    if (v + (U - 1) * step < nu) {
+        double4 ca[U], cb[U], na[U], nb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ca[u] = unit(a, v + (uint64_t)u * step);
+            cb[u] = unit(b, v + (uint64_t)u * step);
         }
-    } else {
-        for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += step) {
-            const double2 u = ld(a, i), v = ld(b, i);
-            sr += u.x * v.x + u.y * v.y;
-            si += u.x * v.y - u.y * v.x;
+        for (;;) {
+            const uint64_t vn = v + U * step;
+            const bool more = vn + (U - 1) * step < nu;
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    na[u] = unit(a, vn + (uint64_t)u * step);
+                    nb[u] = unit(b, vn + (uint64_t)u * step);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                add(ca[u], cb[u]);
+            v = vn;
+            if (!more)
+                break;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ca[u] = na[u];
+                cb[u] = nb[u];
+            }
         }
+    }
+    for (; v < nu; v += step)
+        add(unit(a, v), unit(b, v));
+    if (sizeof(R) == 4 && N == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+        const double2 u = ld(a, 0), w = ld(b, 0);
+        sr += u.x * w.x + u.y * w.y;
+        si += u.x * w.y - u.y * w.x;
     }
     __shared__ double red[2][kBlock];
     red[0][threadIdx.x] = sr;
