@@ -748,7 +748,7 @@ struct ExpPlan {
     std::vector<std::pair<uint64_t, TermChunk>> pairs;
     // complex64 passes are partly bound by their FP64 arithmetic, complex128
     // ones by the state read: register passes with transposed roles and
-    // general strings 2.6 (1.7), with general strings 1.2 (1.05), with
+    // general strings 2.2 (1.45), with general strings 1.05 (1.02), with
     // transposed roles 1.1 (1.0); LDS-tile passes 1.7 (1.3); per-mask passes
     // 1.15; a span pass grows with its arithmetic L (direction strings 1,
     // lane strings 2.5, diagonal strings 0.1 plus 2 for their transform):
@@ -760,7 +760,7 @@ struct ExpPlan {
         double c = (c64 ? 1.7 : 1.3) * (double)tiles.size() + 1.15 * (double)pairs.size();
         for (const RegPassK& k : regs) {
             const bool tr = k.nt > k.n1, gen = k.n1 > k.ns1 || k.nc > k.ns2 || k.nt > k.nc;
-            c += (tr && gen) ? (c64 ? 2.6 : 1.7) : gen ? (c64 ? 1.2 : 1.05) : tr ? (c64 ? 1.1 : 1.0) : 1.0;
+            c += (tr && gen) ? (c64 ? 2.2 : 1.45) : gen ? (c64 ? 1.05 : 1.02) : tr ? (c64 ? 1.1 : 1.0) : 1.0;
         }
         for (const SpanPassK& k : spans) {
             const int ndir = k.koff[2 * kSpanDirs], nlane = k.koff[kSpanGroups] - ndir,

@@ -86,11 +86,9 @@ __device__ __forceinline__ double pair_sum(const double (&re)[kNR], const double
         if ((r >> K) & 1)
             continue;
         const int j = r | (1 << K);
-        const double d = re[r] * re[j] + im[r] * im[j];
-        if (m++ & 1)
-            s1 += d;
-        else
-            s0 += d;
+        double& t = (m++ & 1) ? s1 : s0;
+        t = __builtin_fma(re[r], re[j], t);
+        t = __builtin_fma(im[r], im[j], t);
     }
     return s0 + s1;
 }
@@ -173,11 +171,14 @@ __device__ __forceinline__ Halves gen_sum(const double (&re)[kNR], const double 
         if ((r >> HB) & 1)
             continue;
         const int j = r ^ XR;
-        const double d = IM ? im[r] * re[j] - re[r] * im[j] : re[r] * re[j] + im[r] * im[j];
-        if (LB != HB ? ((r >> LB) & 1) : (m++ & 1))
-            s1 += d;
-        else
-            s0 += d;
+        double& t = (LB != HB ? ((r >> LB) & 1) : (m++ & 1)) ? s1 : s0;
+        if (IM) {
+            t = __builtin_fma(im[r], re[j], t);
+            t = __builtin_fma(-re[r], im[j], t);
+        } else {
+            t = __builtin_fma(re[r], re[j], t);
+            t = __builtin_fma(im[r], im[j], t);
+        }
     }
     return Halves{s0, s1};
 }
@@ -238,11 +239,14 @@ __device__ __forceinline__ double cross_terms(const LaneTerms& L, uint64_t sg, i
         for (int r = 0; r < kNR / 2; ++r) {
             const double br = __shfl_xor(re[r + kNR / 2], xl, 64);
             const double bi = __shfl_xor(im[r + kNR / 2], xl, 64);
-            const double d = (ylo & 1) ? im[r] * br - re[r] * bi : re[r] * br + im[r] * bi;
-            if (r & 1)
-                s1 += d;
-            else
-                s0 += d;
+            double& t = (r & 1) ? s1 : s0;
+            if (ylo & 1) {
+                t = __builtin_fma(im[r], br, t);
+                t = __builtin_fma(-re[r], bi, t);
+            } else {
+                t = __builtin_fma(re[r], br, t);
+                t = __builtin_fma(im[r], bi, t);
+            }
         }
         const double v = term_coef(L, k) * (s0 + s1);
         s += ((sg >> k) & 1) ? -v : v;
