@@ -352,11 +352,12 @@ def test_observables_register_many_terms(q, orc, n):
         assert abs(e[1]) <= 1e-10 * scale
 
 
-@pytest.mark.parametrize("n", [16, 20])
+@pytest.mark.parametrize("n", [12, 16, 20])
 def test_observables_span_passes(q, orc, n, monkeypatch):
     """Strings with arbitrary x masks (random strings, 70 strings on one
     mask, XORs of earlier masks, strings on qubits 0..5, diagonal strings, a
-    Y on the top qubit), an XXZ chain and a Heisenberg chain with fields:
+    Y on the top qubit), an XXZ chain and a Heisenberg chain with fields, at
+    n = 12 (two tiles per span pass), 16 and 20:
     the default plan, the register-pass plans (QSV_EXPECT_PLAN=reg), span
     passes alone (=span) and one pass per x mask (QSV_NO_SPAN_PASS=1), each
     against the oracle."""
@@ -377,7 +378,7 @@ def test_observables_span_passes(q, orc, n, monkeypatch):
             counts[vname] = q.expectation_launches(H, n, q.C64)
             if var:
                 monkeypatch.delenv(var)
-        if mname == "span_sum":
+        if mname == "span_sum" and n >= 16:  # at n = 12 every string fits a 12-qubit tile
             assert counts["default"] < counts["per-mask"], counts
         for name in DTYPES:
             psi = rand_state(n, rng, name)

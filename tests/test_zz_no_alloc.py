@@ -27,8 +27,10 @@ def q():
 def test_noalloc_expectation_matches_workspace_version(q, orc, name):
     import torch
     rng = np.random.default_rng(2027)
-    cases = [(20, W.tfim_chain(20)), (13, W.random_pauli_sum(13, 9, seed=5)),
-             (6, W.xxz_chain(6, 0.7))]
+    # register passes (TFIM), span passes (random strings on 18 qubits), tile
+    # passes, the small-state kernels; sizes shrink from call to call
+    cases = [(20, W.tfim_chain(20)), (18, W.random_pauli_sum(18, 24, seed=7)),
+             (13, W.random_pauli_sum(13, 9, seed=5)), (6, W.xxz_chain(6, 0.7))]
     for n, H in cases:
         psi = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
         psi /= np.linalg.norm(psi)
