@@ -76,6 +76,17 @@ __device__ __forceinline__ void block_sum_store(double v, double* out)
 typedef float nv4f __attribute__((ext_vector_type(4)));
 typedef double nv2d __attribute__((ext_vector_type(2)));
 
+// A 16-byte load, streamed past the caches (NT) for states far larger than
+// the caches, plain for states that the previous kernel left in L2 / MALL.
+template <bool NT, typename V>
+__device__ __forceinline__ V ldu(const V* p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
 template <typename R>
 struct W;
 template <>
@@ -148,14 +159,13 @@ __device__ __forceinline__ double2 phase_sum(uint64_t i, const TermChunk& t)
     return make_double2(re, im);
 }
 
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlock) k_norm2(const R* __restrict__ psi, uint64_t N,
                                                   double* partials, int accumulate)
 {
     (void)accumulate;
     // software pipeline: the next round's U loads are issued before this
-    // round's squares are summed (loads streamed past the caches); the sums
-    // keep the thread's index order
+    // round's squares are summed; the sums keep the thread's index order
     constexpr int U = 4;
     using A = typename W<R>::A;
     const A* p = reinterpret_cast<const A*>(psi);
@@ -164,10 +174,10 @@ __global__ void __launch_bounds__(kBlock) k_norm2(const R* __restrict__ psi, uin
     const uint64_t nu = sizeof(R) == 4 ? N / 2 : N;  // 16-byte units
     auto unit = [&](uint64_t v) {
         if constexpr (sizeof(R) == 4) {
-            const nv4f f = __builtin_nontemporal_load(reinterpret_cast<const nv4f*>(p) + v);
+            const nv4f f = ldu<NT>(reinterpret_cast<const nv4f*>(p) + v);
             return make_double4((double)f.x, (double)f.y, (double)f.z, (double)f.w);
         } else {
-            const nv2d a = __builtin_nontemporal_load(reinterpret_cast<const nv2d*>(p) + v);
+            const nv2d a = ldu<NT>(reinterpret_cast<const nv2d*>(p) + v);
             return make_double4(a.x, a.y, 0.0, 0.0);
         }
     };
@@ -351,7 +361,7 @@ __global__ void __launch_bounds__(kBlock) k_expect_pair1(const R* __restrict__ p
     }
 }
 
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlock) k_inner(const R* __restrict__ a, const R* __restrict__ b,
                                                   uint64_t N, double* partials, int accumulate)
 {
@@ -364,10 +374,10 @@ __global__ void __launch_bounds__(kBlock) k_inner(const R* __restrict__ a, const
     const uint64_t nu = sizeof(R) == 4 ? N / 2 : N;  // 16-byte units
     auto unit = [&](const R* q, uint64_t v) {
         if constexpr (sizeof(R) == 4) {
-            const nv4f f = __builtin_nontemporal_load(reinterpret_cast<const nv4f*>(q) + v);
+            const nv4f f = ldu<NT>(reinterpret_cast<const nv4f*>(q) + v);
             return make_double4((double)f.x, (double)f.y, (double)f.z, (double)f.w);
         } else {
-            const nv2d d = __builtin_nontemporal_load(reinterpret_cast<const nv2d*>(q) + v);
+            const nv2d d = ldu<NT>(reinterpret_cast<const nv2d*>(q) + v);
             return make_double4(d.x, d.y, 0.0, 0.0);
         }
     };
@@ -513,6 +523,11 @@ inline unsigned stream_grid(uint64_t items)
     return (unsigned)b;
 }
 
+// Reads of more than 1 GiB stream past the caches (the 256 MiB of MALL and
+// the L2s cannot hold them); smaller ones keep the plain loads, which hit
+// whatever the previous kernel left there (adjoint states of 20-24 qubits).
+bool streamed(uint64_t bytes) { return bytes > (1ull << 30); }
+
 }  // namespace
 
 hipError_t launch_norm2(const void* psi, int n, int dt, double* partials, int accumulate,
@@ -520,11 +535,12 @@ hipError_t launch_norm2(const void* psi, int n, int dt, double* partials, int ac
 {
     const int nb = reduce_blocks(n, dt);
     const uint64_t N = 1ull << n;
+    const bool nt = streamed(N * (dt == C64 ? 8 : 16));
     if (dt == C64)
-        hipLaunchKernelGGL(k_norm2<float>, dim3(nb), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL((nt ? k_norm2<float, true> : k_norm2<float, false>), dim3(nb), dim3(kBlock), 0, s,
                            static_cast<const float*>(psi), N, partials, accumulate);
     else
-        hipLaunchKernelGGL(k_norm2<double>, dim3(nb), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL((nt ? k_norm2<double, true> : k_norm2<double, false>), dim3(nb), dim3(kBlock), 0, s,
                            static_cast<const double*>(psi), N, partials, accumulate);
     return hipGetLastError();
 }
@@ -581,13 +597,14 @@ hipError_t launch_inner(const void* a, const void* b, int n, int dt, double* par
 {
     const int nb = reduce_blocks(n, dt);
     const uint64_t N = 1ull << n;
+    const bool nt = streamed(2 * N * (dt == C64 ? 8 : 16));
     if (dt == C64)
-        hipLaunchKernelGGL(k_inner<float>, dim3(nb), dim3(kBlock), 0, s, static_cast<const float*>(a),
-                           static_cast<const float*>(b), N, partials2, accumulate);
+        hipLaunchKernelGGL((nt ? k_inner<float, true> : k_inner<float, false>), dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const float*>(a), static_cast<const float*>(b), N, partials2, accumulate);
     else
-        hipLaunchKernelGGL(k_inner<double>, dim3(nb), dim3(kBlock), 0, s,
-                           static_cast<const double*>(a), static_cast<const double*>(b), N,
-                           partials2, accumulate);
+        hipLaunchKernelGGL((nt ? k_inner<double, true> : k_inner<double, false>), dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const double*>(a), static_cast<const double*>(b), N, partials2,
+                           accumulate);
     return hipGetLastError();
 }
 
