@@ -370,6 +370,21 @@ Built build_launch(int n, int dt, const int* ct, int k, const int* ctl, int c, c
             L.mfma3 = 0;
         else if (form && std::strcmp(form, "3m") == 0)
             L.mfma3 = 1;
+        // Tiles per workgroup of the three-product kernel, measured at n = 28
+        // and 30 over random and structured target sets: k = 5 takes four
+        // (the loads of the next tile run under the current one's products;
+        // complex128 5-18% faster than two on nearly every set, complex64 4%
+        // on average at n = 30 and even at n = 28), k = 4 two when its
+        // targets lie in a window of 8 qubits (1-5% faster) and one
+        // otherwise (the prefetch then costs about as much as it hides).
+        // QSV_MFMA_TPB=1|2|4 forces a count (comparisons).
+        const int span = *std::max_element(tgt.begin(), tgt.end()) - *std::min_element(tgt.begin(), tgt.end());
+        L.mfma_tpb = k == 5 ? 4 : (span < 2 * k ? 2 : 1);
+        if (const char* e = std::getenv("QSV_MFMA_TPB")) {
+            const int v = std::atoi(e);
+            if (v == 1 || v == 2 || v == 4)
+                L.mfma_tpb = v;
+        }
         if (L.mfma3)
             mfma3_fragments(Gc, k, dt, b.upload);
         else

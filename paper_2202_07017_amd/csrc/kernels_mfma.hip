@@ -23,10 +23,11 @@
 // registers (16 per lane for k = 5).  Results go back to LDS and the tile is
 // stored in place.  One tile per workgroup, blocks in XCD-contiguous order:
 // on MI355X this streams faster than persistent tile loops (measured), and
-// the small register footprint keeps several workgroups per CU.  The one
-// exception is the k = 5 three-product kernel below: it takes two
-// consecutive tiles per workgroup and issues the loads of the second as soon
-// as the first is in LDS, so they run under the first tile's products.
+// the small register footprint keeps several workgroups per CU.  The
+// exception is the three-product kernel below for k = 5 (and k = 4 with
+// clustered targets): it takes four (two) consecutive tiles per workgroup
+// and issues the loads of the next tile as soon as the current one is in
+// LDS, so they run under its products.
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -336,9 +337,10 @@ __device__ __forceinline__ void mfma3_multiply(R* lds, const R (&afr)[3][(1 << K
     }
 }
 
-// TPB consecutive tiles per workgroup (TPB divides ntiles; 1 or 2).  With
-// two, the loads of the second tile are issued as soon as the first is in
-// LDS (the load registers are free again), so they run under its products.
+// TPB consecutive tiles per workgroup (TPB divides ntiles; 1, 2 or 4).  With
+// more than one, the loads of the next tile are issued as soon as the current
+// one is in LDS (the load registers are free again), so they run under its
+// products.
 template <typename R, int K, int TPB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_wpe<R, K>()))) k_mfma3(R* __restrict__ psi0, R* __restrict__ psi1,
                                                const MfmaK<K> a, const R* __restrict__ frag)
@@ -355,7 +357,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_
     constexpr int WPR = 4 / RB;         // waves per row block
     constexpr int CBW = 4 / WPR;        // 16-column blocks per wave
     static_assert(RB == 1 || RB == 2, "tile split");
-    static_assert(TPB == 1 || TPB == 2, "tiles per workgroup");
+    static_assert(TPB == 1 || TPB == 2 || TPB == 4, "tiles per workgroup");
 
     __shared__ __align__(16) R lds[D * kRow * 2];
 
@@ -424,12 +426,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma3_
             __builtin_nontemporal_store(o, reinterpret_cast<NV*>(psi + 2 * (b + goff[r])));
         }
     };
-    if constexpr (TPB == 2) {
-        for (int it = 0; it < 2; ++it) {
+    if constexpr (TPB > 1) {
+#pragma unroll
+        for (int it = 0; it < TPB; ++it) {
             to_lds();
             __syncthreads();
-            if (it == 0) {
-                const uint64_t b1 = insert_bits(tile + 1, a.ins);
+            if (it + 1 < TPB) {
+                const uint64_t b1 = insert_bits(tile + it + 1, a.ins);
 #pragma unroll
                 for (int r = 0; r < VPT; ++r)
                     in[r] = __builtin_nontemporal_load(reinterpret_cast<const NV*>(psi + 2 * (b1 + goff[r])));
@@ -463,17 +466,18 @@ hipError_t mfma_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
         a.floc[j] = L.floc[j];
     if (L.ntiles > (1ull << 31))
         return hipErrorInvalidValue;
-    // k = 5 three-product blocks take two tiles per workgroup: measured at
-    // n = 30, complex64 2-14% faster on eight of nine target sets and 6%
-    // slower on one; complex128 0-7% faster than the real embedding on six of
-    // six; k = 4 gained on some sets and lost on others and keeps one
-    if constexpr (K == 5) {
-        if (L.mfma3 && L.ntiles >= 2) {
-            hipLaunchKernelGGL((k_mfma3<R, K, 2>), dim3((unsigned)(L.ntiles / 2), p1 ? 2 : 1), dim3(256), 0, s,
-                               static_cast<R*>(p0), static_cast<R*>(p1 ? p1 : p0), a,
-                               static_cast<const R*>(L.gdev));
-            return hipGetLastError();
-        }
+    // consecutive tiles per workgroup as the host chose them by the target
+    // layout (GateLaunch::mfma_tpb; the real-embedding kernel takes one)
+    const int tpb = L.mfma_tpb;
+    if (L.mfma3 && (tpb == 2 || tpb == 4) && L.ntiles >= (uint64_t)tpb) {
+        const dim3 g((unsigned)(L.ntiles / tpb), p1 ? 2 : 1);
+        if (tpb == 2)
+            hipLaunchKernelGGL((k_mfma3<R, K, 2>), g, dim3(256), 0, s, static_cast<R*>(p0),
+                               static_cast<R*>(p1 ? p1 : p0), a, static_cast<const R*>(L.gdev));
+        else
+            hipLaunchKernelGGL((k_mfma3<R, K, 4>), g, dim3(256), 0, s, static_cast<R*>(p0),
+                               static_cast<R*>(p1 ? p1 : p0), a, static_cast<const R*>(L.gdev));
+        return hipGetLastError();
     }
     dim3 grid((unsigned)L.ntiles, p1 ? 2 : 1);
     if (L.mfma3)

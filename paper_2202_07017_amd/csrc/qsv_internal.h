@@ -68,6 +68,7 @@ struct GateLaunch {
     int tloc[5] = {};
     int floc[6] = {};
     int mfma3 = 1;           // mfma: three-product kernel (0: real-embedding kernel)
+    int mfma_tpb = 1;        // mfma: consecutive tiles per workgroup (1, 2 or 4)
     // diagonal run: amplitude i is multiplied by entry tau_f(i) of factor f's
     // table for every factor f with (i & run_fix[f]) == run_val[f]; tau_f bit j
     // = bit run_tpos[f][j] of i (run_nt[f] <= 5 varying bits).  The tables

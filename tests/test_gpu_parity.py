@@ -160,7 +160,8 @@ def test_diagonal_gates(q, orc):
 @pytest.mark.parametrize("n", [10, 11, 12, 14])
 def test_four_and_five_qubit_gates(q, orc, n):
     """k = 4, 5: matrix cores (uncontrolled, n >= k + 6) in both product
-    forms (three real products and one real-embedded product), and the VALU
+    forms (three real products, with the tiles per workgroup the host picks
+    and forced to 1, 2 and 4, and one real-embedded product), and the VALU
     path."""
     rng = np.random.default_rng(200 + n)
     for name in DTYPES:
@@ -171,11 +172,14 @@ def test_four_and_five_qubit_gates(q, orc, n):
                       tuple(int(v) for v in rng.choice(n, k, replace=False))]
             for t in places:
                 G = W.haar_unitary(rng, 2 ** k)
-                for path in ["3m", "real", "valu"]:
+                for path in ["3m", "3m/1", "3m/2", "3m/4", "real", "valu"]:
                     os.environ["QSV_NO_MFMA"] = "1" if path == "valu" else "0"
-                    os.environ["QSV_MFMA_FORM"] = path
+                    os.environ["QSV_MFMA_FORM"] = path.split("/")[0]
+                    if "/" in path:
+                        os.environ["QSV_MFMA_TPB"] = path.split("/")[1]
                     say("k45", name, n, t, path)
                     gate_case(q, orc, psi, name, t, (), G)
+                    os.environ.pop("QSV_MFMA_TPB", None)
                 os.environ.pop("QSV_MFMA_FORM", None)
                 ctl = [v for v in range(n) if v not in t][:1]
                 say("k45 controlled", name, n, t, ctl)
