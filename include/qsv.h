@@ -55,7 +55,15 @@
  *    QSV_MFMA_FORM=3m|real      matrix-core blocks as three real products (Gauss)
  *                               or one real-embedded product (default: three
  *                               products)
+ *    QSV_MFMA_TPB=1|2|4         consecutive tiles per workgroup of the three-
+ *                               product kernel (default: 4 at k = 5; at k = 4
+ *                               2 for targets within 8 qubits, else 1)
  *    QSV_NO_DIAG_RUN=1          plans keep consecutive diagonal gates as separate launches
+ *    QSV_EXPECT_PLAN=reg|span   expectation values through register passes (with
+ *                               LDS-tile or span passes for the rest) or span
+ *                               passes alone (default: the cheaper plan)
+ *    QSV_NO_SPAN_PASS=1         expectation strings no tile holds take one pass
+ *                               per x mask instead of span passes
  *    QSV_NO_TILES=1             per-gate adjoint instead of cache-blocked tile programs
  *    QSV_NO_LANE_SWEEP=1        no cross-lane exchange for low single-qubit targets
  *    QSV_SWEEP_NT=0|1           force the nontemporal hint of sweeps off or on
