@@ -298,18 +298,44 @@ __global__ void __launch_bounds__(256) k_marginal_lanes(const R* __restrict__ ps
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         uint64_t j = 0;
         if (live) {
-            for (; j + 4 <= iters; j += 4) {
-                const uint64_t x1 = masked_add(x, d, G.uhi);
-                const uint64_t x2 = masked_add(x1, d, G.uhi);
-                const uint64_t x3 = masked_add(x2, d, G.uhi);
-                a0 += prob(psi, base | x);
-                a1 += prob(psi, base | x1);
-                a2 += prob(psi, base | x2);
-                a3 += prob(psi, base | x3);
-                x = masked_add(x3, d, G.uhi);
+            // four steps per round; the next round's four loads are issued
+            // before this round's squares are added (software pipeline), the
+            // additions keep the same order
+            using T = typename A2<R>::T;
+            const T* p = reinterpret_cast<const T*>(psi);
+            auto sq = [](const T& a) {
+                const double re = (double)a.x, im = (double)a.y;
+                return re * re + im * im;
+            };
+            if (iters >= 4) {
+                T c[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    c[u] = p[base | x];
+                    x = masked_add(x, d, G.uhi);
+                }
+                for (j = 4; j + 4 <= iters; j += 4) {
+                    T nx[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        nx[u] = p[base | x];
+                        x = masked_add(x, d, G.uhi);
+                    }
+                    a0 += sq(c[0]);
+                    a1 += sq(c[1]);
+                    a2 += sq(c[2]);
+                    a3 += sq(c[3]);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        c[u] = nx[u];
+                }
+                a0 += sq(c[0]);
+                a1 += sq(c[1]);
+                a2 += sq(c[2]);
+                a3 += sq(c[3]);
             }
             for (; j < iters; ++j) {
-                a0 += prob(psi, base | x);
+                a0 += sq(p[base | x]);
                 x = masked_add(x, d, G.uhi);
             }
         }
