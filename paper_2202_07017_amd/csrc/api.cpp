@@ -360,9 +360,9 @@ Built build_launch(int n, int dt, const int* ct, int k, const int* ctl, int c, c
         L.ins = make_ins(B, 0);
         L.ntiles = 1ull << (n - k - 6);
         L.ngroups = L.ntiles;
-        // Three-product kernel by default (complex128 k = 5 with two tiles
-        // per workgroup: with one it ran 6-10% slower than the real
-        // embedding, with two 0-7% faster, measured); QSV_MFMA_FORM=real
+        // Three-product kernel by default (complex128 k = 5 with one tile per
+        // workgroup ran 6-10% slower than the real embedding, with two 0-7%
+        // faster and with four faster still, measured); QSV_MFMA_FORM=real
         // selects the embedding.
         const char* form = std::getenv("QSV_MFMA_FORM");
         L.mfma3 = 1;
@@ -378,8 +378,13 @@ Built build_launch(int n, int dt, const int* ct, int k, const int* ctl, int c, c
         // targets lie in a window of 8 qubits (1-5% faster) and one
         // otherwise (the prefetch then costs about as much as it hides).
         // QSV_MFMA_TPB=1|2|4 forces a count (comparisons).
+        // Small states keep at least 2048 workgroups (eight per CU): at n = 20
+        // four tiles per workgroup left 128 of them and the fused U(2)+CZ
+        // circuit ran 0.34 -> 0.43 ms.
         const int span = *std::max_element(tgt.begin(), tgt.end()) - *std::min_element(tgt.begin(), tgt.end());
         L.mfma_tpb = k == 5 ? 4 : (span < 2 * k ? 2 : 1);
+        while (L.mfma_tpb > 1 && L.ntiles / (uint64_t)L.mfma_tpb < 2048)
+            L.mfma_tpb /= 2;
         if (const char* e = std::getenv("QSV_MFMA_TPB")) {
             const int v = std::atoi(e);
             if (v == 1 || v == 2 || v == 4)
