@@ -232,7 +232,8 @@ qsv_status qsv_apply_pauli_sum(const void* psi, void* out, int n, qsv_dtype dt,
  * the state's own norm is the total mass.  Weights and sums are FP64. */
 
 /* Size in bytes of the scratch buffer qsv_probabilities and qsv_sample need
- * for an n-qubit state (about 2^(n-10) doubles; 8 MiB at n = 30). */
+ * for an n-qubit state (about 2^(n-8) doubles, at least 8 MiB; 32 MiB at
+ * n = 30). */
 qsv_status qsv_measure_workspace_bytes(int n, qsv_dtype dt, size_t* bytes);
 
 /* Marginal distribution of the m distinct qubits qubits[0..m-1] (host array,

@@ -6,10 +6,10 @@
 //
 // Sampling keeps no probability vector.  One streaming pass writes a sum
 // tree into the workspace: level 0 holds the sums of chunks of 2^cb
-// consecutive amplitudes (cb = min(n, 10)), level L + 1 the sums of 64
+// consecutive amplitudes (cb = min(n, 8)), level L + 1 the sums of 64
 // consecutive level-L entries, up to a top level of at most 64 entries.
 // A shot descends the tree one wave-wide 64-way choice per level and
-// resolves the outcome inside one chunk (one 8 or 16 KiB read).
+// resolves the outcome inside one chunk (one 2 or 4 KiB read).
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -18,6 +18,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kPrepThreads = 1024;       // 16 waves per group block
+constexpr int kChunkLog = 8;             // log2(amplitudes per sampling leaf chunk)
 constexpr int kMargItemsLog = 16;        // log2(wave items targeted by the marginal pass)
 constexpr int kMargPartLog = 20;         // log2(doubles of per-slice partial sums)
 
@@ -121,15 +122,25 @@ __global__ void __launch_bounds__(kPrepThreads) k_sample_prep(const R* __restric
     const int G = 1 << gb;
     const uint64_t nvec = sizeof(R) == 4 ? (1ull << cb) / 2 : (1ull << cb);
     const uint64_t grp = blockIdx.x;
-    for (int c = wave; c < G; c += kPrepThreads / kWave) {
-        const uint64_t v0 = ((grp << gb) + (uint64_t)c) * nvec;
-        double s = 0.0;
-#pragma unroll 8
-        for (uint64_t v = lane; v < nvec; v += kWave)
-            s += prob16(psi, v0 + v);
-        s = wave_sum(s);
-        if (lane == 0)
-            csum[c] = s;
+    // a wave's chunks (at most four: G <= 64 chunks over 16 waves) are read
+    // side by side, so all of their loads are in flight together; each
+    // chunk's sum keeps its index order
+    constexpr int NW = kPrepThreads / kWave;
+    static_assert(NW * 4 >= kWave, "four chunks per wave cover a group of 64");
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint64_t v = lane; v < nvec; v += kWave)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = wave + j * NW;
+            if (c < G)
+                s[j] += prob16(psi, ((grp << gb) + (uint64_t)c) * nvec + v);
+        }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = wave + j * NW;
+        const double t = wave_sum(s[j]);
+        if (c < G && lane == 0)
+            csum[c] = t;
     }
     __syncthreads();
     if (wave == 0) {
@@ -448,7 +459,7 @@ __global__ void __launch_bounds__(256) k_collapse(R* __restrict__ psi, uint64_t 
 SampleTree sample_tree(int n)
 {
     SampleTree tr{};
-    tr.cb = n < 10 ? n : 10;
+    tr.cb = n < kChunkLog ? n : kChunkLog;
     uint64_t c = 1ull << (n - tr.cb);
     uint64_t off = 0;
     for (;;) {
