@@ -59,6 +59,8 @@
  *                               product kernel (default: 4 at k = 5; at k = 4
  *                               2 for targets within 8 qubits, else 1)
  *    QSV_NO_DIAG_RUN=1          plans keep consecutive diagonal gates as separate launches
+ *    QSV_NO_SWAP_MERGE=1        plans keep consecutive SWAP gates as separate launches
+ *                               instead of qubit permutation passes
  *    QSV_EXPECT_PLAN=reg|span   expectation values through register passes (with
  *                               LDS-tile or span passes for the rest) or span
  *                               passes alone (default: the cheaper plan)

@@ -236,6 +236,10 @@ Built build_launch(int n, int dt, const int* ct, int k, const int* ctl, int c, c
                 ++m;
             }
         L.nmoved = m;
+        if (k == 2 && c == 0 && src[0] == 0 && src[1] == 2 && src[2] == 1 && src[3] == 3) {
+            L.swapq[0] = ct[0];
+            L.swapq[1] = ct[1];
+        }
         const double groups = std::ldexp(1.0, n - k - c);
         L.bytes = 2.0 * S * groups * m;
         return b;
@@ -565,6 +569,8 @@ qsv_status launch_checked(const GateLaunch& L, void* psi, void* psi2, hipStream_
     hipError_t e;
     if (L.type == L_DIAGRUN)
         e = psi2 ? hipErrorInvalidValue : launch_diag_run(L, psi, s);
+    else if (L.type == L_QPERM)
+        e = launch_qperm(L, psi, psi2, s);
     else
         e = launch_gate(L, psi, psi2, s);
     if (e != hipSuccess)

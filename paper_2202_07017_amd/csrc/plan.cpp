@@ -11,6 +11,7 @@
 
 #include "qsv.h"
 #include "qsv_host.h"
+#include "qsv_qperm_plan.h"
 #include "qsv_internal.h"
 #include "qsv_tileprog.h"
 #include "qsv_tpass.h"
@@ -386,6 +387,76 @@ void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& up
     upload_off.swap(offs);
 }
 
+// A SWAP moves the half of the state whose two bits differ; when the lower
+// qubit is below 4 its moved amplitudes share 128-byte lines with unmoved
+// ones, so it costs a full sweep.  A run of consecutive SWAPs composes into
+// one bit permutation, applied by qubit permutation passes of one full sweep
+// each; the run is replaced when that is cheaper.
+void merge_swaps(std::vector<GateLaunch>& Ls, std::vector<long long>& upload_off, int n, int dt)
+{
+    const int rl = dt == C64 ? kQpRowBitsC64 : kQpRowBitsC128;
+    if (n < 2 * rl)
+        return;
+    std::vector<GateLaunch> out;
+    std::vector<long long> offs;
+    size_t j = 0;
+    while (j < Ls.size()) {
+        if (Ls[j].type != L_PERM || Ls[j].swapq[0] < 0) {
+            out.push_back(Ls[j]);
+            offs.push_back(upload_off[j]);
+            ++j;
+            continue;
+        }
+        size_t e = j;
+        std::vector<std::pair<int, int>> sw;
+        double sep = 0.0;
+        uint64_t qm = 0;
+        for (; e < Ls.size() && Ls[e].type == L_PERM && Ls[e].swapq[0] >= 0; ++e) {
+            const int a = Ls[e].swapq[0], b = Ls[e].swapq[1];
+            sw.push_back({a, b});
+            sep += std::min(a, b) < 4 ? 1.0 : 0.5;
+            qm |= (1ull << a) | (1ull << b);
+        }
+        std::vector<QPermPass> passes;
+        plan_qubit_permutation(compose_swaps(sw, n), n, rl, passes);
+        if ((double)passes.size() < sep) {
+            for (const QPermPass& P : passes) {
+                GateLaunch R{};
+                R.type = L_QPERM;
+                R.dt = dt;
+                R.n = n;
+                R.ngroups = P.ntiles;
+                R.qp_rl = P.rl;
+                R.qp_hb = P.hb;
+                std::vector<int> tpos;
+                for (int k = 0; k < P.rl; ++k)
+                    tpos.push_back(k);
+                for (int k = 0; k < P.hb; ++k) {
+                    R.qp_hpos[k] = P.hpos[k];
+                    tpos.push_back(P.hpos[k]);
+                }
+                for (int k = 0; k < P.rl + P.hb; ++k)
+                    R.qp_cmap[k] = P.cmap[k];
+                for (int b = 0; b < n; ++b)
+                    R.qp_q[b] = P.q[b];
+                R.ins = make_ins(tpos, 0);
+                R.qmask = qm;
+                R.bytes = 2.0 * amp_bytes(dt) * std::ldexp(1.0, n);
+                out.push_back(R);
+                offs.push_back(-1);
+            }
+        } else {
+            for (size_t k = j; k < e; ++k) {
+                out.push_back(Ls[k]);
+                offs.push_back(upload_off[k]);
+            }
+        }
+        j = e;
+    }
+    Ls.swap(out);
+    upload_off.swap(offs);
+}
+
 }  // namespace qsv
 
 // ================================================================= plans
@@ -470,6 +541,9 @@ qsv_status build_plan(const qsv_circuit* circ, int dt, int fuse_k, const double*
         P->upload_off.push_back(b.upload.empty() ? -1 : (long long)P->dev.add(std::move(b.upload)));
         P->launches.push_back(b.L);
     }
+    const char* nosw = getenv("QSV_NO_SWAP_MERGE");
+    if (!nosw || nosw[0] != '1')
+        merge_swaps(P->launches, P->upload_off, P->n, dt);
     const char* nodr = getenv("QSV_NO_DIAG_RUN");
     if (!nodr || nodr[0] != '1') {
         merge_diagonal_runs(P->launches, P->upload_off, P->n, dt);

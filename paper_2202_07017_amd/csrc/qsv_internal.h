@@ -24,7 +24,7 @@ enum Dt : int { C64 = 1, C128 = 2 };
 //          of the same group.
 enum Mode : int { W1 = 0, W2 = 1, INTRA = 2 };
 
-enum LaunchType : int { L_DENSE = 0, L_DIAG = 1, L_PERM = 2, L_MFMA = 3, L_DIAGRUN = 4 };
+enum LaunchType : int { L_DENSE = 0, L_DIAG = 1, L_PERM = 2, L_MFMA = 3, L_DIAGRUN = 4, L_QPERM = 5 };
 
 constexpr int kMaxRunFactors = 16;  // diagonal gates merged into one L_DIAGRUN sweep
 constexpr int kMaxRunEntries = kMaxRunFactors * 32;  // table entries of one run
@@ -81,6 +81,19 @@ struct GateLaunch {
     int run_tpos[kMaxRunFactors][5] = {};
     int run_off[kMaxRunFactors] = {};
     std::vector<double> run_tab;
+    // perm: the two qubits of an uncontrolled SWAP (-1: another permutation)
+    int swapq[2] = {-1, -1};
+    // qubit permutation pass: output amplitude j takes input amplitude i with
+    // bit b of i = bit qp_q[b] of j (an involution); tiles of rows of 2^qp_rl
+    // amplitudes at the offsets of the qp_hb tile bits qp_hpos (ascending),
+    // zeros inserted at the tile bits by `ins`, one tile (or a tile and its
+    // image) per workgroup, ngroups tiles; qp_cmap[k] is the tile-local bit of
+    // the output that lands on tile-local bit k of the source.
+    int qp_rl = 0;
+    int qp_hb = 0;
+    int qp_hpos[6] = {};
+    int qp_cmap[12] = {};
+    int qp_q[64] = {};
     uint64_t qmask = ~0ull;  // every qubit the launch reads or writes (targets and controls)
     // accounting
     double bytes = 0.0;
@@ -92,6 +105,17 @@ struct GateLaunch {
 // bits each) into L_DIAGRUN sweeps where a full sweep is cheaper than the
 // separate launches' estimated traffic.
 void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& upload_off, int n, int dt);
+
+// Compose runs of consecutive SWAP launches into qubit permutation passes
+// (L_QPERM, one or two per run) where that moves fewer bytes.
+void merge_swaps(std::vector<GateLaunch>& Ls, std::vector<long long>& upload_off, int n, int dt);
+
+// Row bits of the qubit permutation tiles: 512-byte rows in both precisions.
+constexpr int kQpRowBitsC64 = 6;
+constexpr int kQpRowBitsC128 = 5;
+
+// kernels_qperm.hip (L_QPERM launches; psi2 may be NULL)
+hipError_t launch_qperm(const GateLaunch& L, void* psi, void* psi2, hipStream_t s);
 
 // kernels_diagrun.hip (L_DIAGRUN launches)
 hipError_t launch_diag_run(const GateLaunch& L, void* psi, hipStream_t s);

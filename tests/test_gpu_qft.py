@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import TOL, rand_state, say, to_gpu, to_np, torch_dtype
+from gpu_util import TOL, rand_state, raw_bits, say, to_gpu, to_np, torch_dtype
 
 pytestmark = pytest.mark.gpu
 DTYPES = ("c128", "c64")
@@ -118,5 +118,68 @@ def test_diagonal_runs(q, orc, name, n, fuse):
     assert np.max(np.abs(got - ref)) <= TOL[name] * scale, np.max(np.abs(got - ref))
     assert np.max(np.abs(to_np(d2) - ref)) <= TOL[name] * scale
     if n >= 7 and fuse == 1:
+        assert merged.info()[0] < plain.info()[0], (merged.info(), plain.info())
+    assert merged.info()[0] <= plain.info()[0]
+
+
+def _swap_circuit(n, kind, seed):
+    """Runs of SWAP gates: the bit reversal that closes the QFT, random swaps
+    that chain into long cycles (two passes), swaps among qubits 0..5 only,
+    among high qubits only, swaps that cancel, and runs cut by Hadamards."""
+    rng = np.random.default_rng(seed)
+    c = W.Circuit(n)
+    if kind == "reverse":
+        pairs = [(b, n - 1 - b) for b in range(n // 2)]
+    elif kind == "random":
+        pairs = [tuple(int(v) for v in rng.permutation(n)[:2]) for _ in range(2 * n)]
+    elif kind == "low":
+        pairs = [(0, 5), (1, 4), (2, 3), (0, 1)]
+    elif kind == "high":
+        pairs = [(n - 1, n - 3), (n - 2, n - 5), (n - 4, n - 6), (n - 1, n - 2)]
+    elif kind == "cancel":
+        pairs = [(1, n - 2), (3, 7), (3, 7), (1, n - 2)]
+    else:  # "cut": three runs separated by Hadamards
+        pairs = []
+        for r in range(3):
+            for _ in range(4):
+                c.ops.append(W.Op("swap", tuple(int(v) for v in rng.permutation(n)[:2])))
+            c.ops.append(W.Op("h", (int(rng.integers(0, n)),)))
+        return c
+    for a, b in pairs:
+        c.ops.append(W.Op("swap", (a, b)))
+    return c
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("n", [12, 13, 17, 20])
+@pytest.mark.parametrize("kind", ["reverse", "random", "low", "high", "cancel", "cut"])
+def test_swap_runs(q, orc, name, n, kind):
+    """Plans compose runs of consecutive swaps into qubit permutation passes
+    (moves of raw bits): the result equals the oracle's gate-by-gate swaps
+    exactly, and equals the plan that keeps the swaps separate bit for bit."""
+    import os
+    circ = _swap_circuit(n, kind, 900 + n)
+    rng = np.random.default_rng(n)
+    psi = rand_state(n, rng, name)
+    if name == "c64":
+        psi[3] = -0.0  # a signed zero survives moves
+    ref = orc.run(circ, psi0=psi)
+    say("swap runs", name, n, kind)
+    d = to_gpu(psi, name)
+    merged = q.Plan(circ, _code(q, name), 1)
+    merged.run(d)
+    os.environ["QSV_NO_SWAP_MERGE"] = "1"
+    try:
+        plain = q.Plan(circ, _code(q, name), 1)
+    finally:
+        del os.environ["QSV_NO_SWAP_MERGE"]
+    d2 = to_gpu(psi, name)
+    plain.run(d2)
+    if kind != "cut":
+        assert np.array_equal(to_np(d), ref)
+    else:
+        assert np.max(np.abs(to_np(d) - ref)) <= TOL[name]
+    assert np.array_equal(raw_bits(d.cpu().numpy()), raw_bits(d2.cpu().numpy()))
+    if kind in ("reverse", "random", "cancel"):
         assert merged.info()[0] < plain.info()[0], (merged.info(), plain.info())
     assert merged.info()[0] <= plain.info()[0]
