@@ -31,9 +31,9 @@ def checker(tmp_path_factory):
     return build_checker(str(tmp_path_factory.mktemp("qperm") / "qperm_check"))
 
 
-def run(checker, n, rl, swaps):
+def run(checker, n, rl, swaps, env=None):
     text = "%d %d %d\n" % (n, rl, len(swaps)) + "".join("%d %d\n" % s for s in swaps)
-    p = subprocess.run([checker], input=text, capture_output=True, text=True)
+    p = subprocess.run([checker], input=text, capture_output=True, text=True, env=env)
     assert p.returncode == 0, p.stderr
     assert "runtime error" not in p.stderr and "Sanitizer" not in p.stderr, p.stderr
     return int(p.stdout.split()[1])

@@ -5,7 +5,9 @@ tests/oracle_sanitize_check.c, the tile-program compiler of the library
 (paper_2202_07017_amd/csrc/tileprog.cpp) through tests/tileprog_check.cpp on
 random gate lists, and the register-pass planner (csrc/rpass_plan.cpp)
 through tests/rpass_check.cpp on mixed Pauli sums, the span-pass planner
-(csrc/span_plan.cpp) through tests/span_check.cpp; all are built with g++/gcc and
+(csrc/span_plan.cpp) through tests/span_check.cpp, the qubit permutation
+planner (csrc/qperm_plan.cpp) through tests/qperm_check.cpp on swap runs; all
+are built with g++/gcc and
 -fsanitize=address,undefined -fno-sanitize-recover=all, so any out-of-bounds
 access, use after free, leak or undefined behaviour aborts the run.  The
 GPU code is not built here (GPU sanitizers are not available)."""
@@ -94,3 +96,14 @@ def test_span_pass_planner_under_sanitizers(orc, tmp_path):
         psi = orc.random_state(n, 55 + n)
         _, e_span = run_span(exe, H, psi, tmp_path, env=ENV)
         assert abs(e_span - orc.expect(psi, H).real) <= 1e-12 * float(np.sum(np.abs(H.coeff)))
+
+
+def test_qubit_permutation_planner_under_sanitizers(tmp_path):
+    from test_qperm_plan import build_checker, reversal
+    from test_qperm_plan import run as run_qperm
+    exe = build_checker(str(tmp_path / "qperm_check"), SAN)
+    rng = np.random.default_rng(8)
+    for n, rl in ((12, 6), (13, 5), (14, 6)):
+        assert run_qperm(exe, n, rl, reversal(n), env=ENV) == 1
+        swaps = [tuple(int(v) for v in rng.permutation(n)[:2]) for _ in range(3 * n)]
+        assert run_qperm(exe, n, rl, swaps, env=ENV) in (0, 1, 2)
