@@ -2,7 +2,10 @@
 // sweep.  Diagonal matrices commute with each other, so the run's product
 // does not depend on the order of its factors; plans build runs from
 // consecutive diagonal gates (moving gates on other qubits ahead of them).
+#include <algorithm>
 #include <cmath>
+#include <utility>
+#include <vector>
 #include <cstdlib>
 
 #include "qsv_internal.h"
@@ -49,14 +52,16 @@ __device__ __forceinline__ void st_nt(double2* p, double2 v)
 
 // A run of diagonal gates applied in one sweep (diagonal matrices commute, so
 // the product's order is free): amplitude i is multiplied by d_f[tau_f(i)]
-// for every factor f whose fixed bits match.
+// for every factor f whose fixed bits match.  Factors are ordered by the
+// varying bits (below) they read: [0, boff[0]) none, [boff[j], boff[j+1])
+// only varying bit j, [boff[NV], nf) two or more.
 template <typename R>
 struct DiagRunK {
     uint64_t nunits;  // 16-byte units of the state
     int nf;
+    int boff[6];
     uint64_t fix[kMaxRunFactors];
     uint64_t val[kMaxRunFactors];
-    uint64_t dep[kMaxRunFactors];  // every bit the factor reads (fixed and varying)
     int nt[kMaxRunFactors];
     int tpos[kMaxRunFactors][5];
     int off[kMaxRunFactors];       // first complex entry of the factor's table
@@ -82,16 +87,38 @@ __device__ __forceinline__ void run_factor(const DiagRunK<R>& a, const R* sd, in
 }
 
 // Each thread takes kRunUPT units kBlock apart (coalesced across the block),
-// so only unit bits 8..11 (and, for complex64, amplitude bit 0) vary across a
-// thread's amplitudes: factors that depend on none of those bits are
-// evaluated once per thread, the others once per amplitude.
+// so only NV index bits vary over its amplitudes: unit bits 8..11 and, in
+// complex64, amplitude bit 0 (the two amplitudes of a 16-byte unit).  The
+// thread builds the run's product for every value v of those bits, a table
+// T[v] of 2^NV entries in registers: factors that read no varying bit are
+// evaluated once; a factor that reads only varying bit j contributes
+// h_j(v_j), evaluated at both values, and the table is built by doubling
+// over j; factors that read several varying bits are evaluated per entry.
+// The sweep then multiplies each amplitude by its entry.  A long ladder of
+// controlled phases on one of the varying bits costs two evaluations per
+// factor and thread instead of one per factor and amplitude.
 constexpr int kRunUPT = 16;
+
+template <typename R>
+struct RunVary;
+template <>
+struct RunVary<float> {
+    static constexpr int NV = 5;
+    // amplitude index bit of varying bit j: amplitude bit 0, then unit bits 8..11
+    __device__ static constexpr int bit(int j) { return j == 0 ? 0 : 8 + j; }
+};
+template <>
+struct RunVary<double> {
+    static constexpr int NV = 4;
+    __device__ static constexpr int bit(int j) { return 8 + j; }
+};
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const DiagRunK<R> a)
 {
     constexpr int AS = sizeof(R) == 4 ? 1 : 0;  // amplitude index = unit << AS
-    const uint64_t vary = (sizeof(R) == 4 ? 1ull : 0ull) | ((uint64_t)(kRunUPT - 1) << (8 + AS));
+    constexpr int NV = RunVary<R>::NV;
+    constexpr int NT = 1 << NV;
     const uint64_t seglen = (uint64_t)kBlock * kRunUPT;
     const uint64_t nseg = (a.nunits + seglen - 1) / seglen;
     __shared__ R sd[2 * kMaxRunEntries];
@@ -100,10 +127,40 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
     __syncthreads();
     for (uint64_t seg = xcd_block(); seg < nseg; seg += gridDim.x) {
         const uint64_t u0 = seg * seglen + threadIdx.x;
-        R cr = (R)1, ci = (R)0;
-        for (int f = 0; f < a.nf; ++f)
-            if (!(a.dep[f] & vary))
-                run_factor(a, sd, f, u0 << AS, cr, ci);
+        const uint64_t i0 = u0 << AS;  // varying bits zero
+        R tr[NT], ti[NT];
+        tr[0] = (R)1;
+        ti[0] = (R)0;
+        for (int f = 0; f < a.boff[0]; ++f)
+            run_factor(a, sd, f, i0, tr[0], ti[0]);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const uint64_t bj = 1ull << RunVary<R>::bit(j);
+            R h0r = (R)1, h0i = (R)0, h1r = (R)1, h1i = (R)0;
+            for (int f = a.boff[j]; f < a.boff[j + 1]; ++f) {
+                run_factor(a, sd, f, i0, h0r, h0i);
+                run_factor(a, sd, f, i0 | bj, h1r, h1i);
+            }
+#pragma unroll
+            for (int v = 0; v < (1 << j); ++v) {
+                const R xr = tr[v], xi = ti[v];
+                tr[v + (1 << j)] = xr * h1r - xi * h1i;
+                ti[v + (1 << j)] = xr * h1i + xi * h1r;
+                tr[v] = xr * h0r - xi * h0i;
+                ti[v] = xr * h0i + xi * h0r;
+            }
+        }
+        for (int f = a.boff[NV]; f < a.nf; ++f)
+#pragma unroll
+            for (int v = 0; v < NT; ++v) {
+                uint64_t iv = i0;
+#pragma unroll
+                for (int j = 0; j < NV; ++j)
+                    if ((v >> j) & 1)
+                        iv |= 1ull << RunVary<R>::bit(j);
+                run_factor(a, sd, f, iv, tr[v], ti[v]);
+            }
+#pragma unroll
         for (int r = 0; r < kRunUPT; ++r) {
             const uint64_t u = u0 + (uint64_t)r * kBlock;
             if (u >= a.nunits)
@@ -111,22 +168,13 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
             if constexpr (sizeof(R) == 4) {
                 float4* p = reinterpret_cast<float4*>(psi);
                 const float4 x = ld_nt(&p[u]);
-                float ar = cr, ai = ci, br = cr, bi = ci;
-                for (int f = 0; f < a.nf; ++f)
-                    if (a.dep[f] & vary) {
-                        run_factor(a, sd, f, u << 1, ar, ai);
-                        run_factor(a, sd, f, (u << 1) | 1u, br, bi);
-                    }
+                const float ar = tr[2 * r], ai = ti[2 * r], br = tr[2 * r + 1], bi = ti[2 * r + 1];
                 st_nt(&p[u], make_float4(ar * x.x - ai * x.y, ar * x.y + ai * x.x, br * x.z - bi * x.w,
                                            br * x.w + bi * x.z));
             } else {
                 double2* p = reinterpret_cast<double2*>(psi);
                 const double2 x = ld_nt(&p[u]);
-                double ar = cr, ai = ci;
-                for (int f = 0; f < a.nf; ++f)
-                    if (a.dep[f] & vary)
-                        run_factor(a, sd, f, u, ar, ai);
-                st_nt(&p[u], make_double2(ar * x.x - ai * x.y, ar * x.y + ai * x.x));
+                st_nt(&p[u], make_double2(tr[r] * x.x - ti[r] * x.y, tr[r] * x.y + ti[r] * x.x));
             }
         }
     }
@@ -145,19 +193,43 @@ inline unsigned run_grid(uint64_t units)
 template <typename R>
 hipError_t diag_run_go(const GateLaunch& L, void* p, hipStream_t s)
 {
+    constexpr int NV = RunVary<R>::NV;
+    // order the factors by the varying bits they read (see DiagRunK)
+    uint64_t vmask[NV];
+    for (int j = 0; j < NV; ++j)
+        vmask[j] = 1ull << (sizeof(R) == 4 ? (j == 0 ? 0 : 8 + j) : 8 + j);
+    std::vector<std::pair<int, int>> order;  // (class, factor)
+    for (int f = 0; f < L.run_nf; ++f) {
+        uint64_t dep = L.run_fix[f];
+        for (int b = 0; b < L.run_nt[f]; ++b)
+            dep |= 1ull << L.run_tpos[f][b];
+        int cls = 0, nread = 0;
+        for (int j = 0; j < NV; ++j)
+            if (dep & vmask[j]) {
+                cls = j + 1;
+                ++nread;
+            }
+        order.push_back({nread >= 2 ? NV + 1 : cls, f});
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.first < y.first; });
     DiagRunK<R> a{};
     a.nunits = L.ngroups;
     a.nf = L.run_nf;
-    for (int f = 0; f < L.run_nf; ++f) {
-        a.fix[f] = L.run_fix[f];
-        a.val[f] = L.run_val[f];
-        a.nt[f] = L.run_nt[f];
-        a.off[f] = L.run_off[f];
-        a.dep[f] = L.run_fix[f];
-        for (int b = 0; b < L.run_nt[f]; ++b) {
-            a.tpos[f][b] = L.run_tpos[f][b];
-            a.dep[f] |= 1ull << L.run_tpos[f][b];
-        }
+    for (int k = 0; k < L.run_nf; ++k) {
+        const int f = order[k].second;
+        a.fix[k] = L.run_fix[f];
+        a.val[k] = L.run_val[f];
+        a.nt[k] = L.run_nt[f];
+        a.off[k] = L.run_off[f];
+        for (int b = 0; b < L.run_nt[f]; ++b)
+            a.tpos[k][b] = L.run_tpos[f][b];
+    }
+    for (int j = 0; j <= NV; ++j) {
+        int c = 0;
+        while (c < L.run_nf && order[c].first <= j)
+            ++c;
+        a.boff[j] = c;  // factors of class <= j come first
     }
     a.tab = static_cast<const R*>(L.gdev);
     a.ntab = (int)(L.run_tab.size() / 2);
