@@ -65,6 +65,14 @@ struct DiagRunK {
     int nt[kMaxRunFactors];
     int tpos[kMaxRunFactors][5];
     int off[kMaxRunFactors];       // first complex entry of the factor's table
+    // factors on several varying bits: fixed bits outside the varying bits
+    // (matched once per thread), fixed varying bits as a mask over v, and the
+    // table index bit that each varying bit sets
+    uint64_t fixn[kMaxRunFactors];
+    uint64_t valn[kMaxRunFactors];
+    int fixv[kMaxRunFactors];
+    int valv[kMaxRunFactors];
+    int tvb[kMaxRunFactors][5];
     const R* tab;                  // all tables, (re, im), state precision
     int ntab;                      // complex entries in tab
 };
@@ -150,16 +158,27 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
                 ti[v] = xr * h0i + xi * h0r;
             }
         }
-        for (int f = a.boff[NV]; f < a.nf; ++f)
+        for (int f = a.boff[NV]; f < a.nf; ++f) {
+            if ((i0 & a.fixn[f]) != a.valn[f])
+                continue;
+            int t0 = 0;  // table index from the thread's fixed bits (varying bits of i0 are 0)
+            for (int b = 0; b < a.nt[f]; ++b)
+                t0 |= (int)((i0 >> a.tpos[f][b]) & 1u) << b;
+            const R* e = sd + 2 * a.off[f];
 #pragma unroll
             for (int v = 0; v < NT; ++v) {
-                uint64_t iv = i0;
+                int t = t0;
 #pragma unroll
                 for (int j = 0; j < NV; ++j)
                     if ((v >> j) & 1)
-                        iv |= 1ull << RunVary<R>::bit(j);
-                run_factor(a, sd, f, iv, tr[v], ti[v]);
+                        t |= a.tvb[f][j];
+                const bool hit = (v & a.fixv[f]) == a.valv[f];
+                const R dr = hit ? e[2 * t] : (R)1, di = hit ? e[2 * t + 1] : (R)0;
+                const R xr = tr[v], xi = ti[v];
+                tr[v] = xr * dr - xi * di;
+                ti[v] = xr * di + xi * dr;
             }
+        }
 #pragma unroll
         for (int r = 0; r < kRunUPT; ++r) {
             const uint64_t u = u0 + (uint64_t)r * kBlock;
@@ -224,6 +243,20 @@ hipError_t diag_run_go(const GateLaunch& L, void* p, hipStream_t s)
         a.off[k] = L.run_off[f];
         for (int b = 0; b < L.run_nt[f]; ++b)
             a.tpos[k][b] = L.run_tpos[f][b];
+        uint64_t vall = 0;
+        for (int j = 0; j < NV; ++j) {
+            vall |= vmask[j];
+            if (L.run_fix[f] & vmask[j]) {
+                a.fixv[k] |= 1 << j;
+                if (L.run_val[f] & vmask[j])
+                    a.valv[k] |= 1 << j;
+            }
+            for (int b = 0; b < L.run_nt[f]; ++b)
+                if (L.run_tpos[f][b] == __builtin_ctzll(vmask[j]))
+                    a.tvb[k][j] = 1 << b;
+        }
+        a.fixn[k] = L.run_fix[f] & ~vall;
+        a.valn[k] = L.run_val[f] & ~vall;
     }
     for (int j = 0; j <= NV; ++j) {
         int c = 0;
