@@ -61,6 +61,9 @@
  *    QSV_NO_DIAG_RUN=1          plans keep consecutive diagonal gates as separate launches
  *    QSV_NO_SWAP_MERGE=1        plans keep consecutive SWAP gates as separate launches
  *                               instead of qubit permutation passes
+ *    QSV_NO_DIAG_DEFER=1        fusion (fuse_k >= 3) closes blocks at diagonal gates that
+ *                               do not fit instead of deferring them past gates they
+ *                               commute with
  *    QSV_EXPECT_PLAN=reg|span   expectation values through register passes (with
  *                               LDS-tile or span passes for the rest) or span
  *                               passes alone (default: the cheaper plan)

@@ -94,11 +94,38 @@ struct Item {
     std::vector<int> qs;       // block qubits (ascending)
 };
 
+// Whether op's matrix is diagonal (controls keep it diagonal).
+static bool is_diagonal_op(const qsv_op& op)
+{
+    if (op.kind == QSV_OP_Z)
+        return true;
+    if (op.kind != QSV_OP_MATRIX || !op.M)
+        return false;
+    const int D = 1 << op.k;
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c)
+            if (r != c && (op.M[((size_t)r * D + c) * 2] != 0.0 || op.M[((size_t)r * D + c) * 2 + 1] != 0.0))
+                return false;
+    return true;
+}
+
 // Greedy DAG-aware fusion: each qubit is owned by at most one open block; a
 // gate joins (and merges) the open blocks owning its qubits when the union
 // has <= fuse_k qubits, otherwise those blocks are emitted.  Open blocks have
 // disjoint qubits, so their relative order is free.
-std::vector<Item> fuse_ops(const qsv_circuit* C, int fuse_k, bool rotations_standalone)
+//
+// With defer_diagonal (plans with fuse_k >= 3), a diagonal gate that does
+// not fit the blocks owning its qubits leaves them open and waits in a pool
+// instead: diagonal gates
+// commute with each other and with gates on other qubits, so the pool only
+// has to be applied before the next non-diagonal gate on one of its qubits
+// (and after the blocks that hold earlier gates on them).  That gate flushes
+// the pool: first the blocks owning pooled qubits, then the pooled gates
+// packed (first fit) into diagonal blocks of <= fuse_k qubits.  A QFT then
+// keeps its Hadamards and the phases among them in blocks of fuse_k qubits,
+// and the phases between blocks become a few diagonal blocks each.
+std::vector<Item> fuse_ops(const qsv_circuit* C, int fuse_k, bool rotations_standalone,
+                           bool defer_diagonal = false)
 {
     struct Blk {
         std::set<int> qs;
@@ -121,10 +148,51 @@ std::vector<Item> fuse_ops(const qsv_circuit* C, int fuse_k, bool rotations_stan
         it.qs.assign(B.qs.begin(), B.qs.end());
         out.push_back(it);
     };
+    std::vector<int> pool;  // deferred diagonal gates
+    std::vector<char> pooled(C->n, 0);
+    auto flush = [&]() {
+        if (pool.empty())
+            return;
+        for (int q = 0; q < C->n; ++q)
+            if (pooled[q] && owner[q] >= 0)
+                emit(owner[q]);
+        std::vector<Item> groups;
+        for (int o : pool) {
+            const qsv_op& op = C->ops[o];
+            std::set<int> Q(op.targets, op.targets + op.k);
+            Q.insert(op.controls, op.controls + op.c);
+            Item* g = nullptr;
+            for (Item& G : groups) {
+                std::set<int> U(G.qs.begin(), G.qs.end());
+                U.insert(Q.begin(), Q.end());
+                if ((int)U.size() <= fuse_k) {
+                    G.qs.assign(U.begin(), U.end());
+                    g = &G;
+                    break;
+                }
+            }
+            if (!g) {
+                groups.emplace_back();
+                g = &groups.back();
+                g->qs.assign(Q.begin(), Q.end());
+            }
+            g->ops.push_back(o);
+        }
+        out.insert(out.end(), groups.begin(), groups.end());
+        pool.clear();
+        std::fill(pooled.begin(), pooled.end(), 0);
+    };
     for (int o = 0; o < C->nops; ++o) {
         const qsv_op& op = C->ops[o];
         std::vector<int> Q(op.targets, op.targets + op.k);
         Q.insert(Q.end(), op.controls, op.controls + op.c);
+        const bool diag = defer_diagonal && !is_rotation(op.kind) && is_diagonal_op(op);
+        if (!pool.empty() && !diag)
+            for (int q : Q)
+                if (pooled[q]) {
+                    flush();
+                    break;
+                }
         std::set<int> owners;
         for (int q : Q)
             if (owner[q] >= 0)
@@ -141,6 +209,12 @@ std::vector<Item> fuse_ops(const qsv_circuit* C, int fuse_k, bool rotations_stan
         std::set<int> U(Q.begin(), Q.end());
         for (int b : owners)
             U.insert(blks[b].qs.begin(), blks[b].qs.end());
+        if (diag && (int)U.size() > fuse_k && (int)Q.size() <= fuse_k) {
+            pool.push_back(o);
+            for (int q : Q)
+                pooled[q] = 1;
+            continue;
+        }
         if ((int)U.size() <= fuse_k) {
             int tgt;
             if (owners.empty()) {
@@ -176,6 +250,7 @@ std::vector<Item> fuse_ops(const qsv_circuit* C, int fuse_k, bool rotations_stan
             }
         }
     }
+    flush();
     for (int b = 0; b < (int)blks.size(); ++b)
         emit(b);
     return out;
@@ -517,7 +592,12 @@ qsv_status build_plan(const qsv_circuit* circ, int dt, int fuse_k, const double*
     P->n = circ->n;
     P->dt = dt;
     P->nparams = circ->nparams;
-    std::vector<Item> items = fuse_ops(circ, fuse_k, params_host == nullptr);
+    // deferring diagonal gates pays when blocks have room to pack them: with
+    // fuse_k = 2 a deferred CZ becomes a launch of its own instead of
+    // starting a block with the gates after it (measured slower)
+    const char* nodd = getenv("QSV_NO_DIAG_DEFER");
+    const bool defer = fuse_k >= 3 && (!nodd || nodd[0] != '1');
+    std::vector<Item> items = fuse_ops(circ, fuse_k, params_host == nullptr, defer);
     for (const Item& it : items) {
         if (it.rotation) {
             const qsv_op& op = circ->ops[it.ops[0]];

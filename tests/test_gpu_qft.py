@@ -183,3 +183,69 @@ def test_swap_runs(q, orc, name, n, kind):
     if kind in ("reverse", "random", "cancel"):
         assert merged.info()[0] < plain.info()[0], (merged.info(), plain.info())
     assert merged.info()[0] <= plain.info()[0]
+
+
+def _phase_circuit(n, seed, rotations):
+    """Hadamards, controlled phases (one and two controls), CZ, diagonal
+    two-qubit matrices and, if asked, rotations with device parameters (RX,
+    RZ: a standalone rotation on a deferred gate's qubit must come after it)
+    in random order."""
+    rng = np.random.default_rng(seed)
+    c = W.Circuit(n)
+    npar = 0
+    for _ in range(8 * n):
+        kind = int(rng.integers(0, 6 if rotations else 4))
+        qs = [int(v) for v in rng.permutation(n)[:3]]
+        if kind == 0:
+            c.ops.append(W.Op("h", (qs[0],)))
+        elif kind == 1:
+            ph = np.exp(1j * rng.uniform(0, 2 * np.pi))
+            ctl = (qs[1],) if rng.integers(0, 2) else (qs[1], qs[2])
+            c.ops.append(W.Op("matrix", (qs[0],), controls=ctl,
+                              matrix=np.diag([1.0, ph]).astype(np.complex128)))
+        elif kind == 2:
+            c.ops.append(W.Op("z", (qs[0],), controls=(qs[1],)))
+        elif kind == 3:
+            d = np.exp(1j * rng.uniform(0, 2 * np.pi, 4))
+            c.ops.append(W.Op("matrix", (qs[0], qs[1]), matrix=np.diag(d).astype(np.complex128)))
+        else:
+            c.ops.append(W.Op("rx" if kind == 4 else "rz", (qs[0],), param=npar))
+            npar += 1
+    c.nparams = npar
+    return c, W.random_params(npar, seed) if npar else None
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("n", [7, 12, 16])
+@pytest.mark.parametrize("fuse", [3, 4, 5])
+@pytest.mark.parametrize("kind", ["qft", "phases", "rotations"])
+def test_diagonal_deferral(q, orc, name, n, fuse, kind):
+    """Fusion defers diagonal gates that do not fit an open block past the
+    gates they commute with and packs them into diagonal blocks: results match
+    the oracle and the plan that closes blocks at such gates, and the QFT
+    takes fewer launches."""
+    import os
+    import torch
+    if kind == "qft":
+        circ, params = W.qft(n), None
+    else:
+        circ, params = _phase_circuit(n, 60 + n, kind == "rotations")
+    rng = np.random.default_rng(n + 1)
+    psi = rand_state(n, rng, name)
+    ref = orc.run(circ, params, psi0=psi)
+    say("diagonal deferral", name, n, fuse, kind)
+    pdev = torch.from_numpy(params).cuda() if params is not None else None
+    d = to_gpu(psi, name)
+    deferred = q.Plan(circ, _code(q, name), fuse)
+    deferred.run(d, pdev)
+    os.environ["QSV_NO_DIAG_DEFER"] = "1"
+    try:
+        plain = q.Plan(circ, _code(q, name), fuse)
+    finally:
+        del os.environ["QSV_NO_DIAG_DEFER"]
+    d2 = to_gpu(psi, name)
+    plain.run(d2, pdev)
+    assert np.max(np.abs(to_np(d) - ref)) <= TOL[name], np.max(np.abs(to_np(d) - ref))
+    assert np.max(np.abs(to_np(d2) - ref)) <= TOL[name]
+    if kind == "qft" and n >= 12:
+        assert deferred.info()[0] < plain.info()[0], (deferred.info(), plain.info())
