@@ -4,6 +4,7 @@
 // consecutive diagonal gates (moving gates on other qubits ahead of them).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <utility>
 #include <vector>
 #include <cstdlib>
@@ -127,9 +128,10 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
     constexpr int AS = sizeof(R) == 4 ? 1 : 0;  // amplitude index = unit << AS
     constexpr int NV = RunVary<R>::NV;
     constexpr int NT = 1 << NV;
+    using V2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
     const uint64_t seglen = (uint64_t)kBlock * kRunUPT;
     const uint64_t nseg = (a.nunits + seglen - 1) / seglen;
-    __shared__ R sd[2 * kMaxRunEntries];
+    __shared__ __align__(16) R sd[2 * kMaxRunEntries];
     for (int k = threadIdx.x; k < 2 * a.ntab; k += kBlock)
         sd[k] = a.tab[k];
     __syncthreads();
@@ -161,22 +163,38 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
         for (int f = a.boff[NV]; f < a.nf; ++f) {
             if ((i0 & a.fixn[f]) != a.valn[f])
                 continue;
-            int t0 = 0;  // table index from the thread's fixed bits (varying bits of i0 are 0)
+            // table index of every entry, by doubling over the varying bits
+            // from the index of the thread's fixed bits (varying bits of i0 are 0)
+            int t0 = 0;
             for (int b = 0; b < a.nt[f]; ++b)
                 t0 |= (int)((i0 >> a.tpos[f][b]) & 1u) << b;
-            const R* e = sd + 2 * a.off[f];
+            // each varying bit adds a table bit that is clear in tt[v], so + is |
+            int tt[NT];
+            tt[0] = a.off[f] + t0;
 #pragma unroll
-            for (int v = 0; v < NT; ++v) {
-                int t = t0;
+            for (int j = 0; j < NV; ++j)
 #pragma unroll
-                for (int j = 0; j < NV; ++j)
-                    if ((v >> j) & 1)
-                        t |= a.tvb[f][j];
-                const bool hit = (v & a.fixv[f]) == a.valv[f];
-                const R dr = hit ? e[2 * t] : (R)1, di = hit ? e[2 * t + 1] : (R)0;
-                const R xr = tr[v], xi = ti[v];
-                tr[v] = xr * dr - xi * di;
-                ti[v] = xr * di + xi * dr;
+                for (int v = 0; v < (1 << j); ++v)
+                    tt[v + (1 << j)] = tt[v] + a.tvb[f][j];
+            const V2* e = reinterpret_cast<const V2*>(sd);
+            if (a.fixv[f] == 0) {
+#pragma unroll
+                for (int v = 0; v < NT; ++v) {
+                    const V2 d = e[tt[v]];
+                    const R xr = tr[v], xi = ti[v];
+                    tr[v] = xr * d.x - xi * d.y;
+                    ti[v] = xr * d.y + xi * d.x;
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < NT; ++v) {
+                    const bool hit = (v & a.fixv[f]) == a.valv[f];
+                    const V2 d = e[tt[v]];
+                    const R dr = hit ? d.x : (R)1, di = hit ? d.y : (R)0;
+                    const R xr = tr[v], xi = ti[v];
+                    tr[v] = xr * dr - xi * di;
+                    ti[v] = xr * di + xi * dr;
+                }
             }
         }
 #pragma unroll
