@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "qsv.h"
+#include "qsv_fuse_plan.h"
 #include "qsv_host.h"
 #include "qsv_qperm_plan.h"
 #include "qsv_internal.h"
@@ -51,11 +52,6 @@ std::vector<double> op_matrix(const qsv_op& op, double theta)
     }
 }
 
-static bool is_rotation(int kind)
-{
-    return kind == QSV_OP_RX || kind == QSV_OP_RY || kind == QSV_OP_RZ;
-}
-
 qsv_status check_circuit(const qsv_circuit* C, int max_n)
 {
     if (!C || (C->nops > 0 && !C->ops) || C->nops < 0)
@@ -87,174 +83,6 @@ qsv_status check_circuit(const qsv_circuit* C, int max_n)
 }
 
 // ------------------------------------------------------------ the planner
-
-struct Item {
-    bool rotation = false;     // standalone unbound rotation
-    std::vector<int> ops;      // ops of the block (one op: emitted natively)
-    std::vector<int> qs;       // block qubits (ascending)
-};
-
-// Whether op's matrix is diagonal (controls keep it diagonal).
-static bool is_diagonal_op(const qsv_op& op)
-{
-    if (op.kind == QSV_OP_Z)
-        return true;
-    if (op.kind != QSV_OP_MATRIX || !op.M)
-        return false;
-    const int D = 1 << op.k;
-    for (int r = 0; r < D; ++r)
-        for (int c = 0; c < D; ++c)
-            if (r != c && (op.M[((size_t)r * D + c) * 2] != 0.0 || op.M[((size_t)r * D + c) * 2 + 1] != 0.0))
-                return false;
-    return true;
-}
-
-// Greedy DAG-aware fusion: each qubit is owned by at most one open block; a
-// gate joins (and merges) the open blocks owning its qubits when the union
-// has <= fuse_k qubits, otherwise those blocks are emitted.  Open blocks have
-// disjoint qubits, so their relative order is free.
-//
-// With defer_diagonal (plans with fuse_k >= 3), a diagonal gate that does
-// not fit the blocks owning its qubits leaves them open and waits in a pool
-// instead: diagonal gates
-// commute with each other and with gates on other qubits, so the pool only
-// has to be applied before the next non-diagonal gate on one of its qubits
-// (and after the blocks that hold earlier gates on them).  That gate flushes
-// the pool: first the blocks owning pooled qubits, then the pooled gates
-// packed (first fit) into diagonal blocks of <= fuse_k qubits.  A QFT then
-// keeps its Hadamards and the phases among them in blocks of fuse_k qubits,
-// and the phases between blocks become a few diagonal blocks each.
-std::vector<Item> fuse_ops(const qsv_circuit* C, int fuse_k, bool rotations_standalone,
-                           bool defer_diagonal = false)
-{
-    struct Blk {
-        std::set<int> qs;
-        std::vector<int> ops;
-        bool open = true;
-    };
-    std::vector<Blk> blks;
-    std::vector<int> owner(C->n, -1);
-    std::vector<Item> out;
-    auto emit = [&](int b) {
-        Blk& B = blks[b];
-        if (!B.open)
-            return;
-        B.open = false;
-        for (int q : B.qs)
-            if (owner[q] == b)
-                owner[q] = -1;
-        Item it;
-        it.ops = B.ops;
-        it.qs.assign(B.qs.begin(), B.qs.end());
-        out.push_back(it);
-    };
-    std::vector<int> pool;  // deferred diagonal gates
-    std::vector<char> pooled(C->n, 0);
-    auto flush = [&]() {
-        if (pool.empty())
-            return;
-        for (int q = 0; q < C->n; ++q)
-            if (pooled[q] && owner[q] >= 0)
-                emit(owner[q]);
-        std::vector<Item> groups;
-        for (int o : pool) {
-            const qsv_op& op = C->ops[o];
-            std::set<int> Q(op.targets, op.targets + op.k);
-            Q.insert(op.controls, op.controls + op.c);
-            Item* g = nullptr;
-            for (Item& G : groups) {
-                std::set<int> U(G.qs.begin(), G.qs.end());
-                U.insert(Q.begin(), Q.end());
-                if ((int)U.size() <= fuse_k) {
-                    G.qs.assign(U.begin(), U.end());
-                    g = &G;
-                    break;
-                }
-            }
-            if (!g) {
-                groups.emplace_back();
-                g = &groups.back();
-                g->qs.assign(Q.begin(), Q.end());
-            }
-            g->ops.push_back(o);
-        }
-        out.insert(out.end(), groups.begin(), groups.end());
-        pool.clear();
-        std::fill(pooled.begin(), pooled.end(), 0);
-    };
-    for (int o = 0; o < C->nops; ++o) {
-        const qsv_op& op = C->ops[o];
-        std::vector<int> Q(op.targets, op.targets + op.k);
-        Q.insert(Q.end(), op.controls, op.controls + op.c);
-        const bool diag = defer_diagonal && !is_rotation(op.kind) && is_diagonal_op(op);
-        if (!pool.empty() && !diag)
-            for (int q : Q)
-                if (pooled[q]) {
-                    flush();
-                    break;
-                }
-        std::set<int> owners;
-        for (int q : Q)
-            if (owner[q] >= 0)
-                owners.insert(owner[q]);
-        if (rotations_standalone && is_rotation(op.kind)) {
-            for (int b : owners)
-                emit(b);
-            Item it;
-            it.rotation = true;
-            it.ops = {o};
-            out.push_back(it);
-            continue;
-        }
-        std::set<int> U(Q.begin(), Q.end());
-        for (int b : owners)
-            U.insert(blks[b].qs.begin(), blks[b].qs.end());
-        if (diag && (int)U.size() > fuse_k && (int)Q.size() <= fuse_k) {
-            pool.push_back(o);
-            for (int q : Q)
-                pooled[q] = 1;
-            continue;
-        }
-        if ((int)U.size() <= fuse_k) {
-            int tgt;
-            if (owners.empty()) {
-                blks.push_back(Blk{});
-                tgt = (int)blks.size() - 1;
-            } else {
-                tgt = *owners.begin();
-                for (int b : owners)
-                    if (b != tgt) {
-                        blks[tgt].ops.insert(blks[tgt].ops.end(), blks[b].ops.begin(),
-                                             blks[b].ops.end());
-                        blks[b].open = false;
-                    }
-            }
-            blks[tgt].ops.push_back(o);
-            blks[tgt].qs = U;
-            for (int q : U)
-                owner[q] = tgt;
-        } else {
-            for (int b : owners)
-                emit(b);
-            if ((int)Q.size() <= fuse_k) {
-                blks.push_back(Blk{});
-                const int tgt = (int)blks.size() - 1;
-                blks[tgt].ops = {o};
-                blks[tgt].qs = std::set<int>(Q.begin(), Q.end());
-                for (int q : Q)
-                    owner[q] = tgt;
-            } else {
-                Item it;
-                it.ops = {o};
-                out.push_back(it);
-            }
-        }
-    }
-    flush();
-    for (int b = 0; b < (int)blks.size(); ++b)
-        emit(b);
-    return out;
-}
 
 // Matrix of `op` embedded in the block on ascending qubits qs (bit j <-> qs[j]).
 static std::vector<double> embed(const qsv_op& op, const std::vector<double>& G,

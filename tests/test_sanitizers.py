@@ -6,8 +6,9 @@ tests/oracle_sanitize_check.c, the tile-program compiler of the library
 random gate lists, and the register-pass planner (csrc/rpass_plan.cpp)
 through tests/rpass_check.cpp on mixed Pauli sums, the span-pass planner
 (csrc/span_plan.cpp) through tests/span_check.cpp, the qubit permutation
-planner (csrc/qperm_plan.cpp) through tests/qperm_check.cpp on swap runs; all
-are built with g++/gcc and
+planner (csrc/qperm_plan.cpp) through tests/qperm_check.cpp on swap runs, the
+fusion planner (csrc/fuse_plan.cpp) through tests/fuse_check.cpp on random
+circuits; all are built with g++/gcc and
 -fsanitize=address,undefined -fno-sanitize-recover=all, so any out-of-bounds
 access, use after free, leak or undefined behaviour aborts the run.  The
 GPU code is not built here (GPU sanitizers are not available)."""
@@ -107,3 +108,14 @@ def test_qubit_permutation_planner_under_sanitizers(tmp_path):
         assert run_qperm(exe, n, rl, reversal(n), env=ENV) == 1
         swaps = [tuple(int(v) for v in rng.permutation(n)[:2]) for _ in range(3 * n)]
         assert run_qperm(exe, n, rl, swaps, env=ENV) in (0, 1, 2)
+
+
+def test_fusion_planner_under_sanitizers(tmp_path):
+    from test_fuse_plan import build_checker, random_circuit
+    from test_fuse_plan import run as run_fuse
+    exe = build_checker(str(tmp_path / "fuse_check"), SAN)
+    for seed in range(4):
+        circ, params = random_circuit(7, 900 + seed, seed % 2 == 0)
+        for k in (2, 3, 5):
+            run_fuse(exe, circ, params, k, seed % 2 == 1, True, env=ENV)
+    run_fuse(exe, W.qft(9), np.zeros(1), 5, True, True, env=ENV)
