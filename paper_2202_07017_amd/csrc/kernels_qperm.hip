@@ -9,7 +9,10 @@
 // images of the row bits, so the image of a tile is one tile and both its
 // reads and its writes are whole rows.  A workgroup takes a tile and its
 // image (or a tile that is its own image), loads them into LDS, and writes
-// each into the other's place, reading the LDS in permuted order.  LDS rows
+// each into the other's place, reading the LDS in permuted order.  The
+// workgroup index maps to the tile index through a bit permutation chosen by
+// the planner, so that consecutive workgroups step through adjacent rows of
+// both their tiles and the images (DRAM page locality on both sides).  LDS rows
 // are XOR-swizzled by row index so that reading a column (the transpose that
 // bit reversal makes of the row bits) spreads over the banks.
 #include "qsv_internal.h"
@@ -29,6 +32,8 @@ struct QPermK {
     int hpos[6];
     int cmap[12];
     unsigned int qw[16];  // q[b] (b < 64) in byte b % 4 of qw[b / 4]
+    unsigned int ww[16];  // wsrc[p] likewise: bit p of the tile index = bit wsrc[p] of the workgroup index
+    int nouter;           // n - RL - hb
 };
 
 // The loops below run to fixed bounds without branches (the launcher pads
@@ -92,11 +97,19 @@ __global__ void __launch_bounds__(NT) k_qperm(V* __restrict__ psi0, V* __restric
     __shared__ V lds[2][TMAX];
 
     V* p = blockIdx.y ? psi1 : psi0;
-    const uint64_t tile = xcd_block();
-    if (tile >= a.ntiles)
+    const uint64_t widx = xcd_block();
+    if (widx >= a.ntiles)
         return;
-    const uint64_t ba = insert_bits(tile, a.ins);
     const int lane = threadIdx.x & 63;
+    // the workgroup's tile: lane p supplies bit p = bit wsrc[p] of widx
+    unsigned int wword = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if ((lane >> 2) == j)
+            wword = a.ww[j];
+    const int wb = (wword >> ((lane & 3) * 8)) & 63;
+    const uint64_t tile = __ballot(lane < a.nouter && ((widx >> wb) & 1ull));
+    const uint64_t ba = insert_bits(tile, a.ins);
     // the image tile: lane b supplies bit b = bit q[b] of ba
     unsigned int qword = 0;
 #pragma unroll
@@ -190,6 +203,9 @@ hipError_t qperm_go(const GateLaunch& L, void* p0, void* p1, hipStream_t s)
         a.cmap[k] = k < RL + L.qp_hb ? L.qp_cmap[k] : 31;
     for (int b = 0; b < L.n; ++b)
         a.qw[b / 4] |= (unsigned int)(L.qp_q[b] & 63) << (8 * (b % 4));
+    a.nouter = L.n - RL - L.qp_hb;
+    for (int b = 0; b < a.nouter; ++b)
+        a.ww[b / 4] |= (unsigned int)(L.qp_wsrc[b] & 63) << (8 * (b % 4));
     const dim3 grid((unsigned)L.ngroups, p1 ? 2 : 1);
     hipLaunchKernelGGL((k_qperm<V, RL, NT>), grid, dim3(NT), 0, s, static_cast<V*>(p0),
                        static_cast<V*>(p1 ? p1 : p0), a);

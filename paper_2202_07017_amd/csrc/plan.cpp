@@ -340,8 +340,10 @@ void merge_swaps(std::vector<GateLaunch>& Ls, std::vector<long long>& upload_off
                 }
                 for (int k = 0; k < P.rl + P.hb; ++k)
                     R.qp_cmap[k] = P.cmap[k];
-                for (int b = 0; b < n; ++b)
+                for (int b = 0; b < n; ++b) {
                     R.qp_q[b] = P.q[b];
+                    R.qp_wsrc[b] = P.wsrc[b];
+                }
                 R.ins = make_ins(tpos, 0);
                 R.qmask = qm;
                 R.bytes = 2.0 * amp_bytes(dt) * std::ldexp(1.0, n);

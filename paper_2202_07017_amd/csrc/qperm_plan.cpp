@@ -68,6 +68,40 @@ QPermPass make_pass(const std::vector<int>& q, int n, int rl)
     for (int b = 0; b < n; ++b)
         P.q[b] = q[b];
     P.ntiles = 1ull << (n - rl - P.hb);
+    // Outer bits (not tile bits) in compact order; the workgroup index takes
+    // them alternately from the lowest outer bit not yet taken and from the
+    // one whose image is the lowest not yet taken, so the low workgroup bits
+    // vary the low bits of both the tile and its image.
+    std::vector<int> outer;
+    for (int b = 0; b < n; ++b)
+        if (!in_t[b])
+            outer.push_back(b);
+    std::vector<int> opos(n, -1);
+    for (size_t p = 0; p < outer.size(); ++p)
+        opos[outer[p]] = (int)p;
+    std::vector<char> taken(outer.size(), 0);
+    int w = 0;
+    size_t lo = 0, lo_img = 0;
+    std::vector<int> by_image(outer);
+    std::sort(by_image.begin(), by_image.end(), [&](int a, int b) { return q[a] < q[b]; });
+    for (int turn = 0; w < (int)outer.size(); turn ^= 1) {
+        int b = -1;
+        if (turn == 0) {
+            while (lo < outer.size() && taken[opos[outer[lo]]])
+                ++lo;
+            if (lo < outer.size())
+                b = outer[lo];
+        } else {
+            while (lo_img < by_image.size() && taken[opos[by_image[lo_img]]])
+                ++lo_img;
+            if (lo_img < by_image.size())
+                b = by_image[lo_img];
+        }
+        if (b < 0)
+            continue;
+        taken[opos[b]] = 1;
+        P.wsrc[opos[b]] = w++;
+    }
     return P;
 }
 

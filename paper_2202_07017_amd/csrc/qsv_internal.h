@@ -94,6 +94,7 @@ struct GateLaunch {
     int qp_hpos[6] = {};
     int qp_cmap[12] = {};
     int qp_q[64] = {};
+    int qp_wsrc[64] = {};  // bit p of the tile index = bit qp_wsrc[p] of the workgroup index
     uint64_t qmask = ~0ull;  // every qubit the launch reads or writes (targets and controls)
     // accounting
     double bytes = 0.0;

@@ -31,6 +31,10 @@ struct QPermPass {
     int cmap[2 * kQpMaxRowBits] = {};
     int q[kQpMaxQubits] = {};
     uint64_t ntiles = 0;  // 2^(n - rl - hb)
+    // tile order: bit p of the compact tile index is bit wsrc[p] of the
+    // workgroup index (p < n - rl - hb), chosen so that consecutive
+    // workgroups step through adjacent rows of both a tile and its image
+    int wsrc[kQpMaxQubits] = {};
 };
 
 // Bit map of a swap sequence applied in order: the result takes its

@@ -72,6 +72,13 @@ int main()
         for (int k = 0; k < tb; ++k)
             require(P.cmap[k] >= 0 && P.cmap[k] < tb && T[P.cmap[k]] == P.q[T[k]], "cmap");
         require(P.ntiles == (1ull << (n - tb)), "tile count");
+        std::vector<int> wseen(n - tb, 0);
+        for (int p = 0; p < n - tb; ++p) {
+            require(P.wsrc[p] >= 0 && P.wsrc[p] < n - tb, "tile order bit");
+            ++wseen[P.wsrc[p]];
+        }
+        for (int p = 0; p < n - tb; ++p)
+            require(wseen[p] == 1, "tile order is not a bijection");
         auto dep = [&](uint64_t l) {
             uint64_t o = 0;
             for (int k = 0; k < tb; ++k)
@@ -85,7 +92,10 @@ int main()
             return o;
         };
         std::vector<unsigned char> hit(N, 0);
-        for (uint64_t t = 0; t < P.ntiles; ++t) {
+        for (uint64_t w = 0; w < P.ntiles; ++w) {
+            uint64_t t = 0;  // the tile of workgroup w
+            for (int p = 0; p < n - tb; ++p)
+                t |= ((w >> P.wsrc[p]) & 1ull) << p;
             uint64_t ba = t;  // insert zeros at the tile bits, ascending
             std::vector<int> Ts(T);
             std::sort(Ts.begin(), Ts.end());
