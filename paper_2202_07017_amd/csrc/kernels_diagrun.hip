@@ -63,7 +63,6 @@ struct DiagRunK {
     int boff[6];
     uint64_t fix[kMaxRunFactors];
     uint64_t val[kMaxRunFactors];
-    int nt[kMaxRunFactors];
     int tpos[kMaxRunFactors][5];
     int off[kMaxRunFactors];       // first complex entry of the factor's table
     // factors on several varying bits: fixed bits outside the varying bits
@@ -78,6 +77,20 @@ struct DiagRunK {
     int ntab;                      // complex entries in tab
 };
 
+// Table index of amplitude i in factor f: bit b is bit tpos[f][b] of i.
+// Unused positions hold 63 (zero in every index), so the loop has a fixed
+// trip count and a factor's descriptor is read in one batch of scalar loads
+// rather than one dependent load per bit.
+template <typename R>
+__device__ __forceinline__ int run_index(const DiagRunK<R>& a, int f, uint64_t i)
+{
+    int t = 0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+        t |= (int)((i >> a.tpos[f][b]) & 1u) << b;
+    return t;
+}
+
 // Multiplies (re, im) by factor f's entry for amplitude i, if i's fixed bits
 // match; the tables sit in LDS.
 template <typename R>
@@ -86,9 +99,7 @@ __device__ __forceinline__ void run_factor(const DiagRunK<R>& a, const R* sd, in
 {
     if ((i & a.fix[f]) != a.val[f])
         return;
-    int t = 0;
-    for (int b = 0; b < a.nt[f]; ++b)
-        t |= (int)((i >> a.tpos[f][b]) & 1u) << b;
+    const int t = run_index(a, f, i);
     const R dr = sd[2 * (a.off[f] + t)], di = sd[2 * (a.off[f] + t) + 1];
     const R r = re * dr - im * di;
     im = re * di + im * dr;
@@ -165,9 +176,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
                 continue;
             // table index of every entry, by doubling over the varying bits
             // from the index of the thread's fixed bits (varying bits of i0 are 0)
-            int t0 = 0;
-            for (int b = 0; b < a.nt[f]; ++b)
-                t0 |= (int)((i0 >> a.tpos[f][b]) & 1u) << b;
+            const int t0 = run_index(a, f, i0);
             // each varying bit adds a table bit that is clear in tt[v], so + is |
             int tt[NT];
             tt[0] = a.off[f] + t0;
@@ -257,10 +266,9 @@ hipError_t diag_run_go(const GateLaunch& L, void* p, hipStream_t s)
         const int f = order[k].second;
         a.fix[k] = L.run_fix[f];
         a.val[k] = L.run_val[f];
-        a.nt[k] = L.run_nt[f];
         a.off[k] = L.run_off[f];
-        for (int b = 0; b < L.run_nt[f]; ++b)
-            a.tpos[k][b] = L.run_tpos[f][b];
+        for (int b = 0; b < 5; ++b)
+            a.tpos[k][b] = b < L.run_nt[f] ? L.run_tpos[f][b] : 63;
         uint64_t vall = 0;
         for (int j = 0; j < NV; ++j) {
             vall |= vmask[j];
