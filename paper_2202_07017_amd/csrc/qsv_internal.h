@@ -26,7 +26,7 @@ enum Mode : int { W1 = 0, W2 = 1, INTRA = 2 };
 
 enum LaunchType : int { L_DENSE = 0, L_DIAG = 1, L_PERM = 2, L_MFMA = 3, L_DIAGRUN = 4, L_QPERM = 5 };
 
-constexpr int kMaxRunFactors = 16;  // diagonal gates merged into one L_DIAGRUN sweep
+constexpr int kMaxRunFactors = 32;  // diagonal gates merged into one L_DIAGRUN sweep
 constexpr int kMaxRunEntries = kMaxRunFactors * 32;  // table entries of one run
 
 // Rotation kinds read from a device parameter vector (values follow qsv_op_kind).
