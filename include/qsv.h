@@ -59,6 +59,8 @@
  *                               product kernel (default: 4 at k = 5; at k = 4
  *                               2 for targets within 8 qubits, else 1)
  *    QSV_NO_DIAG_RUN=1          plans keep consecutive diagonal gates as separate launches
+ *    QSV_NO_GATE_FOLD=1         plans keep single-qubit gates next to diagonal runs as
+ *                               separate launches instead of applying them in the run's sweep
  *    QSV_NO_SWAP_MERGE=1        plans keep consecutive SWAP gates as separate launches
  *                               instead of qubit permutation passes
  *    QSV_NO_DIAG_DEFER=1        fusion (fuse_k >= 3) closes blocks at diagonal gates that

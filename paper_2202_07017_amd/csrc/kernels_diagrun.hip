@@ -75,6 +75,10 @@ struct DiagRunK {
     int tvb[kMaxRunFactors][5];
     const R* tab;                  // all tables, (re, im), state precision
     int ntab;                      // complex entries in tab
+    int w;                         // a thread's units differ in unit bits w..w+3 (w >= 8)
+    uint64_t vmask[5];             // amplitude index bit of varying bit j
+    int gafter;                    // the gate follows the diagonal (else it precedes it)
+    R g[8];                        // its matrix, row-major (re, im); row 0 = target bit 0
 };
 
 // Table index of amplitude i in factor f: bit b is bit tpos[f][b] of i.
@@ -106,9 +110,11 @@ __device__ __forceinline__ void run_factor(const DiagRunK<R>& a, const R* sd, in
     re = r;
 }
 
-// Each thread takes kRunUPT units kBlock apart (coalesced across the block),
-// so only NV index bits vary over its amplitudes: unit bits 8..11 and, in
-// complex64, amplitude bit 0 (the two amplitudes of a 16-byte unit).  The
+// A block covers 256 consecutive units per load (coalesced); each thread
+// takes kRunUPT units that differ in the four unit bits w..w+3 (w >= 8,
+// chosen by the planner; w = 8: units 256 apart), so only NV index bits vary
+// over its amplitudes: those four and, in complex64, amplitude bit 0 (the
+// two amplitudes of a 16-byte unit).  The
 // thread builds the run's product for every value v of those bits, a table
 // T[v] of 2^NV entries in registers: factors that read no varying bit are
 // evaluated once; a factor that reads only varying bit j contributes
@@ -117,23 +123,19 @@ __device__ __forceinline__ void run_factor(const DiagRunK<R>& a, const R* sd, in
 // The sweep then multiplies each amplitude by its entry.  A long ladder of
 // controlled phases on one of the varying bits costs two evaluations per
 // factor and thread instead of one per factor and amplitude.
+//
+// A single-qubit gate whose target is a varying bit pairs amplitudes within
+// the thread, so the sweep can also apply a gate that directly precedes or
+// follows the run (GJ >= 0, the gate's varying bit): the thread loads its units, applies the gate
+// before or after the diagonal, and stores them, one sweep for both.
 constexpr int kRunUPT = 16;
 
 template <typename R>
-struct RunVary;
-template <>
-struct RunVary<float> {
-    static constexpr int NV = 5;
-    // amplitude index bit of varying bit j: amplitude bit 0, then unit bits 8..11
-    __device__ static constexpr int bit(int j) { return j == 0 ? 0 : 8 + j; }
-};
-template <>
-struct RunVary<double> {
-    static constexpr int NV = 4;
-    __device__ static constexpr int bit(int j) { return 8 + j; }
+struct RunVary {
+    static constexpr int NV = sizeof(R) == 4 ? 5 : 4;
 };
 
-template <typename R>
+template <typename R, int GJ>
 __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const DiagRunK<R> a)
 {
     constexpr int AS = sizeof(R) == 4 ? 1 : 0;  // amplitude index = unit << AS
@@ -146,8 +148,11 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
     for (int k = threadIdx.x; k < 2 * a.ntab; k += kBlock)
         sd[k] = a.tab[k];
     __syncthreads();
+    const int wl = a.w - 8;  // segment bits below the window
     for (uint64_t seg = xcd_block(); seg < nseg; seg += gridDim.x) {
-        const uint64_t u0 = seg * seglen + threadIdx.x;
+        // unit of element r: u0 | r << w (unit bits 0..7: the thread; the
+        // segment fills the bits below and above the window)
+        const uint64_t u0 = ((seg >> wl) << (a.w + 4)) | ((seg & ((1ull << wl) - 1)) << 8) | threadIdx.x;
         const uint64_t i0 = u0 << AS;  // varying bits zero
         R tr[NT], ti[NT];
         tr[0] = (R)1;
@@ -156,7 +161,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
             run_factor(a, sd, f, i0, tr[0], ti[0]);
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
-            const uint64_t bj = 1ull << RunVary<R>::bit(j);
+            const uint64_t bj = a.vmask[j];
             R h0r = (R)1, h0i = (R)0, h1r = (R)1, h1i = (R)0;
             for (int f = a.boff[j]; f < a.boff[j + 1]; ++f) {
                 run_factor(a, sd, f, i0, h0r, h0i);
@@ -206,21 +211,76 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
                 }
             }
         }
+        if constexpr (GJ >= 0) {
+            // the planner folds a gate only where every unit of the window
+            // exists (no tail), so pairs never mix loaded and missing units
+            constexpr int NE = NT;
+            R er[NE], ei[NE];
 #pragma unroll
-        for (int r = 0; r < kRunUPT; ++r) {
-            const uint64_t u = u0 + (uint64_t)r * kBlock;
-            if (u >= a.nunits)
-                break;
-            if constexpr (sizeof(R) == 4) {
-                float4* p = reinterpret_cast<float4*>(psi);
-                const float4 x = ld_nt(&p[u]);
-                const float ar = tr[2 * r], ai = ti[2 * r], br = tr[2 * r + 1], bi = ti[2 * r + 1];
-                st_nt(&p[u], make_float4(ar * x.x - ai * x.y, ar * x.y + ai * x.x, br * x.z - bi * x.w,
-                                           br * x.w + bi * x.z));
-            } else {
-                double2* p = reinterpret_cast<double2*>(psi);
-                const double2 x = ld_nt(&p[u]);
-                st_nt(&p[u], make_double2(tr[r] * x.x - ti[r] * x.y, tr[r] * x.y + ti[r] * x.x));
+            for (int r = 0; r < kRunUPT; ++r) {
+                const uint64_t u = u0 | ((uint64_t)r << a.w);
+                if constexpr (sizeof(R) == 4) {
+                    const float4 x = u < a.nunits ? ld_nt(&reinterpret_cast<float4*>(psi)[u]) : make_float4(0, 0, 0, 0);
+                    er[2 * r] = x.x;
+                    ei[2 * r] = x.y;
+                    er[2 * r + 1] = x.z;
+                    ei[2 * r + 1] = x.w;
+                } else {
+                    const double2 x = u < a.nunits ? ld_nt(&reinterpret_cast<double2*>(psi)[u]) : make_double2(0, 0);
+                    er[r] = x.x;
+                    ei[r] = x.y;
+                }
+            }
+            // the gate on element pairs (e, e | 2^GJ)
+            auto gate = [&]() {
+#pragma unroll
+                for (int e = 0; e < NE; ++e)
+                    if (!((e >> GJ) & 1)) {
+                        const int h = e | (1 << GJ);
+                        const R ar = er[e], ai = ei[e], br = er[h], bi = ei[h];
+                        er[e] = a.g[0] * ar - a.g[1] * ai + a.g[2] * br - a.g[3] * bi;
+                        ei[e] = a.g[0] * ai + a.g[1] * ar + a.g[2] * bi + a.g[3] * br;
+                        er[h] = a.g[4] * ar - a.g[5] * ai + a.g[6] * br - a.g[7] * bi;
+                        ei[h] = a.g[4] * ai + a.g[5] * ar + a.g[6] * bi + a.g[7] * br;
+                    }
+            };
+            if (!a.gafter)
+                gate();
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const R xr = er[e], xi = ei[e];
+                er[e] = tr[e] * xr - ti[e] * xi;
+                ei[e] = tr[e] * xi + ti[e] * xr;
+            }
+            if (a.gafter)
+                gate();
+#pragma unroll
+            for (int r = 0; r < kRunUPT; ++r) {
+                const uint64_t u = u0 | ((uint64_t)r << a.w);
+                if (u >= a.nunits)
+                    continue;
+                if constexpr (sizeof(R) == 4)
+                    st_nt(&reinterpret_cast<float4*>(psi)[u], make_float4(er[2 * r], ei[2 * r], er[2 * r + 1], ei[2 * r + 1]));
+                else
+                    st_nt(&reinterpret_cast<double2*>(psi)[u], make_double2(er[r], ei[r]));
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kRunUPT; ++r) {
+                const uint64_t u = u0 | ((uint64_t)r << a.w);
+                if (u >= a.nunits)
+                    break;
+                if constexpr (sizeof(R) == 4) {
+                    float4* p = reinterpret_cast<float4*>(psi);
+                    const float4 x = ld_nt(&p[u]);
+                    const float ar = tr[2 * r], ai = ti[2 * r], br = tr[2 * r + 1], bi = ti[2 * r + 1];
+                    st_nt(&p[u], make_float4(ar * x.x - ai * x.y, ar * x.y + ai * x.x, br * x.z - bi * x.w,
+                                               br * x.w + bi * x.z));
+                } else {
+                    double2* p = reinterpret_cast<double2*>(psi);
+                    const double2 x = ld_nt(&p[u]);
+                    st_nt(&p[u], make_double2(tr[r] * x.x - ti[r] * x.y, tr[r] * x.y + ti[r] * x.x));
+                }
             }
         }
     }
@@ -240,10 +300,18 @@ template <typename R>
 hipError_t diag_run_go(const GateLaunch& L, void* p, hipStream_t s)
 {
     constexpr int NV = RunVary<R>::NV;
-    // order the factors by the varying bits they read (see DiagRunK)
+    constexpr int AS = sizeof(R) == 4 ? 1 : 0;
+    // the window must lie inside the unit index, and a folded gate needs
+    // every unit of it (no tail)
+    const int w = L.run_w;
+    const uint64_t span = 1ull << (w + 4);
+    if (w < 8 || w > 58 || ((w > 8 || L.run_gate) && L.ngroups < span))
+        return hipErrorInvalidValue;
+    // varying bits: (complex64) amplitude bit 0, then unit bits w..w+3
     uint64_t vmask[NV];
     for (int j = 0; j < NV; ++j)
-        vmask[j] = 1ull << (sizeof(R) == 4 ? (j == 0 ? 0 : 8 + j) : 8 + j);
+        vmask[j] = AS ? (j == 0 ? 1ull : 1ull << (w + j)) : 1ull << (w + j);
+    // order the factors by the varying bits they read (see DiagRunK)
     std::vector<std::pair<int, int>> order;  // (class, factor)
     for (int f = 0; f < L.run_nf; ++f) {
         uint64_t dep = L.run_fix[f];
@@ -294,8 +362,30 @@ hipError_t diag_run_go(const GateLaunch& L, void* p, hipStream_t s)
     a.ntab = (int)(L.run_tab.size() / 2);
     if (!a.tab || a.ntab > kMaxRunEntries)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_diag_run<R>), dim3(run_grid(a.nunits)), dim3(kBlock), 0, s,
-                       static_cast<R*>(p), a);
+    a.w = w;
+    for (int j = 0; j < NV; ++j)
+        a.vmask[j] = vmask[j];
+    int gjt = -1;  // the gate's varying bit
+    if (L.run_gate) {
+        for (int j = 0; j < NV; ++j)
+            if (vmask[j] == 1ull << L.run_gt)
+                gjt = j;
+        if (gjt < 0)
+            return hipErrorInvalidValue;
+        a.gafter = L.run_gate == 2;
+        for (int k = 0; k < 8; ++k)
+            a.g[k] = (R)L.run_g[k];
+    }
+    const dim3 grid(run_grid(a.nunits)), block(kBlock);
+    R* ps = static_cast<R*>(p);
+    switch (gjt) {
+    case -1: hipLaunchKernelGGL((k_diag_run<R, -1>), grid, block, 0, s, ps, a); break;
+    case 0: hipLaunchKernelGGL((k_diag_run<R, 0>), grid, block, 0, s, ps, a); break;
+    case 1: hipLaunchKernelGGL((k_diag_run<R, 1>), grid, block, 0, s, ps, a); break;
+    case 2: hipLaunchKernelGGL((k_diag_run<R, 2>), grid, block, 0, s, ps, a); break;
+    case 3: hipLaunchKernelGGL((k_diag_run<R, 3>), grid, block, 0, s, ps, a); break;
+    default: hipLaunchKernelGGL((k_diag_run<R, NV - 1>), grid, block, 0, s, ps, a); break;
+    }
     return hipGetLastError();
 }
 

@@ -290,6 +290,88 @@ void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& up
     upload_off.swap(offs);
 }
 
+// A plain single-qubit gate (uncontrolled, bound matrix) directly before or
+// after a diagonal run joins the run's sweep when its target can be one of
+// the run kernel's varying bits: complex64 qubit 0 (the two amplitudes of a
+// 16-byte unit) or a qubit >= 9, complex128 a qubit >= 8, with the window of
+// four varying unit bits placed over it (states of >= 2^12 units).  The
+// window with the cheapest factor classes is taken.
+static bool plain_1q(const GateLaunch& L, int& t)
+{
+    // no controls: the only inserted bit is the target's (none in complex64
+    // INTRA mode, where the target is qubit 0 inside a 16-byte unit)
+    if (L.type != L_DENSE || L.K != 1 || L.rot != ROT_NONE || L.ins.setmask != 0 ||
+        L.ins.nins != (L.mode == INTRA ? 0 : 1) || L.g.size() < 8)
+        return false;
+    t = L.lowq;
+    return true;
+}
+
+static double run_cost(const GateLaunch& R, int w, int dt)
+{
+    uint64_t vm = 0;
+    for (int j = 0; j < 4; ++j)
+        vm |= 1ull << (w + j + (dt == C64 ? 1 : 0));
+    if (dt == C64)
+        vm |= 1;
+    double c = 0.0;
+    for (int f = 0; f < R.run_nf; ++f) {
+        uint64_t dep = R.run_fix[f];
+        for (int b = 0; b < R.run_nt[f]; ++b)
+            dep |= 1ull << R.run_tpos[f][b];
+        const int nr = __builtin_popcountll(dep & vm);
+        c += nr == 0 ? 1.0 : (nr == 1 ? 2.0 : 16.0);
+    }
+    return c;
+}
+
+void fold_gates_into_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& upload_off, int n, int dt)
+{
+    const int nu = dt == C64 ? n - 1 : n;  // bits of the 16-byte unit index
+    if (nu < 12)
+        return;
+    for (size_t j = 0; j < Ls.size(); ++j) {
+        if (Ls[j].type != L_DIAGRUN || Ls[j].run_gate)
+            continue;
+        for (int side = 0; side < 2; ++side) {  // the launch before, then the one after
+            if (side == 0 && j == 0)
+                continue;
+            const size_t k = side == 0 ? j - 1 : j + 1;
+            int t;
+            if (k >= Ls.size() || !plain_1q(Ls[k], t) || upload_off[k] >= 0)
+                continue;
+            int wlo, whi;
+            if (dt == C64 && t == 0) {
+                wlo = 8;
+                whi = nu - 4;
+            } else {
+                const int tb = dt == C64 ? t - 1 : t;  // the target's unit bit
+                wlo = std::max(8, tb - 3);
+                whi = std::min(tb, nu - 4);
+            }
+            if (wlo > whi)
+                continue;
+            int best = wlo;
+            for (int w = wlo + 1; w <= whi; ++w)
+                if (run_cost(Ls[j], w, dt) < run_cost(Ls[j], best, dt))
+                    best = w;
+            GateLaunch& R = Ls[j];
+            R.run_w = best;
+            R.run_gate = side == 0 ? 1 : 2;
+            R.run_gt = t;
+            for (int q = 0; q < 8; ++q)
+                R.run_g[q] = Ls[k].g[q];
+            R.qmask |= Ls[k].qmask;
+            R.flops += Ls[k].flops;
+            Ls.erase(Ls.begin() + (long)k);
+            upload_off.erase(upload_off.begin() + (long)k);
+            if (side == 0)
+                --j;  // the run moved down by one
+            break;
+        }
+    }
+}
+
 // A SWAP moves the half of the state whose two bits differ; when the lower
 // qubit is below 4 its moved amplitudes share 128-byte lines with unmoved
 // ones, so it costs a full sweep.  A run of consecutive SWAPs composes into
@@ -457,6 +539,9 @@ qsv_status build_plan(const qsv_circuit* circ, int dt, int fuse_k, const double*
     const char* nodr = getenv("QSV_NO_DIAG_RUN");
     if (!nodr || nodr[0] != '1') {
         merge_diagonal_runs(P->launches, P->upload_off, P->n, dt);
+        const char* nogf = getenv("QSV_NO_GATE_FOLD");
+        if (!nogf || nogf[0] != '1')
+            fold_gates_into_runs(P->launches, P->upload_off, P->n, dt);
         for (size_t j = 0; j < P->launches.size(); ++j) {
             const GateLaunch& L = P->launches[j];
             if (L.type != L_DIAGRUN)

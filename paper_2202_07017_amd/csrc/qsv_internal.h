@@ -81,6 +81,14 @@ struct GateLaunch {
     int run_tpos[kMaxRunFactors][5] = {};
     int run_off[kMaxRunFactors] = {};
     std::vector<double> run_tab;
+    // a thread's units differ in unit bits run_w..run_w+3 (run_w >= 8); a
+    // single-qubit gate on amplitude bit run_gt (one of the thread's varying
+    // bits) may be applied in the same sweep, before (run_gate = 1) or after
+    // (2) the diagonal, matrix run_g (canonical, complex128, row-major)
+    int run_w = 8;
+    int run_gate = 0;
+    int run_gt = 0;
+    double run_g[8] = {};
     // perm: the two qubits of an uncontrolled SWAP (-1: another permutation)
     int swapq[2] = {-1, -1};
     // qubit permutation pass: output amplitude j takes input amplitude i with
@@ -106,6 +114,10 @@ struct GateLaunch {
 // bits each) into L_DIAGRUN sweeps where a full sweep is cheaper than the
 // separate launches' estimated traffic.
 void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& upload_off, int n, int dt);
+
+// Apply a plain single-qubit gate next to a diagonal run in the run's sweep
+// (L_DIAGRUN with run_gate set) where its target fits the run kernel.
+void fold_gates_into_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& upload_off, int n, int dt);
 
 // Compose runs of consecutive SWAP launches into qubit permutation passes
 // (L_QPERM, one or two per run) where that moves fewer bytes.

@@ -249,3 +249,61 @@ def test_diagonal_deferral(q, orc, name, n, fuse, kind):
     assert np.max(np.abs(to_np(d2) - ref)) <= TOL[name]
     if kind == "qft" and n >= 12:
         assert deferred.info()[0] < plain.info()[0], (deferred.info(), plain.info())
+
+
+def _fold_circuit(n, seed):
+    """Random single-qubit unitaries on every qubit (low, middle, high, qubit
+    0) around runs of diagonal gates (CZ, controlled phases, diagonal
+    two-qubit matrices), with controlled gates and Paulis (not foldable) in
+    between."""
+    rng = np.random.default_rng(seed)
+    c = W.Circuit(n)
+    for layer in range(3 * n):
+        t = layer % n if layer < n else int(rng.integers(0, n))
+        c.ops.append(W.Op("matrix", (t,), matrix=W.haar_unitary(rng, 2)))
+        for _ in range(int(rng.integers(3, 7))):
+            qs = [int(v) for v in rng.permutation(n)[:2]]
+            if rng.random() < 0.5:
+                c.ops.append(W.Op("z", (qs[0],), controls=(qs[1],)))
+            else:
+                d = np.exp(1j * rng.uniform(0, 2 * np.pi, 4))
+                c.ops.append(W.Op("matrix", (qs[0], qs[1]), matrix=np.diag(d).astype(np.complex128)))
+        r = rng.random()
+        if r < 0.15:
+            qs = [int(v) for v in rng.permutation(n)[:2]]
+            c.ops.append(W.Op("matrix", (qs[0],), controls=(qs[1],), matrix=W.haar_unitary(rng, 2)))
+        elif r < 0.25:
+            c.ops.append(W.Op("x", (int(rng.integers(0, n)),)))
+    return c
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("n", [12, 13, 16, 20])
+@pytest.mark.parametrize("kind", ["qft", "random"])
+@pytest.mark.parametrize("fuse", [1, 5])
+def test_gate_fold(q, orc, name, n, kind, fuse):
+    """Plans apply a single-qubit gate next to a diagonal run in the run's
+    sweep (the run's window of varying bits placed over the target): results
+    match the oracle and the plan that keeps the gates separate."""
+    import os
+    circ = W.qft(n) if kind == "qft" else _fold_circuit(n, 70 + n)
+    rng = np.random.default_rng(n + 2)
+    psi = rand_state(n, rng, name)
+    ref = orc.run(circ, psi0=psi)
+    say("gate fold", name, n, kind, fuse)
+    d = to_gpu(psi, name)
+    folded = q.Plan(circ, _code(q, name), fuse)
+    folded.run(d)
+    os.environ["QSV_NO_GATE_FOLD"] = "1"
+    try:
+        plain = q.Plan(circ, _code(q, name), fuse)
+    finally:
+        del os.environ["QSV_NO_GATE_FOLD"]
+    d2 = to_gpu(psi, name)
+    plain.run(d2)
+    scale = max(1.0, float(np.max(np.abs(ref))))
+    assert np.max(np.abs(to_np(d) - ref)) <= TOL[name] * scale, np.max(np.abs(to_np(d) - ref))
+    assert np.max(np.abs(to_np(d2) - ref)) <= TOL[name] * scale
+    assert folded.info()[0] <= plain.info()[0]
+    if kind == "qft" and fuse == 1 and n >= 16:
+        assert folded.info()[0] < plain.info()[0], (folded.info(), plain.info())
