@@ -295,7 +295,8 @@ void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& up
 // the run kernel's varying bits: complex64 qubit 0 (the two amplitudes of a
 // 16-byte unit) or a qubit >= 9, complex128 a qubit >= 8, with the window of
 // four varying unit bits placed over it (states of >= 2^12 units).  The
-// window with the cheapest factor classes is taken.
+// window with the cheapest factor classes is taken, also for runs without a
+// gate.
 static bool plain_1q(const GateLaunch& L, int& t)
 {
     // no controls: the only inserted bit is the target's (none in complex64
@@ -370,6 +371,12 @@ void fold_gates_into_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& u
             break;
         }
     }
+    // runs without a gate take the window with the cheapest factor classes
+    for (GateLaunch& R : Ls)
+        if (R.type == L_DIAGRUN && !R.run_gate)
+            for (int w = 9; w + 4 <= nu; ++w)
+                if (run_cost(R, w, dt) < run_cost(R, R.run_w, dt))
+                    R.run_w = w;
 }
 
 // A SWAP moves the half of the state whose two bits differ; when the lower
