@@ -307,3 +307,53 @@ def test_gate_fold(q, orc, name, n, kind, fuse):
     assert folded.info()[0] <= plain.info()[0]
     if kind == "qft" and fuse == 1 and n >= 16:
         assert folded.info()[0] < plain.info()[0], (folded.info(), plain.info())
+
+
+def _swap_source(j, swaps):
+    """Input index that output index j reads after the swaps are applied in
+    order: the last swap acts first on the index."""
+    j = np.asarray(j, dtype=np.int64).copy()
+    for a, b in reversed(swaps):
+        ba, bb = (j >> a) & 1, (j >> b) & 1
+        j = j & ~((1 << a) | (1 << b)) | (ba << b) | (bb << a)
+    return j
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("kind", ["reverse", "random", "high"])
+def test_swap_runs_full_size(q, name, kind):
+    """n = 30: swap runs as qubit permutation passes on a state that holds
+    its own index (complex64: low 24 bits in the real part, the rest in the
+    imaginary part, both exact), checked on sampled outputs against the
+    index the swaps map them to; the random run needs two passes."""
+    import torch
+    n = 30
+    N = 1 << n
+    rng = np.random.default_rng(31)
+    if kind == "reverse":
+        swaps = [(b, n - 1 - b) for b in range(n // 2)]
+    elif kind == "random":
+        swaps = [tuple(int(v) for v in rng.permutation(n)[:2]) for _ in range(40)]
+    else:
+        swaps = [(n - 1, n - 7), (n - 2, n - 9), (n - 3, 12), (n - 4, 0)]
+    circ = W.Circuit(n, [W.Op("swap", s) for s in swaps])
+    say("swap runs n30", name, kind)
+    i = torch.arange(N, device="cuda", dtype=torch.int64)
+    if name == "c64":
+        d = torch.complex((i & 0xFFFFFF).to(torch.float32), (i >> 24).to(torch.float32))
+    else:
+        d = torch.complex(i.to(torch.float64), torch.zeros(N, device="cuda", dtype=torch.float64))
+    del i
+    plan = q.Plan(circ, _code(q, name), 1)
+    plan.run(d)
+    j = np.concatenate([rng.integers(0, N, 4096), [0, 1, N - 1, N // 2, 0x15555555, 0x2AAAAAAA]])
+    got = d[torch.from_numpy(j).cuda()].cpu().numpy()
+    if name == "c64":
+        idx = got.real.astype(np.int64) | (got.imag.astype(np.int64) << 24)
+    else:
+        idx = got.real.astype(np.int64)
+    want = _swap_source(j, swaps)
+    assert np.array_equal(idx, want), np.flatnonzero(idx != want)[:8]
+    assert plan.info()[0] <= 2
+    del d
+    torch.cuda.empty_cache()
