@@ -126,8 +126,11 @@ __device__ __forceinline__ void run_factor(const DiagRunK<R>& a, const R* sd, in
 //
 // A single-qubit gate whose target is a varying bit pairs amplitudes within
 // the thread, so the sweep can also apply a gate that directly precedes or
-// follows the run (GJ >= 0, the gate's varying bit): the thread loads its units, applies the gate
-// before or after the diagonal, and stores them, one sweep for both.
+// follows the run (0 <= GJ < NV, the gate's varying bit): the thread loads
+// its units, applies the gate before or after the diagonal, and stores them,
+// one sweep for both.  A gate on unit bit b < 6 (GJ = 8 + b) pairs each
+// element with the same element of the lane whose id differs in bit b (the
+// unit index's bits 0..5 are the lane id), exchanged with a lane shuffle.
 constexpr int kRunUPT = 16;
 
 template <typename R>
@@ -212,6 +215,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
             }
         }
         if constexpr (GJ >= 0) {
+            static_assert(GJ < NV || (GJ >= 8 && GJ < 14), "gate bit");
             // the planner folds a gate only where every unit of the window
             // exists (no tail), so pairs never mix loaded and missing units
             constexpr int NE = NT;
@@ -231,18 +235,34 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
                     ei[r] = x.y;
                 }
             }
-            // the gate on element pairs (e, e | 2^GJ)
             auto gate = [&]() {
+                if constexpr (GJ < NV) {
+                    // element pairs (e, e | 2^GJ) within the thread
 #pragma unroll
-                for (int e = 0; e < NE; ++e)
-                    if (!((e >> GJ) & 1)) {
-                        const int h = e | (1 << GJ);
-                        const R ar = er[e], ai = ei[e], br = er[h], bi = ei[h];
-                        er[e] = a.g[0] * ar - a.g[1] * ai + a.g[2] * br - a.g[3] * bi;
-                        ei[e] = a.g[0] * ai + a.g[1] * ar + a.g[2] * bi + a.g[3] * br;
-                        er[h] = a.g[4] * ar - a.g[5] * ai + a.g[6] * br - a.g[7] * bi;
-                        ei[h] = a.g[4] * ai + a.g[5] * ar + a.g[6] * bi + a.g[7] * br;
+                    for (int e = 0; e < NE; ++e)
+                        if (!((e >> GJ) & 1)) {
+                            const int h = e | (1 << GJ);
+                            const R ar = er[e], ai = ei[e], br = er[h], bi = ei[h];
+                            er[e] = a.g[0] * ar - a.g[1] * ai + a.g[2] * br - a.g[3] * bi;
+                            ei[e] = a.g[0] * ai + a.g[1] * ar + a.g[2] * bi + a.g[3] * br;
+                            er[h] = a.g[4] * ar - a.g[5] * ai + a.g[6] * br - a.g[7] * bi;
+                            ei[h] = a.g[4] * ai + a.g[5] * ar + a.g[6] * bi + a.g[7] * br;
+                        }
+                } else {
+                    // the same element of lane ^ 2^(GJ - 8): this lane's row of
+                    // the matrix (row 0 if its bit is 0) times (mine, other)
+                    constexpr int LM = 1 << (GJ - 8);
+                    const bool hi = (threadIdx.x & LM) != 0;
+                    const R mr0 = hi ? a.g[6] : a.g[0], mi0 = hi ? a.g[7] : a.g[1];
+                    const R or0 = hi ? a.g[4] : a.g[2], oi0 = hi ? a.g[5] : a.g[3];
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) {
+                        const R pr = __shfl_xor(er[e], LM), pi = __shfl_xor(ei[e], LM);
+                        const R xr = er[e], xi = ei[e];
+                        er[e] = mr0 * xr - mi0 * xi + or0 * pr - oi0 * pi;
+                        ei[e] = mr0 * xi + mi0 * xr + or0 * pi + oi0 * pr;
                     }
+                }
             };
             if (!a.gafter)
                 gate();
@@ -365,11 +385,14 @@ hipError_t diag_run_go(const GateLaunch& L, void* p, hipStream_t s)
     a.w = w;
     for (int j = 0; j < NV; ++j)
         a.vmask[j] = vmask[j];
-    int gjt = -1;  // the gate's varying bit
+    int gjt = -1;  // the gate's varying bit, or 8 + its unit bit below 6
     if (L.run_gate) {
         for (int j = 0; j < NV; ++j)
             if (vmask[j] == 1ull << L.run_gt)
                 gjt = j;
+        const int tb = L.run_gt - AS;  // the target's unit bit
+        if (gjt < 0 && tb >= 0 && tb < 6)
+            gjt = 8 + tb;
         if (gjt < 0)
             return hipErrorInvalidValue;
         a.gafter = L.run_gate == 2;
@@ -384,7 +407,14 @@ hipError_t diag_run_go(const GateLaunch& L, void* p, hipStream_t s)
     case 1: hipLaunchKernelGGL((k_diag_run<R, 1>), grid, block, 0, s, ps, a); break;
     case 2: hipLaunchKernelGGL((k_diag_run<R, 2>), grid, block, 0, s, ps, a); break;
     case 3: hipLaunchKernelGGL((k_diag_run<R, 3>), grid, block, 0, s, ps, a); break;
-    default: hipLaunchKernelGGL((k_diag_run<R, NV - 1>), grid, block, 0, s, ps, a); break;
+    case 4: hipLaunchKernelGGL((k_diag_run<R, NV - 1>), grid, block, 0, s, ps, a); break;
+    case 8: hipLaunchKernelGGL((k_diag_run<R, 8>), grid, block, 0, s, ps, a); break;
+    case 9: hipLaunchKernelGGL((k_diag_run<R, 9>), grid, block, 0, s, ps, a); break;
+    case 10: hipLaunchKernelGGL((k_diag_run<R, 10>), grid, block, 0, s, ps, a); break;
+    case 11: hipLaunchKernelGGL((k_diag_run<R, 11>), grid, block, 0, s, ps, a); break;
+    case 12: hipLaunchKernelGGL((k_diag_run<R, 12>), grid, block, 0, s, ps, a); break;
+    case 13: hipLaunchKernelGGL((k_diag_run<R, 13>), grid, block, 0, s, ps, a); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

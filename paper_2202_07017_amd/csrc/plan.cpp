@@ -291,12 +291,14 @@ void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& up
 }
 
 // A plain single-qubit gate (uncontrolled, bound matrix) directly before or
-// after a diagonal run joins the run's sweep when its target can be one of
-// the run kernel's varying bits: complex64 qubit 0 (the two amplitudes of a
-// 16-byte unit) or a qubit >= 9, complex128 a qubit >= 8, with the window of
-// four varying unit bits placed over it (states of >= 2^12 units).  The
-// window with the cheapest factor classes is taken, also for runs without a
-// gate.
+// after a diagonal run joins the run's sweep when the run kernel holds both
+// amplitudes of its pairs: complex64 qubit 0 (inside a 16-byte unit), a
+// target on unit bits 0..5 (across lanes: complex64 qubits 1..6, complex128
+// 0..5), or one on a unit bit >= 8 with the window of four varying unit bits
+// placed over it (complex64 qubits >= 9, complex128 >= 8); states of >= 2^12
+// units.  Targets on unit bits 6 and 7 (the waves of a block) stay separate.
+// The window with the cheapest factor classes is taken, also for runs
+// without a gate.
 static bool plain_1q(const GateLaunch& L, int& t)
 {
     // no controls: the only inserted bit is the target's (none in complex64
@@ -342,11 +344,12 @@ void fold_gates_into_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& u
             if (k >= Ls.size() || !plain_1q(Ls[k], t) || upload_off[k] >= 0)
                 continue;
             int wlo, whi;
-            if (dt == C64 && t == 0) {
+            const int tb = dt == C64 ? t - 1 : t;  // the target's unit bit (-1: inside a unit)
+            if (tb < 6) {
+                // inside a 16-byte unit or across lanes: any window
                 wlo = 8;
                 whi = nu - 4;
             } else {
-                const int tb = dt == C64 ? t - 1 : t;  // the target's unit bit
                 wlo = std::max(8, tb - 3);
                 whi = std::min(tb, nu - 4);
             }
