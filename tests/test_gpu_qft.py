@@ -357,3 +357,34 @@ def test_swap_runs_full_size(q, name, kind):
     assert plan.info()[0] <= 2
     del d
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("fuse", [1, 5])
+def test_plan_passes_graph_replay(q, orc, name, fuse):
+    """A plan with every plan pass (a QFT: deferred diagonal gates, diagonal
+    runs with gates in their sweeps, a qubit permutation pass) records a HIP
+    graph on its first run and replays it on later runs: three runs on one
+    state match the oracle's circuit applied three times, and a replay on a
+    copy of an earlier state matches the run that produced the next one."""
+    import torch
+    n = 16
+    circ = W.qft(n)
+    rng = np.random.default_rng(5)
+    psi = rand_state(n, rng, name)
+    ref = psi
+    for _ in range(3):
+        ref = orc.run(circ, psi0=ref)
+    say("plan passes replay", name, fuse)
+    plan = q.Plan(circ, _code(q, name), fuse)
+    d = to_gpu(psi, name)
+    plan.run(d)
+    first = d.clone()
+    plan.run(d)
+    second = d.clone()
+    plan.run(d)
+    assert np.max(np.abs(to_np(d) - ref)) <= 3 * TOL[name], np.max(np.abs(to_np(d) - ref))
+    again = first.clone()
+    plan.run(again)
+    torch.cuda.synchronize()
+    assert torch.equal(again, second), "replay differs from the recorded run"
