@@ -225,7 +225,7 @@ def main():
                     help="comma list of side legs to run alone (adjoint, adjoint26, batched, configs, expect, measure, circuits): profiling runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the path runs on a single MI355X and this build has no "
+        print("bench.py measures one GPU: the path runs on a single MI355X and the library has no "
               "multi-GPU mode (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
