@@ -75,7 +75,7 @@ struct DiagRunK {
     int tvb[kMaxRunFactors][5];
     const R* tab;                  // all tables, (re, im), state precision
     int ntab;                      // complex entries in tab
-    int w;                         // a thread's units differ in unit bits w..w+3 (w >= 8)
+    int w;                         // a thread's units differ in unit bits w..w+3 (w >= 6)
     uint64_t vmask[5];             // amplitude index bit of varying bit j
     int gafter;                    // the gate follows the diagonal (else it precedes it)
     R g[8];                        // its matrix, row-major (re, im); row 0 = target bit 0
@@ -110,9 +110,11 @@ __device__ __forceinline__ void run_factor(const DiagRunK<R>& a, const R* sd, in
     re = r;
 }
 
-// A block covers 256 consecutive units per load (coalesced); each thread
-// takes kRunUPT units that differ in the four unit bits w..w+3 (w >= 8,
-// chosen by the planner; w = 8: units 256 apart), so only NV index bits vary
+// Lanes cover unit bits 0..5, so every load of a wave is 64 consecutive
+// units (1 KiB); each thread takes kRunUPT units that differ in the four
+// unit bits w..w+3 (w >= 6, chosen by the planner), and the block's four
+// waves sit on unit bits 6, 7 (w >= 8; w = 8: units 256 apart) or just above
+// the window (w < 8).  So only NV index bits vary
 // over its amplitudes: those four and, in complex64, amplitude bit 0 (the
 // two amplitudes of a 16-byte unit).  The
 // thread builds the run's product for every value v of those bits, a table
@@ -151,11 +153,15 @@ __global__ void __launch_bounds__(kBlock) k_diag_run(R* __restrict__ psi, const 
     for (int k = threadIdx.x; k < 2 * a.ntab; k += kBlock)
         sd[k] = a.tab[k];
     __syncthreads();
-    const int wl = a.w - 8;  // segment bits below the window
+    // zeros inserted at k bit positions from p up
+    auto ins = [](uint64_t x, int p, int k) { return ((x >> p) << (p + k)) | (x & ((1ull << p) - 1)); };
+    const int wp = a.w >= 8 ? 6 : a.w + 4;  // unit bit of the wave index
     for (uint64_t seg = xcd_block(); seg < nseg; seg += gridDim.x) {
-        // unit of element r: u0 | r << w (unit bits 0..7: the thread; the
-        // segment fills the bits below and above the window)
-        const uint64_t u0 = ((seg >> wl) << (a.w + 4)) | ((seg & ((1ull << wl) - 1)) << 8) | threadIdx.x;
+        // unit of element r: u0 | r << w; the segment fills the unit bits
+        // that are neither lane, wave nor window bits
+        uint64_t x = seg << 6;
+        x = a.w >= 8 ? ins(ins(x, 6, 2), a.w, 4) : ins(x, a.w, 6);
+        const uint64_t u0 = x | ((uint64_t)(threadIdx.x >> 6) << wp) | (threadIdx.x & 63);
         const uint64_t i0 = u0 << AS;  // varying bits zero
         R tr[NT], ti[NT];
         tr[0] = (R)1;
@@ -324,8 +330,8 @@ hipError_t diag_run_go(const GateLaunch& L, void* p, hipStream_t s)
     // the window must lie inside the unit index, and a folded gate needs
     // every unit of it (no tail)
     const int w = L.run_w;
-    const uint64_t span = 1ull << (w + 4);
-    if (w < 8 || w > 58 || ((w > 8 || L.run_gate) && L.ngroups < span))
+    const uint64_t span = 1ull << (w >= 8 ? w + 4 : w + 6);  // units the thread and wave bits reach
+    if (w < 6 || w > 58 || ((w != 8 || L.run_gate) && L.ngroups < span))
         return hipErrorInvalidValue;
     // varying bits: (complex64) amplitude bit 0, then unit bits w..w+3
     uint64_t vmask[NV];

@@ -294,9 +294,9 @@ void merge_diagonal_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& up
 // after a diagonal run joins the run's sweep when the run kernel holds both
 // amplitudes of its pairs: complex64 qubit 0 (inside a 16-byte unit), a
 // target on unit bits 0..5 (across lanes: complex64 qubits 1..6, complex128
-// 0..5), or one on a unit bit >= 8 with the window of four varying unit bits
-// placed over it (complex64 qubits >= 9, complex128 >= 8); states of >= 2^12
-// units.  Targets on unit bits 6 and 7 (the waves of a block) stay separate.
+// 0..5), or one on a unit bit >= 6 with the window of four varying unit bits
+// placed over it (complex64 qubits >= 7, complex128 >= 6; a window below
+// unit bit 8 moves the block's wave bits above it); states of >= 2^12 units.
 // The window with the cheapest factor classes is taken, also for runs
 // without a gate.
 static bool plain_1q(const GateLaunch& L, int& t)
@@ -350,15 +350,18 @@ void fold_gates_into_runs(std::vector<GateLaunch>& Ls, std::vector<long long>& u
                 wlo = 8;
                 whi = nu - 4;
             } else {
-                wlo = std::max(8, tb - 3);
+                wlo = std::max(6, tb - 3);
                 whi = std::min(tb, nu - 4);
             }
-            if (wlo > whi)
-                continue;
-            int best = wlo;
-            for (int w = wlo + 1; w <= whi; ++w)
-                if (run_cost(Ls[j], w, dt) < run_cost(Ls[j], best, dt))
+            int best = -1;
+            for (int w = wlo; w <= whi; ++w) {
+                if (w < 8 && w + 6 > nu)
+                    continue;  // below 8 the waves sit above the window
+                if (best < 0 || run_cost(Ls[j], w, dt) < run_cost(Ls[j], best, dt))
                     best = w;
+            }
+            if (best < 0)
+                continue;
             GateLaunch& R = Ls[j];
             R.run_w = best;
             R.run_gate = side == 0 ? 1 : 2;
