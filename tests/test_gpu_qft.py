@@ -388,3 +388,45 @@ def test_plan_passes_graph_replay(q, orc, name, fuse):
     plan.run(again)
     torch.cuda.synchronize()
     assert torch.equal(again, second), "replay differs from the recorded run"
+
+
+@pytest.fixture(scope="module")
+def qft26_reference(orc):
+    """n = 26: the oracle's seeded random state and its QFT at sampled
+    outputs y from the transform's definition, psi_out[y] = 2^(-n/2)
+    sum_x psi_in[x] exp(+2 pi i x y / 2^n), with exact integer phases; x is
+    split into 13-bit halves, so each output is a matrix-vector product."""
+    n, seed = 26, 2602
+    N, H = 1 << n, 1 << 13
+    psi = orc.random_state(n, seed)
+    M = psi.reshape(H, H)  # M[xh, xl] = psi[xh * 2^13 + xl]
+    rng = np.random.default_rng(26)
+    ys = np.concatenate([rng.integers(0, N, 6), [0, N - 1]]).astype(np.int64)
+    h = np.arange(H, dtype=np.int64)
+    want = np.empty(len(ys), dtype=np.complex128)
+    for k, y in enumerate(ys):
+        vl = np.exp(2j * np.pi * ((h * y) % N) / N)
+        vh = np.exp(2j * np.pi * (((h << 13) * y) % N) / N)
+        want[k] = np.dot(vh, M @ vl) / np.sqrt(N)
+    return n, seed, ys, want
+
+
+@pytest.mark.parametrize("name", DTYPES)
+def test_qft_random_state_vs_dft(q, qft26_reference, name):
+    """n = 26, a seeded random input (the device generator, equal to the
+    oracle's): the QFT fused to k = 5 and unfused (every plan pass: deferred
+    diagonal gates, runs with gates in their sweeps on window, lane and moved
+    wave bits, the permutation pass) against the transform's definition at
+    sampled outputs."""
+    import torch
+    n, seed, ys, want = qft26_reference
+    for fuse in (1, 5):
+        say("qft random n26", name, fuse)
+        d = torch.empty(1 << n, dtype=torch_dtype(name), device="cuda")
+        q.qsv_init_random(d, seed)
+        q.Plan(W.qft(n), _code(q, name), fuse).run(d)
+        got = d[torch.from_numpy(ys).cuda()].cpu().numpy().astype(np.complex128)
+        err = np.max(np.abs(got - want))
+        assert err <= TOL[name] * 1e-2, (fuse, err, np.max(np.abs(want)))
+        del d
+    torch.cuda.empty_cache()
