@@ -184,6 +184,33 @@ def profile_kernels():
     print("profile run done: 2 x 4 GiB copy, 10 x single-qubit sweep n=30 c64 t=15", flush=True)
 
 
+def profile_circuits():
+    """Short run for rocprofv3 counter passes over the plan kernels: a 4 GiB
+    torch copy (calibration) twice, then the QFT at n = 30 complex64 fused to
+    k = 5 (matrix-core blocks, diagonal runs, the qubit permutation pass) and
+    unfused (runs with gates in their sweeps), twice each."""
+    import torch
+
+    import workloads as W
+    from paper_2202_07017_amd import qsv
+    dev = torch.device("cuda:0")
+    src = torch.empty(1 << 29, dtype=torch.float64, device=dev)
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    del src, dst
+    n = 30
+    psi = torch.empty(1 << n, dtype=torch.complex64, device=dev)
+    qsv.qsv_init_random(psi, 5)
+    for fuse in (5, 1):
+        plan = qsv.Plan(W.qft(n), qsv.C64, fuse)
+        for _ in range(2):
+            plan.run(psi)
+    torch.cuda.synchronize()
+    print("profile run done: 2 x 4 GiB copy, QFT n=30 c64 fused k=5 and unfused, 2 runs each", flush=True)
+
+
 def profile_mfma():
     """Short run for the matrix-core counters: fused dense blocks of k = 4 and
     k = 5 qubits (Haar unitaries) on a 30-qubit state, complex64 then
@@ -219,6 +246,8 @@ def main():
     ap.add_argument("--skip-side", action="store_true", help="only the timed step")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only the dominant kernel and a copy of known size (counter runs)")
+    ap.add_argument("--profile-circuits", action="store_true",
+                    help="short run for counter passes over the plan kernels (QFT n=30 c64)")
     ap.add_argument("--profile-mfma", action="store_true",
                     help="only fused k = 4, 5 blocks (matrix-core counter runs)")
     ap.add_argument("--legs", default="",
@@ -231,6 +260,9 @@ def main():
 
     if args.profile_kernels:
         profile_kernels()
+        return
+    if args.profile_circuits:
+        profile_circuits()
         return
     if args.profile_mfma:
         profile_mfma()
